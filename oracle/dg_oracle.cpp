@@ -81,17 +81,19 @@ template <class T> inline T dmax(T a, T b) { return (b > a) ? b : a; }
 template <class T> inline bool finite(T a) { return std::isfinite(val(a)); }
 
 // ------------------------------------------------------------------- mesh --
-// A face f joins cells L and R; its unit normal n points from L to R.  Face
-// and Gauss-point coordinates are given in L's frame; the image of R next to
-// L sits at c_R + shift (periodic wrap).
+// A face f joins cells L and R; its unit normal n points from L to R.
+// Positions are offsets in the local frame of L's centroid (Sec. 2.2 writes the
+// expansion in coordinates with origin at the centroid): rc is the face
+// centroid, rg the Gauss points, and dLR the centroid of R's periodic image
+// next to L.  Offsets from R's centroid are these minus dLR.
 struct FaceGeo {
   int64_t L, R;
   double n[3];
   double A;
-  double xc[3];
-  double shift[3];
+  double rc[3];
+  double dLR[3];
   int ng;
-  double xg[4][3];
+  double rg[4][3];
   double wg[4];
 };
 
@@ -173,27 +175,24 @@ struct Mesh {
       a[d] += 1;
       g.L = e;
       g.R = cidx(a[0], a[1], a[2]);
-      double c[3] = {lo[0] + (i + 0.5) * h[0], lo[1] + (j + 0.5) * h[1],
-                     lo[2] + (k + 0.5) * h[2]};
       double A = 1.0;
       for (int q = 0; q < dim; ++q)
         if (q != d) A *= h[q];
       g.A = A;
+      // The face sits half a cell from L's centroid along d; R's centroid (or
+      // its periodic image) one cell away.
       for (int q = 0; q < 3; ++q) {
         g.n[q] = (q == d) ? 1.0 : 0.0;
-        g.xc[q] = c[q] + ((q == d) ? 0.5 * h[q] : 0.0);
-        g.shift[q] = 0.0;
+        g.rc[q] = (q == d) ? 0.5 * h[q] : 0.0;
+        g.dLR[q] = (q == d) ? h[q] : 0.0;
       }
-      // R's image next to L: shift by one box length when the neighbour
-      // index wrapped.
-      if (a[d] >= N[d]) g.shift[d] = N[d] * h[d];
       const double s = 1.0 / std::sqrt(3.0);
       if (dim == 2) {
         int t = 1 - d;  // the tangential axis
         g.ng = 2;
         for (int p = 0; p < 2; ++p) {
-          for (int q = 0; q < 3; ++q) g.xg[p][q] = g.xc[q];
-          g.xg[p][t] += (p == 0 ? -1.0 : 1.0) * 0.5 * h[t] * s;
+          for (int q = 0; q < 3; ++q) g.rg[p][q] = g.rc[q];
+          g.rg[p][t] += (p == 0 ? -1.0 : 1.0) * 0.5 * h[t] * s;
           g.wg[p] = 0.5 * A;
         }
       } else {
@@ -203,9 +202,9 @@ struct Mesh {
         int p = 0;
         for (int s1 = -1; s1 <= 1; s1 += 2)
           for (int s2 = -1; s2 <= 1; s2 += 2) {
-            for (int q = 0; q < 3; ++q) g.xg[p][q] = g.xc[q];
-            g.xg[p][t1] += s1 * 0.5 * h[t1] * s;
-            g.xg[p][t2] += s2 * 0.5 * h[t2] * s;
+            for (int q = 0; q < 3; ++q) g.rg[p][q] = g.rc[q];
+            g.rg[p][t1] += s1 * 0.5 * h[t1] * s;
+            g.rg[p][t2] += s2 * 0.5 * h[t2] * s;
             g.wg[p] = 0.25 * A;
             ++p;
           }
@@ -219,17 +218,17 @@ struct Mesh {
     g.A = fA[f];
     for (int q = 0; q < 3; ++q) {
       g.n[q] = q < 2 ? fn[2 * f + q] : 0.0;
-      g.xc[q] = q < 2 ? fx[2 * f + q] : 0.0;
-      g.shift[q] = q < 2 ? fsh[2 * f + q] : 0.0;
+      g.rc[q] = q < 2 ? fx[2 * f + q] - cc[2 * g.L + q] : 0.0;
+      g.dLR[q] = q < 2 ? cc[2 * g.R + q] + fsh[2 * f + q] - cc[2 * g.L + q] : 0.0;
     }
     double t[2] = {-g.n[1], g.n[0]};
     double o = g.A / (2.0 * std::sqrt(3.0));
     g.ng = 2;
     for (int p = 0; p < 2; ++p) {
       double sg = p == 0 ? -1.0 : 1.0;
-      g.xg[p][0] = g.xc[0] + sg * o * t[0];
-      g.xg[p][1] = g.xc[1] + sg * o * t[1];
-      g.xg[p][2] = 0.0;
+      g.rg[p][0] = g.rc[0] + sg * o * t[0];
+      g.rg[p][1] = g.rc[1] + sg * o * t[1];
+      g.rg[p][2] = 0.0;
       g.wg[p] = 0.5 * g.A;
     }
   }
@@ -703,14 +702,11 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e) {
     Poly<T> qL, qR;
     load_poly(P, U, nc, fg.L, qL);
     load_poly(P, U, nc, fg.R, qR);
-    CellGeo gL, gR;
-    M.cell(fg.L, gL);
-    M.cell(fg.R, gR);
     for (int p = 0; p < fg.ng; ++p) {
       double rL[3], rR[3];
       for (int d = 0; d < 3; ++d) {
-        rL[d] = fg.xg[p][d] - gL.c[d];
-        rR[d] = fg.xg[p][d] - gR.c[d] - fg.shift[d];
+        rL[d] = fg.rg[p][d];
+        rR[d] = fg.rg[p][d] - fg.dLR[d];
         if (d >= dim) rL[d] = rR[d] = 0.0;
       }
       T uL[8], uR[8], F[8];
@@ -827,8 +823,8 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
       phimin[k] = dmin(phimin[k], qn.m[k]);
     }
     for (int d = 0; d < 3; ++d) {
-      double off = sides[m] == 0 ? 0.0 : fg.shift[d];
-      rf[m][d] = d < dim ? fg.xc[d] - off - cg.c[d] : 0.0;
+      double off = sides[m] == 0 ? 0.0 : fg.dLR[d];
+      rf[m][d] = d < dim ? fg.rc[d] - off : 0.0;
     }
   }
   auto alpha_of = [&](int k, const T* grad) {
@@ -1148,14 +1144,11 @@ void or_divB(void* h, const double* U, double* divB) {
       Poly<double> qL, qR;
       load_poly(P, U, nc, fg.L, qL);
       load_poly(P, U, nc, fg.R, qR);
-      CellGeo gL, gR;
-      M.cell(fg.L, gL);
-      M.cell(fg.R, gR);
       for (int p = 0; p < fg.ng; ++p) {
         double rL[3], rR[3], uL[8], uR[8];
         for (int d = 0; d < 3; ++d) {
-          rL[d] = fg.xg[p][d] - gL.c[d];
-          rR[d] = fg.xg[p][d] - gR.c[d] - fg.shift[d];
+          rL[d] = fg.rg[p][d];
+          rR[d] = fg.rg[p][d] - fg.dLR[d];
         }
         eval_poly(P, qL, rL, uL);
         eval_poly(P, qR, rR, uR);
