@@ -1,0 +1,163 @@
+/*
+ * dg.h - C ABI of the MI355X (gfx950) library for the second-order
+ * centroidal-Taylor discontinuous Galerkin scheme of Mocz et al. (2013),
+ * "A discontinuous Galerkin method for solving the fluid and MHD equations in
+ * astrophysical simulations".
+ *
+ * The library computes, on the GPU, the per-stage DG right-hand side of the
+ * weak form (Sec. 2.2, eqn:dg, eqn:fv, eqn:dgderiv, eqn:fv3d, eqn:dgderiv3d,
+ * eqn:GalerkUpdate): P1 Taylor coefficients evaluated at face Gauss points,
+ * the face Riemann problem (HLL for Euler, HLLD for ideal MHD; Sec. 2.3),
+ * surface-flux accumulation, volume quadrature of F . grad(basis), the inverse
+ * mass matrices, the slope limiter of Sec. 2.5, and SSP-RK2 stages.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout.  Coefficient-major structure of arrays: element
+ *   U[k * ncells + cell]
+ * Hydro variable v (rho, rho v_x, rho v_y[, rho v_z], E) owns coefficients
+ * k = v*(1+dim) + c, c = 0 the cell mean, c = 1..dim the gradient along x, y(,
+ * z) about the cell centroid (the Taylor basis of Sec. 2.2).  Ideal MHD (3D)
+ * appends the three B means and the coefficients a4..a11 of the locally
+ * divergence-free functions V4..V11 of Sec. 2.2 (31 arrays in all).
+ * Cartesian cells are numbered x fastest: cell = (k*ny + j)*nx + i.
+ * Element type is double (DG_FP64) or float (DG_FP32), per dg_config.
+ *
+ * Ownership.  State, derivative and adjoint buffers are DEVICE pointers owned
+ * by the caller (at least 16-byte aligned, contiguous, dg_state_len elements).
+ * The library owns the mesh handle, its device geometry and its workspace
+ * (allocated in dg_mesh_create, freed in dg_mesh_destroy).  Host arrays passed
+ * in a descriptor are copied during dg_mesh_create and not retained.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every compute
+ * call only enqueues work and returns without synchronising.
+ *
+ * Errors.  Functions return dg_status; nothing is thrown across the ABI.  On a
+ * non-OK status, dg_last_error() returns a thread-local message.  Device-side
+ * detection of a non-physical state (rho <= 0, p <= 0 or a non-finite value at
+ * any quadrature point) is latched in a per-mesh status word and reported (and
+ * cleared) by dg_check().  A handle must not be used from two host threads at
+ * once.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_mesh* dg_mesh_t;
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = 1,        /* invalid argument, descriptor or size */
+  DG_ENOMEM = 2,        /* device or host allocation failed */
+  DG_EHIP = 3,          /* a HIP runtime call failed (message in dg_last_error) */
+  DG_EUNSUPPORTED = 4,  /* valid but not built: e.g. MHD on a face-list mesh */
+  DG_ENONPHYSICAL = 5   /* latched non-physical state (dg_check only) */
+} dg_status;
+
+typedef enum { DG_EULER = 0, DG_MHD = 1 } dg_physics;
+typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
+typedef enum { DG_FLUX_HLL = 0, DG_FLUX_HLLD = 1 } dg_flux;
+typedef enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1 } dg_limiter;
+
+/* Physics and numerics of a mesh.  Euler needs DG_FLUX_HLL; MHD needs
+ * DG_FLUX_HLLD and a 3D Cartesian mesh.  gamma is the adiabatic index of
+ * p_gas = (gamma - 1) rho u (Sec. 2.1). */
+typedef struct {
+  int physics;    /* dg_physics */
+  int precision;  /* dg_precision */
+  int flux;       /* dg_flux */
+  int limiter;    /* dg_limiter: the slope limiter of Sec. 2.5 */
+  double gamma;
+} dg_config;
+
+/* Mesh descriptor.
+ * kind 0: periodic Cartesian box [lo, hi] of n[0] x n[1] (x n[2]) cells.
+ * kind 1: periodic 2D face list (e.g. a static Voronoi mesh built on the
+ *   host).  All arrays are HOST arrays, copied at create:
+ *   cell_volume[ncells], cell_centroid[ncells][2],
+ *   cell_moments[ncells][3] = (Mxx, Mxy, Myy), the second moments about the
+ *     centroid (the mass matrix of Sec. 2.2),
+ *   face_cells[nfaces][2] = (L, R) with the unit normal pointing from L to R,
+ *   face_area[nfaces] (edge length), face_normal[nfaces][2],
+ *   face_centroid[nfaces][2] (edge midpoint, in L's periodic frame),
+ *   face_shift[nfaces][2] in {-1, 0, 1}: R's image next to L sits at
+ *     centroid[R] + shift * box.
+ *   Every cell must be closed: sum over its faces of A n = 0 (checked). */
+typedef struct {
+  int dim;
+  int kind;
+  int64_t n[3];
+  double lo[3], hi[3];
+  int64_t ncells, nfaces;
+  double box[2];
+  const double* cell_volume;
+  const double* cell_centroid;
+  const double* cell_moments;
+  const int32_t* face_cells;
+  const double* face_area;
+  const double* face_normal;
+  const double* face_centroid;
+  const int8_t* face_shift;
+} dg_mesh_desc;
+
+/* Create a mesh handle: validates the descriptor and configuration, uploads
+ * the geometry and allocates the workspace.  On failure *out is NULL. */
+dg_status dg_mesh_create(const dg_mesh_desc* desc, const dg_config* cfg, dg_mesh_t* out);
+
+/* Release the handle and its device memory (synchronises the device).
+ * NULL is ignored. */
+void dg_mesh_destroy(dg_mesh_t mesh);
+
+/* Number of state elements (ncoef * ncells), or -1 for a NULL handle. */
+int64_t dg_state_len(dg_mesh_t mesh);
+
+/* Number of coefficient arrays per cell (12 for 2D Euler, 31 for 3D MHD). */
+int dg_ncoef(dg_mesh_t mesh);
+
+/* dUdt = L(U): the semi-discrete DG right-hand side (Sec. 2.2) without the
+ * limiter: face Gauss-point states, Riemann fluxes, surface and volume
+ * terms, inverse mass matrices.  U and dUdt must not alias. */
+dg_status dg_rhs(dg_mesh_t mesh, const void* U, void* dUdt, void* stream);
+
+/* U_lim = Pi(U): the slope limiter of Sec. 2.5, alpha = min(1, min_j psi_ij)
+ * per conserved variable from the means of the cell and its face neighbours
+ * and the linear extrapolation to each face centroid; means are unchanged;
+ * the three B components share one alpha.  U and U_lim must not alias. */
+dg_status dg_limit(dg_mesh_t mesh, const void* U, void* U_lim, void* stream);
+
+/* One SSP-RK2 step of size dt with the limiter (if configured) at the start of
+ * each stage:
+ *   Ua = Pi(U); V1 = Ua + dt L(Ua); Ub = Pi(V1); U_next = Ua/2 + (Ub + dt L(Ub))/2.
+ * U_next is stored unlimited; the next step limits it first.  U_next may
+ * equal U (the library then stages the result in its workspace and copies it
+ * back: one extra state copy). */
+dg_status dg_step(dg_mesh_t mesh, const void* U, void* U_next, double dt, void* stream);
+
+/* Same as dg_step with the step size read from device memory (*dt_dev, a
+ * double), so a step can follow dg_cfl_dt without a host synchronisation. */
+dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,
+                        void* stream);
+
+/* *dt_dev = cfl * min_e 2 V_e / sum_{f of e} A_f (|v_e . n_f| + c_e(n_f)) from
+ * the cell means of U (c the sound speed, or the fast magnetosonic speed along
+ * n_f for MHD).  dt_dev is a device pointer to one double. */
+dg_status dg_cfl_dt(dg_mesh_t mesh, const void* U, double cfl, double* dt_dev, void* stream);
+
+/* Synchronise the device, then return DG_ENONPHYSICAL if any kernel of this
+ * mesh met a non-physical state since the last call (and clear the flag),
+ * else DG_OK (or DG_EHIP if synchronisation failed). */
+dg_status dg_check(dg_mesh_t mesh);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

@@ -1,0 +1,93 @@
+// Internal declarations shared by the host side of the library and its kernel
+// launchers.  Not part of the public ABI (that is include/dg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "dg.h"
+
+namespace dg {
+
+// Kernel modes of a fused stage.
+enum StageMode : int {
+  kRhs = 0,     // out = L(in)
+  kStage1 = 1,  // out = Pi(in) + dt L(Pi(in))
+  kStage2 = 2,  // out = Pi(u0)/2 + (Pi(in) + dt L(Pi(in)))/2
+  kLimit = 3    // out = Pi(in)
+};
+
+// Geometry and launch shape of a periodic 2D Cartesian mesh.
+struct Cart2D {
+  int nx, ny;
+  double hx, hy;
+  int rows_per_tile;  // rows marched by one wave
+  int tiles_x, tiles_y;
+};
+
+struct Cart3D {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  int planes_per_tile;  // z-planes marched by one wave
+  int tiles_x, tiles_y, tiles_z;
+};
+
+// Device geometry of a 2D face-list mesh (see facelist2d.hip).
+struct FaceList2D {
+  int64_t ncells, nfaces;
+  int nblocks;              // cell blocks
+  int block_cells;          // cells per block (max)
+  // per block: cell range [cell_ptr[b], cell_ptr[b+1]) and face range
+  int* block_cell_ptr;
+  int* block_face_ptr;
+  // per block-local face slot: face data (blocked order)
+  int* bf_cells;            // [2 * nbf]  global L, R
+  double* bf_geo;           // [8 * nbf]  nx, ny, A, gx0, gy0 (offset of Gauss pt 0 from L centroid), rx, ry (L->R centroid image offset), pad
+  // per cell (cells in block order = original order after host renumbering)
+  int* cell_face_ptr;       // CSR into cell_faces (block-local face slots, signed: +1 L, -1 R)
+  int* cell_faces;
+  double* cell_geo;         // [12 * ncells]: V, Minv(3), quad axes (4), ...
+  int64_t nbf;
+};
+
+template <typename T>
+struct Workspace {
+  T* v1 = nullptr;       // stage-1 output
+  T* tmp = nullptr;      // staging for in-place steps
+};
+
+}  // namespace dg
+
+struct dg_mesh {
+  dg_config cfg;
+  int dim = 2;
+  int kind = 0;
+  int ncoef = 0;
+  int64_t ncells = 0;
+  dg::Cart2D c2{};
+  dg::Cart3D c3{};
+  dg::FaceList2D fl{};
+  size_t elem = 8;            // sizeof(element)
+  void* v1 = nullptr;         // workspace: stage-1 output
+  void* tmp = nullptr;        // workspace: staging for in-place steps (lazy)
+  int* status = nullptr;      // device status word
+  double* dtpart = nullptr;   // per-wave partial minima for dg_cfl_dt
+  int ndtpart = 0;
+  int device = 0;
+};
+
+namespace dg {
+
+void set_error(const std::string& msg);
+dg_status hip_fail(hipError_t e, const char* what);
+
+// Launchers (return hipSuccess or the launch error).
+// Step size: *dt_dev when dt_dev is not NULL, else dt_host.
+hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
+                         const double* dt_dev, double dt_host, hipStream_t s);
+hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                             hipStream_t s);
+
+}  // namespace dg

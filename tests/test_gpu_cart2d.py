@@ -1,0 +1,219 @@
+"""GPU parity of the 2D Euler Cartesian path against the CPU oracle (through the C ABI).
+
+Tolerances: single calls agree to 1e-12 of the field scale (different rounding
+order only); 100-step runs to 1e-11 relative per field, with the per-field error
+err_k = max_e max(|d mean_k|, h |d grad_k|_inf) / max_e |mean_k|.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G14 = 1.4
+G53 = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(n, lo, hi, gamma, limiter=True, precision="fp64"):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    return Solver(cartesian(n, lo, hi), precision=precision, limiter=limiter, gamma=gamma)
+
+
+def field_errors(A, B, n, lo, hi, nvar=4):
+    """Per-field relative error of A against the reference B (means and h-scaled
+    gradients, normalised by the largest mean of the field)."""
+    dim = len(n)
+    h = min((hi[d] - lo[d]) / n[d] for d in range(dim))
+    A = A.reshape(nvar * (1 + dim), -1)
+    B = B.reshape(nvar * (1 + dim), -1)
+    errs = []
+    for v in range(nvar):
+        k = v * (1 + dim)
+        scale = max(np.abs(B[k]).max(), 1e-300)
+        d = np.abs(A[k] - B[k]).max()
+        for c in range(1, 1 + dim):
+            d = max(d, h * np.abs(A[k + c] - B[k + c]).max())
+        errs.append(d / scale)
+    return np.array(errs)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+SHAPES = [(100, 70), (61, 9), (1, 5), (3, 1), (130, 4), (64, 64)]
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_rhs_matches_oracle(oracle, torch_cuda, n):
+    lo, hi = (0.0, -0.5), (1.3, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G14, seed=hash(n) % 1000, amp=0.25)
+    s = _solver(n, lo, hi, G14, limiter=False)
+    got = s.rhs(s.to_device(U0)).cpu().numpy()
+    s.check()
+    ref = oracle.rhs(oracle.Mesh.cartesian(n, lo, hi), U0, G14)
+    # The gradient equations subtract O(|F|) surface and volume sums that are
+    # then scaled by 12/(V h^2): compare gradients in the h-scaled norm.
+    errs = field_errors(got, ref, n, lo, hi)
+    assert errs.max() < 1e-12, (n, errs)
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_limit_matches_oracle(oracle, torch_cuda, n):
+    lo, hi = (0.0, 0.0), (1.0, 2.0)
+    U0 = W.random_p1_state(n, lo, hi, G14, seed=3, amp=0.3).reshape(12, -1)
+    U0[1::3] *= 4.0  # steep gradients so the limiter is active
+    U0[2::3] *= -3.0
+    U0 = U0.reshape(-1)
+    s = _solver(n, lo, hi, G14)
+    got = s.limit(s.to_device(U0)).cpu().numpy()
+    ref = oracle.limit(oracle.Mesh.cartesian(n, lo, hi), U0)
+    assert _rel(got, ref) < 1e-13
+    assert np.array_equal(got.reshape(12, -1)[0::3], U0.reshape(12, -1)[0::3])
+
+
+@pytest.mark.parametrize("limiter", [False, True])
+@pytest.mark.parametrize("n", [(100, 70), (61, 9), (2, 3)])
+def test_step_matches_oracle(oracle, torch_cuda, n, limiter):
+    lo, hi = (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=5, amp=0.3)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    dt = oracle.cfl_dt(om, U0, G53, 0.3)
+    ref = oracle.step(om, U0, dt, G53, limiter)
+    s = _solver(n, lo, hi, G53, limiter=limiter)
+    got = s.step(s.to_device(U0), dt).cpu().numpy()
+    s.check()
+    assert field_errors(got, ref, n, lo, hi).max() < 1e-13
+
+
+def test_step_is_composition_of_limit_and_rhs(torch_cuda):
+    """dg_step equals Ua = Pi(U); V1 = Ua + dt L(Ua); Ub = Pi(V1);
+    U' = Ua/2 + (Ub + dt L(Ub))/2 built from dg_limit and dg_rhs."""
+    n, lo, hi = (90, 33), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=8, amp=0.3)
+    s = _solver(n, lo, hi, G53, limiter=True)
+    s_nolim = _solver(n, lo, hi, G53, limiter=False)
+    U = s.to_device(U0)
+    dt = 1e-3
+    Ua = s.limit(U)
+    V1 = Ua + dt * s_nolim.rhs(Ua)
+    Ub = s.limit(V1)
+    comp = 0.5 * Ua + 0.5 * (Ub + dt * s_nolim.rhs(Ub))
+    got = s.step(U, dt)
+    assert _rel(got.cpu().numpy(), comp.cpu().numpy()) < 1e-14
+
+
+def test_c1_vortex_100_steps(oracle, torch_cuda):
+    """The 64x64 isentropic vortex (gamma 1.4, no limiter), 100 steps on the
+    oracle's CFL-0.3 dt schedule: 1e-11 relative per field."""
+    n, lo, hi = (64, 64), (0.0, 0.0), (10.0, 10.0)
+    U0 = W.c1_state(64)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    ref, dts = oracle.run(om, U0, 100, G14, 0.3, False)
+    s = _solver(n, lo, hi, G14, limiter=False)
+    U = s.to_device(U0)
+    V = s.empty()
+    for dt in dts:
+        s.step(U, dt, out=V)
+        U, V = V, U
+    s.check()
+    errs = field_errors(U.cpu().numpy(), ref, n, lo, hi)
+    print("C1 FP64 per-field error after 100 steps:", errs)
+    assert errs.max() < 1e-11
+
+
+def test_c2_shear_100_steps_small(oracle, torch_cuda):
+    """The shear-layer recipe (gamma 5/3, limiter on) at 128x128, 100 steps on
+    the oracle's dt schedule."""
+    n, lo, hi = (128, 128), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.c2_state(128)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    ref, dts = oracle.run(om, U0, 100, G53, 0.3, True)
+    s = _solver(n, lo, hi, G53, limiter=True)
+    U = s.to_device(U0)
+    V = s.empty()
+    for dt in dts:
+        s.step(U, dt, out=V)
+        U, V = V, U
+    s.check()
+    errs = field_errors(U.cpu().numpy(), ref, n, lo, hi)
+    print("C2(128^2) FP64 per-field error after 100 steps:", errs)
+    assert errs.max() < 1e-11
+    # FP32 run on the same schedule: error stated per field
+    s32 = _solver(n, lo, hi, G53, limiter=True, precision="fp32")
+    U = s32.to_device(U0)
+    V = s32.empty()
+    for dt in dts:
+        s32.step(U, dt, out=V)
+        U, V = V, U
+    s32.check()
+    e32 = field_errors(U.double().cpu().numpy(), ref, n, lo, hi)
+    print("C2(128^2) FP32 per-field error after 100 steps:", e32)
+    assert e32.max() < 1e-3
+
+
+def test_in_place_step_and_determinism(torch_cuda):
+    n, lo, hi = (200, 37), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=9, amp=0.3)
+    s = _solver(n, lo, hi, G53)
+    a = s.to_device(U0)
+    b = s.step(a.clone(), 1e-3)
+    c = s.step(a.clone(), 1e-3)
+    assert torch_cuda.equal(b, c)
+    s.step(a, 1e-3, out=a)
+    assert torch_cuda.equal(a, b)
+
+
+def test_cfl_dt_matches_oracle(oracle, torch_cuda):
+    n, lo, hi = (77, 50), (0.0, 0.0), (2.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G14, seed=10, amp=0.3)
+    s = _solver(n, lo, hi, G14)
+    dt = s.cfl_dt(s.to_device(U0), 0.3).item()
+    ref = oracle.cfl_dt(oracle.Mesh.cartesian(n, lo, hi), U0, G14, 0.3)
+    assert abs(dt - ref) <= 1e-14 * ref
+
+
+def test_device_dt_step(oracle, torch_cuda):
+    n, lo, hi = (64, 64), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=12, amp=0.2)
+    s = _solver(n, lo, hi, G53)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    a = s.step(U, dt)
+    b = s.step(U, dt.item())
+    assert torch_cuda.equal(a, b)
+
+
+def test_nonphysical_state_is_reported(torch_cuda):
+    from paper_1305_5536_amd.capi import NonPhysicalState
+    n, lo, hi = (16, 16), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G14, seed=1, amp=0.1).reshape(12, -1)
+    U0[0, 37] = -1.0  # negative density in one cell
+    s = _solver(n, lo, hi, G14, limiter=False)
+    s.rhs(s.to_device(U0.reshape(-1)))
+    with pytest.raises(NonPhysicalState):
+        s.check()
+    s.check()  # the flag was cleared
+
+
+def test_bad_arguments_are_rejected(torch_cuda):
+    from paper_1305_5536_amd.capi import DGError
+    s = _solver((8, 8), (0, 0), (1, 1), G14)
+    with pytest.raises(ValueError):
+        s.rhs(torch_cuda.zeros(10, dtype=torch_cuda.float64, device="cuda"))
+    U = torch_cuda.ones(s.state_len, dtype=torch_cuda.float64, device="cuda")
+    import ctypes
+    from paper_1305_5536_amd import capi as C
+    st = C.lib().dg_rhs(s._h, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(U.data_ptr()), None)
+    assert st == C.DG_EINVAL
+    with pytest.raises(DGError):
+        C.check(st, "dg_rhs")
