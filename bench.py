@@ -1,0 +1,155 @@
+"""Throughput of the DG hot path on one MI355X.
+
+Workload (default): the 2D Euler shear layer on a periodic 2048 x 2048 Cartesian
+mesh of [0,1]^2, gamma 5/3, P1 centroidal Taylor basis, HLL flux at two Gauss
+points per face, slope limiter on, SSP-RK2 with the CFL-0.3 step recomputed on
+the device every step (seeded synthetic initial state: see workloads.c2_state).
+
+A step is one SSP-RK2 step: stage-1 kernel, stage-2 kernel (which also takes
+per-wave minima of the next CFL step) and a one-workgroup dt reduction.  The
+metric counts cells x RK stages per second.  Inputs are resident in HBM before
+timing starts.
+
+Prints one JSON line (rank 0): value, roofline of the dominant kernel (stage 2,
+timed with HIP events on the stream it is launched on), and the CPU oracle timed
+on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DG cell-updates/s (cells×RK stages) & %HBM roofline; fwd+adjoint/fwd time ratio"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cell for each stage kernel of 2D Euler (12 coefficients):
+# stage 1 reads U and writes V1 (24 values); stage 2 reads V1 and U and writes
+# U_next (36 values).  Limiter and CFL minima add no algorithmic traffic.
+STAGE_VALUES = {1: 24, 2: 36}
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--n", type=int, default=2048, help="cells per side")
+    p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    p.add_argument("--also-fp32", action="store_true", default=True)
+    p.add_argument("--no-fp32", dest="also_fp32", action="store_false")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-steps", type=int, default=2)
+    return p.parse_args()
+
+
+def run_gpu(U0, n, precision, steps, warmup, cfl=0.3):
+    import torch
+
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), precision=precision, limiter=True,
+               gamma=5.0 / 3.0)
+    U = s.to_device(U0)
+    V1 = s.empty()
+    Un = s.empty()
+    dt = s.cfl_dt(U, cfl)
+    for _ in range(warmup):
+        s.stage1(U, dt, V1)
+        s.stage2(U, V1, dt, Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    s.check()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[3 * k].record(stream)
+        s.stage1(U, dt, V1)
+        ev[3 * k + 1].record(stream)
+        s.stage2(U, V1, dt, Un, cfl=cfl, dt_next=dt)
+        ev[3 * k + 2].record(stream)
+        U, Un = Un, U
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.check()
+    t1 = sum(ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(steps)) / steps * 1e-3
+    t2 = sum(ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(steps)) / steps * 1e-3
+    tev = ev[0].elapsed_time(ev[-1]) * 1e-3
+    final_dt = dt.item()
+    s.close()
+    return {"wall_s": wall, "event_s": tev, "stage1_s": t1, "stage2_s": t2, "dt_last": final_dt}
+
+
+def cpu_baseline(U0, n, nsteps):
+    import oracle
+    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    dt = oracle.cfl_dt(om, U0, 5.0 / 3.0, 0.3)
+    t0 = time.perf_counter()
+    U = U0
+    for _ in range(nsteps):
+        U = oracle.step(om, U, dt, 5.0 / 3.0, True)
+    el = time.perf_counter() - t0
+    return {"value": n * n * 2 * nsteps / el, "unit": "cell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nsteps} SSP-RK2 steps (limited) of the same {n}x{n} shear-layer state, "
+                      f"FP64, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import workloads as W
+    n = a.n
+    U0 = W.c2_state(n)
+    elem = 8 if a.precision == "fp64" else 4
+    r = run_gpu(U0, n, a.precision, a.steps, a.warmup)
+    ncells = n * n
+    value = ncells * 2 * a.steps / r["event_s"]
+    stage2_bytes = STAGE_VALUES[2] * elem * ncells
+    achieved = stage2_bytes / r["stage2_s"] / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
+                               "P1 Taylor DG, HLL, limiter on, SSP-RK2 CFL 0.3",
+                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cart2d stage 2 (+ dt reduction)",
+                     "bytes_per_launch": stage2_bytes,
+                     "avg_launch_s": r["stage2_s"]},
+        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
+                    "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu(U0, n, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
+                       "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / r32["stage1_s"] / 1e9}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

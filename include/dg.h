@@ -138,6 +138,20 @@ dg_status dg_limit(dg_mesh_t mesh, const void* U, void* U_lim, void* stream);
  * back: one extra state copy). */
 dg_status dg_step(dg_mesh_t mesh, const void* U, void* U_next, double dt, void* stream);
 
+/* The two stages of dg_step as separate launches:
+ *   dg_stage1: V1 = Pi(U) + dt L(Pi(U))                          (one kernel)
+ *   dg_stage2: U_next = Pi(U)/2 + (Pi(V1) + dt L(Pi(V1)))/2      (one kernel)
+ * The step size is *dt_dev when dt_dev is not NULL (a device double), else dt.
+ * When dt_next_dev is not NULL, dg_stage2 also writes
+ *   *dt_next_dev = cfl * min_e (CFL bound of U_next's cell means)
+ * (the formula of dg_cfl_dt), from per-wave minima taken inside the stage
+ * kernel plus one single-workgroup reduction; it may equal dt_dev.
+ * V1 must not alias U; U_next must alias neither U nor V1. */
+dg_status dg_stage1(dg_mesh_t mesh, const void* U, void* V1, double dt, const double* dt_dev,
+                    void* stream);
+dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next, double dt,
+                    const double* dt_dev, double cfl, double* dt_next_dev, void* stream);
+
 /* Same as dg_step with the step size read from device memory (*dt_dev, a
  * double), so a step can follow dg_cfl_dt without a host synchronisation. */
 dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,

@@ -64,6 +64,11 @@ SYMBOLS = [
     ("dg_limit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                ctypes.c_void_p]),
+    ("dg_stage1", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_stage2", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_step_devdt", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_cfl_dt", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,

@@ -58,6 +58,13 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
+// Number of per-wave partial minima the stage-2 kernel writes.
+static int stage_waves(const dg_mesh* m) {
+  if (m->kind == 1) return m->fl.nblocks * 4;
+  if (m->dim == 2) return m->c2.tiles_x * m->c2.tiles_y;
+  return m->c3.tiles_x * m->c3.tiles_y * m->c3.tiles_z;
+}
+
 static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                           const double* dt_dev, double dt_host, hipStream_t s) {
   hipError_t e;
@@ -238,6 +245,28 @@ dg_status dg_step(dg_mesh_t m, const void* U, void* Un, double dt, void* stream)
   if (!m || !U || !Un) return einval("dg_step: NULL argument");
   if (!std::isfinite(dt) || dt < 0) return einval("dg_step: dt must be finite and >= 0");
   return step_impl(m, U, Un, nullptr, dt, (hipStream_t)stream);
+}
+
+dg_status dg_stage1(dg_mesh_t m, const void* U, void* V1, double dt, const double* dt_dev,
+                    void* stream) {
+  if (!m || !U || !V1) return einval("dg_stage1: NULL argument");
+  if (U == V1) return einval("dg_stage1: U and V1 must not alias");
+  if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage1: dt must be finite and >= 0");
+  return dispatch(m, kStage1, U, nullptr, V1, dt_dev, dt, (hipStream_t)stream);
+}
+
+dg_status dg_stage2(dg_mesh_t m, const void* U, const void* V1, void* Un, double dt,
+                    const double* dt_dev, double cfl, double* dt_next_dev, void* stream) {
+  if (!m || !U || !V1 || !Un) return einval("dg_stage2: NULL argument");
+  if (Un == U || Un == V1) return einval("dg_stage2: U_next must not alias U or V1");
+  if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage2: dt must be finite and >= 0");
+  if (dt_next_dev && !(cfl > 0 && std::isfinite(cfl))) return einval("dg_stage2: cfl must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  dg_status st = dispatch(m, kStage2, V1, U, Un, dt_dev, dt, s);
+  if (st != DG_OK || !dt_next_dev) return st;
+  hipError_t e = launch_min_finalize(m->dtpart, stage_waves(m), cfl, dt_next_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "dg_stage2: CFL reduction");
+  return DG_OK;
 }
 
 dg_status dg_step_devdt(dg_mesh_t m, const void* U, void* Un, const double* dt_dev,

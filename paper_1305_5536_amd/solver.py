@@ -128,6 +128,34 @@ class Solver:
         C.check(st, "dg_step")
         return out
 
+    @staticmethod
+    def _dt_args(dt):
+        if isinstance(dt, torch.Tensor):
+            if dt.dtype != torch.float64 or dt.numel() != 1:
+                raise ValueError("device dt must be a one-element float64 tensor")
+            return 0.0, _ptr(dt)
+        return float(dt), None
+
+    def stage1(self, U: torch.Tensor, dt, out: torch.Tensor) -> torch.Tensor:
+        """V1 = Pi(U) + dt L(Pi(U)); dt a float or a device float64 scalar tensor."""
+        self._check_state(U)
+        self._check_state(out, "out")
+        h, d = self._dt_args(dt)
+        C.check(C.lib().dg_stage1(self._h, _ptr(U), _ptr(out), h, d, _stream()), "dg_stage1")
+        return out
+
+    def stage2(self, U: torch.Tensor, V1: torch.Tensor, dt, out: torch.Tensor,
+               cfl: float = 0.0, dt_next: torch.Tensor | None = None) -> torch.Tensor:
+        """U' = Pi(U)/2 + (Pi(V1) + dt L(Pi(V1)))/2; optionally dt_next = CFL step of U'."""
+        self._check_state(U)
+        self._check_state(V1, "V1")
+        self._check_state(out, "out")
+        h, d = self._dt_args(dt)
+        nxt = None if dt_next is None else _ptr(dt_next)
+        C.check(C.lib().dg_stage2(self._h, _ptr(U), _ptr(V1), _ptr(out), h, d, float(cfl), nxt,
+                                  _stream()), "dg_stage2")
+        return out
+
     def cfl_dt(self, U: torch.Tensor, cfl: float, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check_state(U)
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out

@@ -217,3 +217,26 @@ def test_bad_arguments_are_rejected(torch_cuda):
     assert st == C.DG_EINVAL
     with pytest.raises(DGError):
         C.check(st, "dg_rhs")
+
+
+def test_stages_with_device_dt_and_fused_cfl(oracle, torch_cuda):
+    """dg_stage1 + dg_stage2 equal dg_step; the fused CFL minimum of stage 2
+    equals dg_cfl_dt of the new state (and the oracle's)."""
+    n, lo, hi = (150, 90), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=13, amp=0.3)
+    s = _solver(n, lo, hi, G53)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    V1 = s.empty()
+    Un = s.empty()
+    dt_next = torch_cuda.empty(1, dtype=torch_cuda.float64, device="cuda")
+    s.stage1(U, dt, V1)
+    s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt_next)
+    ref = s.step(U, dt.item())
+    assert torch_cuda.equal(Un, ref)
+    assert dt_next.item() == s.cfl_dt(Un, 0.3).item()
+    o = oracle.cfl_dt(oracle.Mesh.cartesian(n, lo, hi), Un.cpu().numpy(), G53, 0.3)
+    assert abs(dt_next.item() - o) <= 1e-14 * o
+    # dt_next may alias dt
+    s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt)
+    assert dt.item() == dt_next.item()
