@@ -162,6 +162,16 @@ dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const doubl
  * n_f for MHD).  dt_dev is a device pointer to one double. */
 dg_status dg_cfl_dt(dg_mesh_t mesh, const void* U, double cfl, double* dt_dev, void* stream);
 
+/* Launch shape of the Cartesian stage kernels: the number of rows (2D) or
+ * z-planes (3D) one wave marches through.  0 restores the library default.
+ * Results do not depend on it (every face and cell is computed with the same
+ * arithmetic whatever the tiling); only speed does.  Face-list meshes ignore
+ * it.  Returns DG_EINVAL for a negative value. */
+dg_status dg_set_tiling(dg_mesh_t mesh, int rows_per_tile);
+
+/* Current rows (or planes) per wave, or -1 for a NULL handle. */
+int dg_get_tiling(dg_mesh_t mesh);
+
 /* Synchronise the device, then return DG_ENONPHYSICAL if any kernel of this
  * mesh met a non-physical state since the last call (and clear the flag),
  * else DG_OK (or DG_EHIP if synchronisation failed). */

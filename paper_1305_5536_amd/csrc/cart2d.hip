@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dg_internal.h"
+#include "dg_math.h"
 
 namespace dg {
 namespace {
@@ -43,23 +44,24 @@ struct P2 {
   const double* dt_dev;
   double dt_host;
   int* status;
-  double* dtpart;
-  int nx, ny, rows, tiles_x, ntiles;
-  int64_t nc;
-  T hx, hy, gamma;
+  double* dtpart;       // per-wave CFL minima (stage 2 with dt_next)
+  double* dt_next;
+  double cfl;
+  int nx, ny, rows, tiles_x, ntiles, nc;
+  T gamma;
   T cmx, cmy, cgx, cgy, ccr;  // 1/(2hx), 1/(2hy), 3/hx^2, 3/hy^2, sqrt3/(hx hy)
   T hx2, hy2, qx, qy;         // hx/2, hy/2, hx/(2 sqrt3), hy/(2 sqrt3)
+  double ihx, ihy;            // 1/hx, 1/hy
 };
 
-// One row of a column: 4 variables x (mean, gx, gy).
+// One cell: 4 variables x (mean, gx, gy).
 template <typename T>
 struct Cell {
   T m[4], gx[4], gy[4];
 };
 
 template <typename T>
-__device__ __forceinline__ void load_cell(const T* __restrict__ U, int64_t nc, int64_t e,
-                                          Cell<T>& c) {
+__device__ __forceinline__ void load_cell(const T* __restrict__ U, int nc, int e, Cell<T>& c) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     c.m[v] = U[(3 * v) * nc + e];
@@ -69,15 +71,25 @@ __device__ __forceinline__ void load_cell(const T* __restrict__ U, int64_t nc, i
 }
 
 template <typename T>
-__device__ __forceinline__ void load_means(const T* __restrict__ U, int64_t nc, int64_t e, T* m) {
+__device__ __forceinline__ void load_means(const T* __restrict__ U, int nc, int e, T* m) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) m[v] = U[(3 * v) * nc + e];
 }
 
+template <typename T>
+__device__ __forceinline__ void store_cell(T* __restrict__ U, int nc, int e, const Cell<T>& c) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    U[(3 * v) * nc + e] = c.m[v];
+    U[(3 * v + 1) * nc + e] = c.gx[v];
+    U[(3 * v + 2) * nc + e] = c.gy[v];
+  }
+}
+
 // Limiter of one cell from its x-neighbour means (shuffled) and y-neighbour
-// means (window).  On a Cartesian cell the +d and -d face centroids sit at
-// -+ h_d/2, so the two psi of an axis reduce to min(max-phi, phi-min)/|g_d h_d/2|
-// and alpha = min(1, D / max_d |g_d h_d / 2|).
+// means.  On a Cartesian cell the +d and -d face centroids sit at -+ h_d/2,
+// so the two psi of an axis reduce to min(max-phi, phi-min)/|g_d h_d/2| and
+// alpha = min(1, D / max_d |g_d h_d / 2|).
 template <typename T>
 __device__ __forceinline__ void limit_cell(Cell<T>& c, const T* mS, const T* mN, const P2<T>& p) {
 #pragma unroll
@@ -89,23 +101,25 @@ __device__ __forceinline__ void limit_cell(Cell<T>& c, const T* mS, const T* mN,
     T lo = fmin(fmin(fmin(phi, mW), fmin(mE, mS[v])), mN[v]);
     T D = fmin(hi - phi, phi - lo);
     T dm = fmax(fabs(c.gx[v]) * p.hx2, fabs(c.gy[v]) * p.hy2);
-    T a = (dm > D) ? D / dm : T(1);
+    T a = (dm > D) ? D * rcp(dm) : T(1);
     c.gx[v] *= a;
     c.gy[v] *= a;
   }
 }
 
-// HLL flux (Davis wave speeds) along axis AX between states uL, uR.
+// HLL flux (Davis wave speeds) along axis AX between states uL, uR, written
+// as F = a F_L + b F_R + c (u_R - u_L) with (a, b, c) = (1, 0, 0) left of the
+// fan, (0, 1, 0) right of it and (S_R, -S_L, S_L S_R)/(S_R - S_L) inside.
 template <typename T, int AX>
 __device__ __forceinline__ void hll(const T* uL, const T* uR, T gamma, T* F, bool& bad) {
   const T gm1 = gamma - T(1);
-  T irL = T(1) / uL[0], irR = T(1) / uR[0];
+  T irL = rcp(uL[0]), irR = rcp(uR[0]);
   T vxL = uL[1] * irL, vyL = uL[2] * irL;
   T vxR = uR[1] * irR, vyR = uR[2] * irR;
   T pL = gm1 * (uL[3] - T(0.5) * (uL[1] * vxL + uL[2] * vyL));
   T pR = gm1 * (uR[3] - T(0.5) * (uR[1] * vxR + uR[2] * vyR));
   bad |= !(uL[0] > T(0)) || !(uR[0] > T(0)) || !(pL > T(0)) || !(pR > T(0));
-  T cL = sqrt(gamma * pL * irL), cR = sqrt(gamma * pR * irR);
+  T cL = sqrt_pos(gamma * pL * irL), cR = sqrt_pos(gamma * pR * irR);
   T vnL = AX == 0 ? vxL : vyL;
   T vnR = AX == 0 ? vxR : vyR;
   T SL = fmin(vnL - cL, vnR - cR);
@@ -114,19 +128,20 @@ __device__ __forceinline__ void hll(const T* uL, const T* uR, T gamma, T* F, boo
   T FR[4] = {uR[0] * vnR, uR[1] * vnR, uR[2] * vnR, (uR[3] + pR) * vnR};
   FL[1 + AX] += pL;
   FR[1 + AX] += pR;
-  T inv = T(1) / (SR - SL);
-  T SLSR = SL * SR;
+  T inv = rcp(SR - SL);
+  T a = SR * inv, b = -SL * inv, c = SL * SR * inv;
+  const bool left = SL >= T(0), right = SR <= T(0);
+  a = left ? T(1) : (right ? T(0) : a);
+  b = left ? T(0) : (right ? T(1) : b);
+  c = (left || right) ? T(0) : c;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    T mid = (SR * FL[k] - SL * FR[k] + SLSR * (uR[k] - uL[k])) * inv;
-    F[k] = SL >= T(0) ? FL[k] : (SR <= T(0) ? FR[k] : mid);
-  }
+  for (int k = 0; k < 4; ++k) F[k] = fma(a, FL[k], fma(b, FR[k], c * (uR[k] - uL[k])));
 }
 
 // Both Cartesian flux rows F_x, F_y at one state (volume term).
 template <typename T>
 __device__ __forceinline__ void flux_xy(const T* u, T gamma, T* Fx, T* Fy, bool& bad) {
-  T ir = T(1) / u[0];
+  T ir = rcp(u[0]);
   T vx = u[1] * ir, vy = u[2] * ir;
   T p = (gamma - T(1)) * (u[3] - T(0.5) * (u[1] * vx + u[2] * vy));
   bad |= !(u[0] > T(0)) || !(p > T(0));
@@ -140,38 +155,32 @@ __device__ __forceinline__ void flux_xy(const T* u, T gamma, T* Fx, T* Fy, bool&
   Fy[3] = (u[3] + p) * vy;
 }
 
-template <typename T>
-__device__ __forceinline__ void shfl_up_cell(const Cell<T>& c, Cell<T>& o) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    o.m[v] = __shfl_up(c.m[v], 1);
-    o.gx[v] = __shfl_up(c.gx[v], 1);
-    o.gy[v] = __shfl_up(c.gy[v], 1);
-  }
-}
-
-// x-face between the left neighbour L (lane-1) and this cell R: returns S, D.
+// x-face between the left neighbour L (lane - 1) and this cell R.  Returns
+// S = F(g0) + F(g1), D = F(g1) - F(g0) per variable (g0 at y offset -qy).
 template <typename T>
 __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
-  T F0[4], F1[4];
-  {
-    T uL[4], uR[4];
+  T bl[4], br[4], tl[4], tr[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      T bl = L.m[v] + L.gx[v] * p.hx2, br = R.m[v] - R.gx[v] * p.hx2;
-      uL[v] = bl - L.gy[v] * p.qy;
-      uR[v] = br - R.gy[v] * p.qy;
-    }
-    hll<T, 0>(uL, uR, p.gamma, F0, bad);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      T bl = L.m[v] + L.gx[v] * p.hx2, br = R.m[v] - R.gx[v] * p.hx2;
-      uL[v] = bl + L.gy[v] * p.qy;
-      uR[v] = br + R.gy[v] * p.qy;
-    }
-    hll<T, 0>(uL, uR, p.gamma, F1, bad);
+  for (int v = 0; v < 4; ++v) {
+    bl[v] = fma(L.gx[v], p.hx2, L.m[v]);
+    br[v] = fma(-R.gx[v], p.hx2, R.m[v]);
+    tl[v] = L.gy[v] * p.qy;
+    tr[v] = R.gy[v] * p.qy;
   }
+  T uL[4], uR[4], F0[4], F1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    uL[v] = bl[v] - tl[v];
+    uR[v] = br[v] - tr[v];
+  }
+  hll<T, 0>(uL, uR, p.gamma, F0, bad);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    uL[v] = bl[v] + tl[v];
+    uR[v] = br[v] + tr[v];
+  }
+  hll<T, 0>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     S[v] = F0[v] + F1[v];
@@ -183,20 +192,25 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
 template <typename T>
 __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
-  T F0[4], F1[4];
-  T uL[4], uR[4];
+  T bl[4], br[4], tl[4], tr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    T bl = L.m[v] + L.gy[v] * p.hy2, br = R.m[v] - R.gy[v] * p.hy2;
-    uL[v] = bl - L.gx[v] * p.qx;
-    uR[v] = br - R.gx[v] * p.qx;
+    bl[v] = fma(L.gy[v], p.hy2, L.m[v]);
+    br[v] = fma(-R.gy[v], p.hy2, R.m[v]);
+    tl[v] = L.gx[v] * p.qx;
+    tr[v] = R.gx[v] * p.qx;
+  }
+  T uL[4], uR[4], F0[4], F1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    uL[v] = bl[v] - tl[v];
+    uR[v] = br[v] - tr[v];
   }
   hll<T, 1>(uL, uR, p.gamma, F0, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    T bl = L.m[v] + L.gy[v] * p.hy2, br = R.m[v] - R.gy[v] * p.hy2;
-    uL[v] = bl + L.gx[v] * p.qx;
-    uR[v] = br + R.gx[v] * p.qx;
+    uL[v] = bl[v] + tl[v];
+    uR[v] = br[v] + tr[v];
   }
   hll<T, 1>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
@@ -206,7 +220,7 @@ __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const 
   }
 }
 
-// Volume term: sum of F_x and F_y over the 2x2 Gauss points.
+// Volume term: sums of F_x and F_y over the 2x2 Gauss points.
 template <typename T>
 __device__ __forceinline__ void volume(const Cell<T>& c, const P2<T>& p, T* sx, T* sy,
                                        bool& bad) {
@@ -218,7 +232,7 @@ __device__ __forceinline__ void volume(const Cell<T>& c, const P2<T>& p, T* sx, 
     const T oy = (q & 1) ? p.qy : -p.qy;
     T u[4], Fx[4], Fy[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) u[v] = c.m[v] + c.gx[v] * ox + c.gy[v] * oy;
+    for (int v = 0; v < 4; ++v) u[v] = fma(c.gx[v], ox, fma(c.gy[v], oy, c.m[v]));
     flux_xy(u, p.gamma, Fx, Fy, bad);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -228,17 +242,6 @@ __device__ __forceinline__ void volume(const Cell<T>& c, const P2<T>& p, T* sx, 
   }
 }
 
-template <typename T>
-struct Acc {
-  T m[4], x[4], y[4];
-};
-
-template <typename T>
-__device__ __forceinline__ void zero(Acc<T>& a) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v) a.m[v] = a.x[v] = a.y[v] = T(0);
-}
-
 // CFL bound of one cell from its means: 1 / sum_d (|v_d| + c)/h_d.
 template <typename T>
 __device__ __forceinline__ double cell_dt(const T* m, const P2<T>& p) {
@@ -246,17 +249,8 @@ __device__ __forceinline__ double cell_dt(const T* m, const P2<T>& p) {
   double vx = m[1] * ir, vy = m[2] * ir;
   double pr = ((double)p.gamma - 1.0) * (m[3] - 0.5 * r * (vx * vx + vy * vy));
   double c = sqrt((double)p.gamma * pr * ir);
-  double s = (fabs(vx) + c) / (double)p.hx + (fabs(vy) + c) / (double)p.hy;
+  double s = (fabs(vx) + c) * p.ihx + (fabs(vy) + c) * p.ihy;
   return 1.0 / s;
-}
-
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of tiles so vertically/horizontally adjacent tiles (and
-  // their halo rows) share that XCD's L2.
-  int per = nb >> 3;
-  if (b < (per << 3)) return (b & 7) * per + (b >> 3);
-  return b;
 }
 
 template <typename T, int MODE, bool LIM>
@@ -269,150 +263,137 @@ __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
   const bool own = lane >= 2 && lane < 2 + kCols && colu < p.nx;
   int col = colu % p.nx;
   if (col < 0) col += p.nx;
+  const int nx = p.nx, ny = p.ny, nc = p.nc;
   const int y0 = ty * p.rows;
-  const int y1 = min(y0 + p.rows, p.ny);
-  const int64_t nc = p.nc;
-  auto rowi = [&](int r) -> int64_t {
-    r %= p.ny;
-    if (r < 0) r += p.ny;
-    return (int64_t)r * p.nx + col;
+  const int y1 = min(y0 + p.rows, ny);
+  auto wrap = [ny](int r) {
+    r %= ny;
+    return r < 0 ? r + ny : r;
   };
-  T dt = T(0);
-  if (MODE == kStage1 || MODE == kStage2) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
+  auto next = [ny](int r) { return r + 1 == ny ? 0 : r + 1; };
   bool bad = false;
   double dtmin = 1e300;
 
-  Cell<T> cur, prevlim;
-  T mS[4];  // means of row j-1 (raw)
-  load_means(p.in, nc, rowi(y0 - 2), mS);
-  load_cell(p.in, nc, rowi(y0 - 1), cur);
-  // stage 2: window over u0 (rows j-2 means, j-1 full)
-  T u0S[4];
-  Cell<T> u0C;
+  // Row window of the input: prev = row j-1 (limited; only its means before
+  // the first iteration), cur = row j, nx1 = row j+1, nx2 = row j+2 (loads in
+  // flight while row j is processed).
+  Cell<T> prev, cur, nx1;
+  load_means(p.in, nc, wrap(y0 - 2) * nx + col, prev.m);
+  int r = wrap(y0 - 1);
+  load_cell(p.in, nc, r * nx + col, cur);
+  r = next(r);
+  load_cell(p.in, nc, r * nx + col, nx1);
+  int r2 = next(r);  // row index of j+2
+
+  // Stage 2: window over u0 for the row being finalised (f = j-1):
+  // u0m = means of f-1, u0c = row f, u0n = row f+1 (means only beyond y1-1).
+  T u0m[4];
+  Cell<T> u0c, u0n;
+  int ru = 0;
   if (MODE == kStage2) {
-    load_means(p.u0, nc, rowi(y0 - 1), u0S);
-    load_cell(p.u0, nc, rowi(y0), u0C);
+    load_means(p.u0, nc, wrap(y0 - 1) * nx + col, u0m);
+    ru = wrap(y0);
+    load_cell(p.u0, nc, ru * nx + col, u0c);
+    ru = next(ru);
+    if (y0 + 1 <= y1 - 1)
+      load_cell(p.u0, nc, ru * nx + col, u0n);
+    else
+      load_means(p.u0, nc, ru * nx + col, u0n.m);
+    ru = next(ru);  // row f+2 for the first finalised row
   }
-  Acc<T> accP, accC;
-  zero(accP);
-  zero(accC);
+  T ySm[4], yDm[4];
+  // the step size is first needed when row y0 is finalised
+  T dt = T(0);
+  if (MODE == kStage1 || MODE == kStage2) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
 
   for (int j = y0 - 1; j <= y1; ++j) {
-    // next raw row (only means needed beyond the halo row)
-    Cell<T> nxt;
-    T mN[4];
-    if (j + 1 <= y1) {
-      load_cell(p.in, nc, rowi(j + 1), nxt);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) mN[v] = nxt.m[v];
-    } else {
-      load_means(p.in, nc, rowi(j + 1), mN);
-    }
-    Cell<T> lim = cur;
-    if (LIM || MODE == kLimit) limit_cell(lim, mS, mN, p);
+    Cell<T> nx2;
+    if (j + 2 <= y1)
+      load_cell(p.in, nc, r2 * nx + col, nx2);
+    else if (j + 2 == y1 + 1)
+      load_means(p.in, nc, r2 * nx + col, nx2.m);
+    r2 = next(r2);
+
+    if (LIM || MODE == kLimit) limit_cell(cur, prev.m, nx1.m, p);
 
     if (MODE == kLimit) {
-      if (own && j >= y0 && j < y1) {
-        const int64_t e = rowi(j);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          p.out[(3 * v) * nc + e] = lim.m[v];
-          p.out[(3 * v + 1) * nc + e] = lim.gx[v];
-          p.out[(3 * v + 2) * nc + e] = lim.gy[v];
-        }
-      }
+      if (own && j >= y0 && j < y1) store_cell(p.out, nc, wrap(j) * nx + col, cur);
     } else {
-      if (j >= y0) {
-        T S[4], D[4];
-        yface(prevlim, lim, p, S, D, bad);
+      T Sy[4], Dy[4];
+      if (j >= y0) yface(prev, cur, p, Sy, Dy, bad);
+      if (j >= y0 + 1) {
+        // Finalise row f = j - 1 (held in prev).
+        Cell<T> u0nn;
+        if (MODE == kStage2) {
+          if (j + 1 <= y1 - 1)
+            load_cell(p.u0, nc, ru * nx + col, u0nn);
+          else if (j + 1 == y1)
+            load_means(p.u0, nc, ru * nx + col, u0nn.m);
+          ru = next(ru);
+        }
+        Cell<T> left;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          accP.m[v] -= S[v] * p.cmy;
-          accP.y[v] -= S[v] * p.cgy;
-          accP.x[v] -= D[v] * p.ccr;
-          accC.m[v] += S[v] * p.cmy;
-          accC.y[v] -= S[v] * p.cgy;
-          accC.x[v] += D[v] * p.ccr;
+          left.m[v] = __shfl_up(prev.m[v], 1);
+          left.gx[v] = __shfl_up(prev.gx[v], 1);
+          left.gy[v] = __shfl_up(prev.gy[v], 1);
         }
-      }
-      if (j >= y0 && j < y1) {
-        Cell<T> left;
-        shfl_up_cell(lim, left);
-        T Sm[4], Dm[4];
-        xface(left, lim, p, Sm, Dm, bad);
-        T sx[4], sy[4];
-        volume(lim, p, sx, sy, bad);
+        T Sm[4], Dm[4], sx[4], sy[4];
+        xface(left, prev, p, Sm, Dm, bad);
+        volume(prev, p, sx, sy, bad);
+        Cell<T> o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           T Sp = __shfl_down(Sm[v], 1);
           T Dp = __shfl_down(Dm[v], 1);
-          accC.m[v] += (Sm[v] - Sp) * p.cmx;
-          accC.x[v] += (sx[v] - Sm[v] - Sp) * p.cgx;
-          accC.y[v] += (sy[v]) * p.cgy + (Dm[v] - Dp) * p.ccr;
-        }
-      }
-      if (j - 1 >= y0) {
-        // finalize row j-1
-        Cell<T> o;
-        if (MODE == kRhs) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            o.m[v] = accP.m[v];
-            o.gx[v] = accP.x[v];
-            o.gy[v] = accP.y[v];
-          }
-        } else if (MODE == kStage1) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            o.m[v] = prevlim.m[v] + dt * accP.m[v];
-            o.gx[v] = prevlim.gx[v] + dt * accP.x[v];
-            o.gy[v] = prevlim.gy[v] + dt * accP.y[v];
-          }
-        } else {  // kStage2
-          T u0N[4];
-          Cell<T> u0nxt;
-          if (j < y1) {
-            load_cell(p.u0, nc, rowi(j), u0nxt);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) u0N[v] = u0nxt.m[v];
+          T dm = (Sm[v] - Sp) * p.cmx + (ySm[v] - Sy[v]) * p.cmy;
+          T dgx = (sx[v] - Sm[v] - Sp) * p.cgx + (yDm[v] - Dy[v]) * p.ccr;
+          T dgy = (sy[v] - ySm[v] - Sy[v]) * p.cgy + (Dm[v] - Dp) * p.ccr;
+          if (MODE == kRhs) {
+            o.m[v] = dm;
+            o.gx[v] = dgx;
+            o.gy[v] = dgy;
           } else {
-            load_means(p.u0, nc, rowi(j), u0N);
+            o.m[v] = fma(dt, dm, prev.m[v]);
+            o.gx[v] = fma(dt, dgx, prev.gx[v]);
+            o.gy[v] = fma(dt, dgy, prev.gy[v]);
           }
-          Cell<T> ua = u0C;
-          if (LIM) limit_cell(ua, u0S, u0N, p);
+        }
+        if (MODE == kStage2) {
+          Cell<T> ua = u0c;
+          if (LIM) limit_cell(ua, u0m, u0n.m, p);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            o.m[v] = T(0.5) * ua.m[v] + T(0.5) * (prevlim.m[v] + dt * accP.m[v]);
-            o.gx[v] = T(0.5) * ua.gx[v] + T(0.5) * (prevlim.gx[v] + dt * accP.x[v]);
-            o.gy[v] = T(0.5) * ua.gy[v] + T(0.5) * (prevlim.gy[v] + dt * accP.y[v]);
+            o.m[v] = T(0.5) * (ua.m[v] + o.m[v]);
+            o.gx[v] = T(0.5) * (ua.gx[v] + o.gx[v]);
+            o.gy[v] = T(0.5) * (ua.gy[v] + o.gy[v]);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) u0S[v] = u0C.m[v];
-          if (j < y1) u0C = u0nxt;
+          for (int v = 0; v < 4; ++v) u0m[v] = u0c.m[v];
+          u0c = u0n;
+          u0n = u0nn;
         }
         if (own) {
-          const int64_t e = rowi(j - 1);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            p.out[(3 * v) * nc + e] = o.m[v];
-            p.out[(3 * v + 1) * nc + e] = o.gx[v];
-            p.out[(3 * v + 2) * nc + e] = o.gy[v];
-          }
-          if (MODE == kStage2 && p.dtpart) dtmin = fmin(dtmin, cell_dt(o.m, p));
+          store_cell(p.out, nc, wrap(j - 1) * nx + col, o);
+          if (MODE == kStage2 && p.dt_next) dtmin = fmin(dtmin, cell_dt(o.m, p));
         }
       }
-      accP = accC;
-      zero(accC);
-    }
+      if (j >= y0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) mS[v] = cur.m[v];
-    prevlim = lim;
-    if (j + 1 <= y1) cur = nxt;
+        for (int v = 0; v < 4; ++v) {
+          ySm[v] = Sy[v];
+          yDm[v] = Dy[v];
+        }
+      }
+    }
+    prev = cur;
+    cur = nx1;
+    nx1 = nx2;
   }
   if (bad && own) atomicOr(p.status, 1);
-  if (MODE == kStage2 && p.dtpart) {
-    // wave minimum (lanes exchange via shuffles), one write per wave
-    for (int o = 32; o > 0; o >>= 1) dtmin = fmin(dtmin, __shfl_xor(dtmin, o));
+  if (MODE == kStage2 && p.dt_next) {
+    // per-wave CFL minimum; a one-workgroup kernel reduces them afterwards
+    dtmin = wave_min(dtmin);
     if (lane == 0) p.dtpart[wave] = dtmin;
   }
 }
@@ -420,7 +401,7 @@ __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
 // Per-wave CFL minima of a state's cell means (stand-alone dg_cfl_dt).
 template <typename T>
 __global__ __launch_bounds__(256) void k_cart2d_cfl(P2<T> p) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   double d = 1e300;
   if (e < p.nc) {
     T m[4];
@@ -431,20 +412,21 @@ __global__ __launch_bounds__(256) void k_cart2d_cfl(P2<T> p) {
   if ((threadIdx.x & 63) == 0) p.dtpart[e >> 6] = d;
 }
 
-// Final minimum over the partials: *dt = cfl * min.  One workgroup, fixed
-// order (deterministic).
-__global__ __launch_bounds__(256) void k_min_finalize(const double* part, int n, double cfl,
-                                                      double* dt) {
-  __shared__ double s[256];
+// Final minimum over the partials: *dt = cfl * min.  One workgroup of 1024
+// threads; min is exact in any order, so the result is deterministic.
+__global__ __launch_bounds__(1024) void k_min_finalize(const double* part, int n, double cfl,
+                                                       double* dt) {
+  __shared__ double s[16];
   double d = 1e300;
-  for (int i = threadIdx.x; i < n; i += 256) d = fmin(d, part[i]);
-  s[threadIdx.x] = d;
+  for (int i = threadIdx.x; i < n; i += 1024) d = fmin(d, part[i]);
+  d = wave_min(d);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = d;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + w]);
-    __syncthreads();
+  if (threadIdx.x < 64) {
+    d = threadIdx.x < 16 ? s[threadIdx.x] : 1e300;
+    d = wave_min(d);
+    if (threadIdx.x == 0) *dt = cfl * d;
   }
-  if (threadIdx.x == 0) *dt = cfl * s[0];
 }
 
 template <typename T>
@@ -457,16 +439,16 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
   p.dt_dev = dt_dev;
   p.dt_host = dt_host;
   p.status = m->status;
-  p.dtpart = nullptr;
+  p.dtpart = m->dtpart;
+  p.dt_next = nullptr;
+  p.cfl = 0.0;
   p.nx = m->c2.nx;
   p.ny = m->c2.ny;
   p.rows = m->c2.rows_per_tile;
   p.tiles_x = m->c2.tiles_x;
   p.ntiles = m->c2.tiles_x * m->c2.tiles_y;
-  p.nc = m->ncells;
+  p.nc = (int)m->ncells;
   const double hx = m->c2.hx, hy = m->c2.hy, s3 = 1.7320508075688772;
-  p.hx = (T)hx;
-  p.hy = (T)hy;
   p.gamma = (T)m->cfg.gamma;
   p.cmx = (T)(0.5 / hx);
   p.cmy = (T)(0.5 / hy);
@@ -477,16 +459,22 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
   p.hy2 = (T)(0.5 * hy);
   p.qx = (T)(0.5 * hx / s3);
   p.qy = (T)(0.5 * hy / s3);
+  p.ihx = 1.0 / hx;
+  p.ihy = 1.0 / hy;
   return p;
 }
 
 template <typename T>
 hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                    const double* dt_dev, double dt_host, hipStream_t s) {
+                    const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                    hipStream_t s) {
   P2<T> p = make_params<T>(m, in, u0, out, dt_dev, dt_host);
   const int nblocks = (p.ntiles + 3) / 4;
   const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
-  if (mode == kStage2) p.dtpart = m->dtpart;
+  if (mode == kStage2) {
+    p.dt_next = dt_next;
+    p.cfl = cfl;
+  }
   switch (mode) {
     case kRhs:
       hipLaunchKernelGGL((k_cart2d<T, kRhs, false>), dim3(nblocks), dim3(256), 0, s, p);
@@ -505,6 +493,9 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
         hipLaunchKernelGGL((k_cart2d<T, kStage2, true>), dim3(nblocks), dim3(256), 0, s, p);
       else
         hipLaunchKernelGGL((k_cart2d<T, kStage2, false>), dim3(nblocks), dim3(256), 0, s, p);
+      if (dt_next)
+        hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
+                           dt_next);
       break;
     default:
       return hipErrorInvalidValue;
@@ -519,17 +510,18 @@ hipError_t cfl_t(const dg_mesh* m, const void* U, double cfl, double* dt_dev, hi
   const int64_t nblk = (m->ncells + 255) / 256;
   hipLaunchKernelGGL((k_cart2d_cfl<T>), dim3((unsigned)nblk), dim3(256), 0, s, p);
   const int nparts = (int)((m->ncells + 63) / 64);
-  hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(256), 0, s, m->dtpart, nparts, cfl, dt_dev);
+  hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, nparts, cfl, dt_dev);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                         const double* dt_dev, double dt_host, hipStream_t s) {
+                         const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                         hipStream_t s) {
   if (m->cfg.precision == DG_FP64)
-    return launch_t<double>(m, mode, in, u0, out, dt_dev, dt_host, s);
-  return launch_t<float>(m, mode, in, u0, out, dt_dev, dt_host, s);
+    return launch_t<double>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+  return launch_t<float>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
 }
 
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
@@ -540,7 +532,7 @@ hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double
 
 hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(256), 0, s, part, n, cfl, dt);
+  hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, part, n, cfl, dt);
   return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 
 namespace dg {
 hipError_t launch_cart3d(const dg_mesh*, int, const void*, const void*, void*, const double*,
-                         double, hipStream_t) {
+                         double, double, double*, hipStream_t) {
   return hipErrorNotSupported;
 }
 hipError_t launch_cart3d_cfl(const dg_mesh*, const void*, double, double*, hipStream_t) {

@@ -32,11 +32,13 @@ hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt
 dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d);
 void facelist_destroy(dg_mesh* m);
 hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                           const double* dt_dev, double dt_host, hipStream_t s);
+                           const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                           hipStream_t s);
 hipError_t launch_facelist_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                                hipStream_t s);
 hipError_t launch_cart3d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                         const double* dt_dev, double dt_host, hipStream_t s);
+                         const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                         hipStream_t s);
 hipError_t launch_cart3d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
 
@@ -58,22 +60,16 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
-// Number of per-wave partial minima the stage-2 kernel writes.
-static int stage_waves(const dg_mesh* m) {
-  if (m->kind == 1) return m->fl.nblocks * 4;
-  if (m->dim == 2) return m->c2.tiles_x * m->c2.tiles_y;
-  return m->c3.tiles_x * m->c3.tiles_y * m->c3.tiles_z;
-}
-
 static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                          const double* dt_dev, double dt_host, hipStream_t s) {
+                          const double* dt_dev, double dt_host, hipStream_t s,
+                          double cfl = 0.0, double* dt_next = nullptr) {
   hipError_t e;
   if (m->kind == 1)
-    e = launch_facelist(m, mode, in, u0, out, dt_dev, dt_host, s);
+    e = launch_facelist(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else if (m->dim == 2)
-    e = launch_cart2d(m, mode, in, u0, out, dt_dev, dt_host, s);
+    e = launch_cart2d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else
-    e = launch_cart3d(m, mode, in, u0, out, dt_dev, dt_host, s);
+    e = launch_cart3d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return DG_OK;
 }
@@ -181,8 +177,11 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
   // the stand-alone CFL kernel (whole 256-thread blocks write)
+  // (the finest tiling, one row per wave, has at most ncells/60 + rows waves)
+  nwaves = std::max<int64_t>(nwaves, (m->ncells + 59) / 60 + (m->dim == 2 ? m->c2.ny : m->c3.ny * m->c3.nz));
   m->ndtpart = (int)std::max<int64_t>(nwaves, 4 * ((m->ncells + 255) / 256));
   if (e == hipSuccess) e = hipMalloc(&m->dtpart, sizeof(double) * m->ndtpart);
+
   if (e != hipSuccess) {
     dg_status st = hip_fail(e, "dg_mesh_create: device allocation");
     dg_mesh_destroy(m);
@@ -261,12 +260,7 @@ dg_status dg_stage2(dg_mesh_t m, const void* U, const void* V1, void* Un, double
   if (Un == U || Un == V1) return einval("dg_stage2: U_next must not alias U or V1");
   if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage2: dt must be finite and >= 0");
   if (dt_next_dev && !(cfl > 0 && std::isfinite(cfl))) return einval("dg_stage2: cfl must be > 0");
-  hipStream_t s = (hipStream_t)stream;
-  dg_status st = dispatch(m, kStage2, V1, U, Un, dt_dev, dt, s);
-  if (st != DG_OK || !dt_next_dev) return st;
-  hipError_t e = launch_min_finalize(m->dtpart, stage_waves(m), cfl, dt_next_dev, s);
-  if (e != hipSuccess) return hip_fail(e, "dg_stage2: CFL reduction");
-  return DG_OK;
+  return dispatch(m, kStage2, V1, U, Un, dt_dev, dt, (hipStream_t)stream, cfl, dt_next_dev);
 }
 
 dg_status dg_step_devdt(dg_mesh_t m, const void* U, void* Un, const double* dt_dev,
@@ -288,6 +282,29 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
     e = launch_cart3d_cfl(m, U, cfl, dt_dev, s);
   if (e != hipSuccess) return hip_fail(e, "dg_cfl_dt launch");
   return DG_OK;
+}
+
+dg_status dg_set_tiling(dg_mesh_t m, int rows) {
+  if (!m) return einval("dg_set_tiling: NULL handle");
+  if (rows < 0) return einval("dg_set_tiling: rows must be >= 0");
+  if (m->kind != 0) return DG_OK;
+  if (m->dim == 2) {
+    int r = rows ? std::min(rows, m->c2.ny) : default_rows(m->c2.tiles_x, m->c2.ny);
+    m->c2.rows_per_tile = r;
+    m->c2.tiles_y = (m->c2.ny + r - 1) / r;
+  } else {
+    int r = rows ? std::min(rows, m->c3.nz)
+                 : default_rows((int64_t)m->c3.tiles_x * m->c3.tiles_y, m->c3.nz);
+    m->c3.planes_per_tile = r;
+    m->c3.tiles_z = (m->c3.nz + r - 1) / r;
+  }
+  return DG_OK;
+}
+
+int dg_get_tiling(dg_mesh_t m) {
+  if (!m) return -1;
+  if (m->kind != 0) return 0;
+  return m->dim == 2 ? m->c2.rows_per_tile : m->c3.planes_per_tile;
 }
 
 dg_status dg_check(dg_mesh_t m) {

@@ -84,9 +84,11 @@ void set_error(const std::string& msg);
 dg_status hip_fail(hipError_t e, const char* what);
 
 // Launchers (return hipSuccess or the launch error).
-// Step size: *dt_dev when dt_dev is not NULL, else dt_host.
+// Step size: *dt_dev when dt_dev is not NULL, else dt_host.  Stage 2 with
+// dt_next != NULL also writes *dt_next = cfl * min CFL bound of its output.
 hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
-                         const double* dt_dev, double dt_host, hipStream_t s);
+                         const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                         hipStream_t s);
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
 

@@ -1,0 +1,67 @@
+// Device arithmetic helpers shared by the stage kernels (gfx950).
+//
+// Reciprocal and square root.  The kernels need 1/rho, 1/(S_R - S_L), the
+// limiter ratio and sound speeds at every quadrature point; IEEE-exact FP64
+// division and sqrt expand to long scaled sequences.  Inputs here are positive
+// and far from the denormal range (rho, p > 0 are checked separately), so the
+// hardware estimates refined by Newton-Raphson (reciprocal) and Goldschmidt
+// (square root) iterations give results within an ulp or two, which the parity
+// tolerances absorb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dg {
+
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+// sqrt(x) for x > 0: Goldschmidt iterations on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+// seeded by the hardware reciprocal square root, then one residual correction.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+__device__ __forceinline__ float sqrt_pos(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  float g = x * y, h = 0.5f * y;
+  float d = fmaf(-g, g, x);
+  return fmaf(d, h, g);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip; remap the
+// block index so each XCD receives a contiguous range of tiles (neighbouring
+// tiles, and the halo rows they share, then hit the same L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  int per = nb >> 3;
+  if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+  return b;
+}
+
+// Wave-wide minimum of a double (lanes exchange through DPP/permute).
+__device__ __forceinline__ double wave_min(double d) {
+  for (int o = 32; o > 0; o >>= 1) d = fmin(d, __shfl_xor(d, o));
+  return d;
+}
+
+}  // namespace dg

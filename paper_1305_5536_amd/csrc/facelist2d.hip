@@ -10,7 +10,7 @@ dg_status facelist_create(dg_mesh*, const dg_mesh_desc*) {
 }
 void facelist_destroy(dg_mesh*) {}
 hipError_t launch_facelist(const dg_mesh*, int, const void*, const void*, void*, const double*,
-                           double, hipStream_t) {
+                           double, double, double*, hipStream_t) {
   return hipErrorNotSupported;
 }
 hipError_t launch_facelist_cfl(const dg_mesh*, const void*, double, double*, hipStream_t) {

@@ -163,6 +163,14 @@ class Solver:
                 "dg_cfl_dt")
         return out
 
+    @property
+    def tiling(self) -> int:
+        return C.lib().dg_get_tiling(self._h)
+
+    @tiling.setter
+    def tiling(self, rows: int) -> None:
+        C.check(C.lib().dg_set_tiling(self._h, int(rows)), "dg_set_tiling")
+
     def check(self) -> None:
         """Synchronise and raise NonPhysicalState if a kernel met one."""
         C.check(C.lib().dg_check(self._h), "dg_check")
