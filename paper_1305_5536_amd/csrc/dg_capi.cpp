@@ -157,7 +157,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c3.hx = (d->hi[0] - d->lo[0]) / d->n[0];
     m->c3.hy = (d->hi[1] - d->lo[1]) / d->n[1];
     m->c3.hz = (d->hi[2] - d->lo[2]) / d->n[2];
-    m->c3.tiles_x = (int)((d->n[0] + 59) / 60);
+    m->c3.tiles_x = (int)((d->n[0] + 61) / 62);
     m->c3.tiles_y = (int)d->n[1];
     m->c3.planes_per_tile = default_rows((int64_t)m->c3.tiles_x * d->n[1], d->n[2]);
     m->c3.tiles_z = (int)((d->n[2] + m->c3.planes_per_tile - 1) / m->c3.planes_per_tile);
@@ -173,6 +173,8 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   }
   const size_t bytes = (size_t)m->ncoef * (size_t)m->ncells * m->elem;
   hipError_t e = hipMalloc(&m->v1, bytes);
+  if (e == hipSuccess && m->dim == 3) e = hipMalloc(&m->ws_a, bytes);
+  if (e == hipSuccess && m->dim == 3) e = hipMalloc(&m->ws_b, bytes);
   if (e == hipSuccess) e = hipMalloc(&m->status, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
@@ -197,6 +199,8 @@ void dg_mesh_destroy(dg_mesh_t m) {
   if (m->kind == 1) facelist_destroy(m);
   (void)hipFree(m->v1);
   (void)hipFree(m->tmp);
+  (void)hipFree(m->ws_a);
+  (void)hipFree(m->ws_b);
   (void)hipFree(m->status);
   (void)hipFree(m->dtpart);
   delete m;
@@ -230,7 +234,10 @@ static dg_status step_impl(dg_mesh_t m, const void* U, void* Un, const double* d
   }
   dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, dt_dev, dt_host, s);
   if (st != DG_OK) return st;
+  // 3D keeps Pi(U) of stage 1 in its workspace for the stage-2 combination
+  m->ws_a_fresh = true;
   st = dispatch(m, kStage2, m->v1, U, target, dt_dev, dt_host, s);
+  m->ws_a_fresh = false;
   if (st != DG_OK) return st;
   if (target != Un) {
     hipError_t e = hipMemcpyAsync(Un, target, (size_t)m->ncoef * m->ncells * m->elem,

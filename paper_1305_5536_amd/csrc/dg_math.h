@@ -49,6 +49,12 @@ __device__ __forceinline__ float sqrt_pos(float x) {
   return fmaf(d, h, g);
 }
 
+// sqrt of a value that may be exactly zero.
+template <typename T>
+__device__ __forceinline__ T sqrt_nn(T x) {
+  return x > T(0) ? sqrt_pos(x) : T(0);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip; remap the
 // block index so each XCD receives a contiguous range of tiles (neighbouring
 // tiles, and the halo rows they share, then hit the same L2).

@@ -28,17 +28,22 @@ def _solver(n, lo, hi, gamma, limiter=True, precision="fp64"):
     return Solver(cartesian(n, lo, hi), precision=precision, limiter=limiter, gamma=gamma)
 
 
-def field_errors(A, B, n, lo, hi, nvar=4):
+def field_errors(A, B, n, lo, hi, nvar=4, U=None):
     """Per-field relative error of A against the reference B (means and h-scaled
-    gradients, normalised by the largest mean of the field)."""
+    gradients, normalised by the largest mean of the field).  With U given the
+    arguments are right-hand sides L(U), whose natural size is |U| c / h
+    (c ~ 1 here), and that is the scale."""
     dim = len(n)
     h = min((hi[d] - lo[d]) / n[d] for d in range(dim))
     A = A.reshape(nvar * (1 + dim), -1)
     B = B.reshape(nvar * (1 + dim), -1)
+    Us = None if U is None else U.reshape(nvar * (1 + dim), -1)
     errs = []
     for v in range(nvar):
         k = v * (1 + dim)
         scale = max(np.abs(B[k]).max(), 1e-300)
+        if Us is not None:
+            scale = max(scale, np.abs(Us[k]).max() / h)
         d = np.abs(A[k] - B[k]).max()
         for c in range(1, 1 + dim):
             d = max(d, h * np.abs(A[k + c] - B[k + c]).max())
@@ -63,8 +68,8 @@ def test_rhs_matches_oracle(oracle, torch_cuda, n):
     ref = oracle.rhs(oracle.Mesh.cartesian(n, lo, hi), U0, G14)
     # The gradient equations subtract O(|F|) surface and volume sums that are
     # then scaled by 12/(V h^2): compare gradients in the h-scaled norm.
-    errs = field_errors(got, ref, n, lo, hi)
-    assert errs.max() < 1e-12, (n, errs)
+    errs = field_errors(got, ref, n, lo, hi, U=U0)
+    assert errs.max() < 1e-13, (n, errs)
 
 
 @pytest.mark.parametrize("n", SHAPES)

@@ -1,0 +1,162 @@
+"""GPU parity of the 3D ideal-MHD Cartesian path (HLLD, divergence-free B basis)
+against the CPU oracle, through the C ABI.
+
+Per-field error: max over cells of max(|d mean|, h |d gradient-like coefficient|)
+divided by the largest mean of the field (B fields use the B means and the
+a4..a11 coefficients).  Steps: 1e-13 (one) and 1e-11 (50); single L(U) calls:
+1e-13 of their natural scale |U| c / h.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G53 = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(n, lo, hi, limiter=True, precision="fp64"):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    return Solver(cartesian(n, lo, hi), physics="mhd", precision=precision, limiter=limiter,
+                  gamma=G53)
+
+
+FIELDS = {"rho": (0, [1, 2, 3]), "mx": (4, [5, 6, 7]), "my": (8, [9, 10, 11]),
+          "mz": (12, [13, 14, 15]), "E": (16, [17, 18, 19])}
+
+
+def field_errors(A, B, n, lo, hi, U=None):
+    """U given: the arguments are right-hand sides L(U), whose natural size is
+    |U| c / h (c ~ 1 here); errors are measured against that scale."""
+    h = min((hi[d] - lo[d]) / n[d] for d in range(3))
+    A = A.reshape(31, -1)
+    B = B.reshape(31, -1)
+    Us = None if U is None else U.reshape(31, -1)
+    out = {}
+    for name, (k, gs) in FIELDS.items():
+        scale = max(np.abs(B[k]).max(), 1e-300)
+        if Us is not None:
+            scale = max(scale, np.abs(Us[k]).max() / h)
+        d = np.abs(A[k] - B[k]).max()
+        for g in gs:
+            d = max(d, h * np.abs(A[g] - B[g]).max())
+        out[name] = d / scale
+    bscale = max(np.abs(B[20:23]).max(), 1e-300)
+    if Us is not None:
+        bscale = max(bscale, np.abs(Us[20:23]).max() / h)
+    d = np.abs(A[20:23] - B[20:23]).max()
+    d = max(d, h * np.abs(A[23:31] - B[23:31]).max())
+    out["B"] = d / bscale
+    return out
+
+
+SHAPES = [(8, 6, 5), (70, 3, 4), (1, 2, 3), (5, 1, 1), (130, 2, 2)]
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_rhs_matches_oracle(oracle, torch_cuda, n):
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 0.8, 1.2)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=sum(n), amp=0.2, mhd=True)
+    s = _solver(n, lo, hi, limiter=False)
+    got = s.rhs(s.to_device(U0)).cpu().numpy()
+    s.check()
+    ref = oracle.rhs(oracle.Mesh.cartesian(n, lo, hi), U0, G53, mhd=True)
+    errs = field_errors(got, ref, n, lo, hi, U=U0)
+    assert max(errs.values()) < 1e-13, errs
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_limit_matches_oracle(oracle, torch_cuda, n):
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=3, amp=0.3, mhd=True).reshape(31, -1)
+    U0[[1, 2, 3, 5, 9, 14, 18]] *= 3.0  # steep gradients: limiter active
+    U0[23:31] *= -2.5
+    U0 = U0.reshape(-1)
+    s = _solver(n, lo, hi)
+    got = s.limit(s.to_device(U0)).cpu().numpy()
+    ref = oracle.limit(oracle.Mesh.cartesian(n, lo, hi), U0, mhd=True)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # B keeps a zero cell divergence after limiting: the trace of grad B is
+    # a10 + a11 - a10 - a11 = 0 by construction, so only check the means
+    assert np.array_equal(got.reshape(31, -1)[[0, 4, 8, 12, 16, 20, 21, 22]],
+                          U0.reshape(31, -1)[[0, 4, 8, 12, 16, 20, 21, 22]])
+
+
+@pytest.mark.parametrize("limiter", [False, True])
+@pytest.mark.parametrize("n", [(8, 6, 5), (70, 3, 4)])
+def test_step_matches_oracle(oracle, torch_cuda, n, limiter):
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=4, amp=0.25, mhd=True)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    dt = oracle.cfl_dt(om, U0, G53, 0.3, mhd=True)
+    ref = oracle.step(om, U0, dt, G53, limiter, mhd=True)
+    s = _solver(n, lo, hi, limiter=limiter)
+    U = s.to_device(U0)
+    got = s.step(U, dt).cpu().numpy()
+    s.check()
+    errs = field_errors(got, ref, n, lo, hi)
+    assert max(errs.values()) < 1e-13, errs
+    # the stage-split path gives the same result
+    V1 = s.empty()
+    out = s.empty()
+    s.stage1(U, dt, V1)
+    s.stage2(U, V1, dt, out)
+    assert torch_cuda.equal(out, s.step(U, dt))
+
+
+def test_cfl_matches_oracle(oracle, torch_cuda):
+    n, lo, hi = (9, 7, 5), (0.0, 0.0, 0.0), (1.0, 0.5, 2.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=5, amp=0.3, mhd=True)
+    s = _solver(n, lo, hi)
+    dt = s.cfl_dt(s.to_device(U0), 0.3).item()
+    ref = oracle.cfl_dt(oracle.Mesh.cartesian(n, lo, hi), U0, G53, 0.3, mhd=True)
+    assert abs(dt - ref) <= 1e-14 * ref
+
+
+def test_c3_recipe_50_steps_small(oracle, torch_cuda):
+    """The C3 turbulence recipe (16 velocity and 16 potential modes, limiter on)
+    at 16^3: 50 steps on the oracle's dt schedule agree to 1e-11 per field;
+    the FP32 error is stated per field."""
+    n, lo, hi = (16, 16, 16), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    U0 = W.c3_state(16)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    ref, dts = oracle.run(om, U0, 50, G53, 0.3, True, mhd=True)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-3)):
+        s = _solver(n, lo, hi, precision=prec)
+        U = s.to_device(U0)
+        V = s.empty()
+        for dt in dts:
+            s.step(U, dt, out=V)
+            U, V = V, U
+        s.check()
+        errs = field_errors(U.double().cpu().numpy(), ref, n, lo, hi)
+        print(f"C3(16^3) {prec} per-field error after 50 steps:", errs)
+        assert max(errs.values()) < tol, (prec, errs)
+
+
+def test_stage2_cfl_and_determinism(oracle, torch_cuda):
+    n, lo, hi = (20, 6, 7), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=6, amp=0.2, mhd=True)
+    s = _solver(n, lo, hi)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    V1 = s.empty()
+    a = s.empty()
+    dt_next = torch_cuda.empty(1, dtype=torch_cuda.float64, device="cuda")
+    s.stage1(U, dt, V1)
+    s.stage2(U, V1, dt, a, cfl=0.3, dt_next=dt_next)
+    assert dt_next.item() == s.cfl_dt(a, 0.3).item()
+    b = s.step(U, dt)
+    assert torch_cuda.equal(a, b)
+    for rows in (1, 3, 7):
+        s.tiling = rows
+        assert torch_cuda.equal(s.step(U, dt), b)

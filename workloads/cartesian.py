@@ -179,9 +179,10 @@ def _modes(rng, nmodes, kmax, dim, norm="inf"):
     return np.array(ks)
 
 
-def random_p1_state(n, lo, hi, gamma, seed, amp=0.1, nmodes=4, kmax=3, mhd=False, bamp=0.3):
+def random_p1_state(n, lo, hi, gamma, seed, amp=0.1, nmodes=4, kmax=3, mhd=False, bamp=0.03):
     """Smooth random state: rho = 1 + amp * sum of random modes, v likewise, p = 1
-    (+ amp modes); MHD adds B = B0 + curl of a random vector potential."""
+    (+ amp modes); MHD adds B = B0 + curl of a random vector potential of
+    amplitude ``bamp`` (|B| stays O(2 pi kmax bamp)), B0 ~ U(-0.5, 0.5)*10 bamp."""
     rng = np.random.default_rng(seed)
     dim = len(n)
     L = np.array([hi[d] - lo[d] for d in range(dim)])
@@ -195,7 +196,7 @@ def random_p1_state(n, lo, hi, gamma, seed, amp=0.1, nmodes=4, kmax=3, mhd=False
     sr, sp = series(nmodes), series(nmodes)
     sv = [series(nmodes) for _ in range(3 if mhd else dim)]
     sa = [series(nmodes) for _ in range(3)] if mhd else None
-    b0 = rng.uniform(-0.5, 0.5, 3) * bamp if mhd else None
+    b0 = rng.uniform(-0.5, 0.5, 3) * 10 * bamp if mhd else None
 
     def ev(X, s):
         k, a, ph = s
@@ -228,11 +229,7 @@ def random_p1_state(n, lo, hi, gamma, seed, amp=0.1, nmodes=4, kmax=3, mhd=False
 
 
 # ---------------------------------------------------------------- MHD turbulence
-def c3_state(n=256, seed=1003, gamma=5.0 / 3.0, nq=3):
-    """3D MHD on [0,1]^3: rho = 1, p = 1; v = sum_{m=1..16} a_m sin(2 pi k_m.x +
-    phi_m) with integer k_m, 1 <= |k_m| <= 4, a_m ~ N(0, I3), rescaled to an rms
-    |v| of 0.5; A from 16 modes drawn the same way, B = curl A, rescaled to an
-    rms |B| of 0.3 (rms over cell centres)."""
+def _c3_modes(seed):
     rng = np.random.default_rng(seed)
     kv = _modes(rng, 16, 4, 3, norm="l2")
     av = rng.normal(size=(16, 3))
@@ -240,44 +237,95 @@ def c3_state(n=256, seed=1003, gamma=5.0 / 3.0, nq=3):
     kA = _modes(rng, 16, 4, 3, norm="l2")
     aA = rng.normal(size=(16, 3))
     pA = rng.uniform(0, 2 * math.pi, 16)
-    two_pi = 2 * math.pi
+    # B = curl A: mode m contributes 2 pi cos(theta) (k_m x a_m)
+    qB = np.array([np.cross(2 * math.pi * kA[m], aA[m]) for m in range(16)])
+    # rms rescaling from cell centres of a 16^3 grid (distinct integer modes
+    # with |k| <= 4 are orthogonal on it)
+    g = (np.arange(16) + 0.5) / 16
+    S = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    vs = (av.T @ np.sin(2 * math.pi * kv @ S + pv[:, None]))
+    bs = (qB.T @ np.cos(2 * math.pi * kA @ S + pA[:, None]))
+    sv = 0.5 / math.sqrt(np.mean(np.sum(vs * vs, axis=0)))
+    sb = 0.3 / math.sqrt(np.mean(np.sum(bs * bs, axis=0)))
+    return kv, av * sv, pv, kA, qB * sb, pA
 
-    def vfield(X):
-        out = [0.0 * X[0] for _ in range(3)]
+
+def c3_state(n=256, seed=1003, gamma=5.0 / 3.0, nq=None):
+    """3D MHD on [0,1]^3: rho = 1, p = 1; v = sum_{m=1..16} a_m sin(2 pi k_m.x +
+    phi_m) with integer k_m, 1 <= |k_m| <= 4, a_m ~ N(0, I3), rescaled to an rms
+    |v| of 0.5; A from 16 modes drawn the same way, B = curl A, rescaled to an
+    rms |B| of 0.3 (rms over cell centres).  P1 projection with an nq^3 Gauss
+    rule per cell (nq = 3, or 2 from 128^3 up); each mode's phase at the cell
+    centre is computed once and shifted to the quadrature points with the sum
+    formulas (torch CPU tensors, float64)."""
+    import torch
+    nq = nq or (3 if n < 128 else 2)
+    kv, av, pv, kA, qB, pA = _c3_modes(seed)
+    h = 1.0 / n
+    xs, ws = _gauss(nq)
+    c = (torch.arange(n, dtype=torch.float64) + 0.5) * h
+    nc = n ** 3
+    # cell centres, x fastest
+    Z, Y, X = torch.meshgrid(c, c, c, indexing="ij")
+    X, Y, Z = X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
+    tp = 2 * math.pi
+
+    def phases(k, ph):
+        out = []
         for m in range(16):
-            s = np.sin(two_pi * (kv[m][0] * X[0] + kv[m][1] * X[1] + kv[m][2] * X[2]) + pv[m])
-            for c in range(3):
-                out[c] = out[c] + av[m][c] * s
+            th = tp * (float(k[m][0]) * X + float(k[m][1]) * Y + float(k[m][2]) * Z) + float(ph[m])
+            out.append((torch.sin(th), torch.cos(th)))
         return out
 
-    def bfield(X):
-        out = [0.0 * X[0] for _ in range(3)]
+    Pv = phases(kv, pv)
+    PA = phases(kA, pA)
+    del X, Y, Z
+    U = torch.zeros((31, nc), dtype=torch.float64)
+    second = 0.0
+    gram = np.zeros((8, 8))
+    gv = [[1, 2, 3], [5, 6, 7], [9, 10, 11], [13, 14, 15], [17, 18, 19]]
+    for idx in np.ndindex(nq, nq, nq):
+        r = [xs[idx[d]] * h for d in range(3)]
+        w = float(ws[idx[0]] * ws[idx[1]] * ws[idx[2]])
+        vel = [torch.zeros(nc, dtype=torch.float64) for _ in range(3)]
+        B = [torch.zeros(nc, dtype=torch.float64) for _ in range(3)]
         for m in range(16):
-            cth = np.cos(two_pi * (kA[m][0] * X[0] + kA[m][1] * X[1] + kA[m][2] * X[2]) + pA[m])
-            q = np.cross(two_pi * kA[m], aA[m])
-            for c in range(3):
-                out[c] = out[c] + q[c] * cth
-        return out
-
-    # rms rescaling from a coarse sample of cell centres (distinct integer modes
-    # are orthogonal on the grid, so any grid of >= 9 points per axis is exact).
-    ns = 16
-    g = (np.arange(ns) + 0.5) / ns
-    S = np.meshgrid(g, g, g, indexing="ij")
-    S = [s.reshape(-1) for s in S]
-    vs = vfield(S)
-    bs = bfield(S)
-    sv = 0.5 / math.sqrt(np.mean(sum(v * v for v in vs)))
-    sb = 0.3 / math.sqrt(np.mean(sum(b * b for b in bs)))
-
-    def f(X, Y, Z):
-        Xs = (X, Y, Z)
-        vel = [sv * v for v in vfield(Xs)]
-        B = [sb * b for b in bfield(Xs)]
-        one = 1.0 + 0.0 * X
-        return _mhd_conserved(one, vel, one, B, gamma)
-
-    return project_cartesian(f, (n, n, n), (0.0,) * 3, (1.0,) * 3, nq=nq, mhd=True)
+            dv = tp * float(kv[m] @ r)
+            s_ = Pv[m][0] * math.cos(dv) + Pv[m][1] * math.sin(dv)
+            for cc in range(3):
+                vel[cc].add_(s_, alpha=float(av[m][cc]))
+            dA = tp * float(kA[m] @ r)
+            c_ = PA[m][1] * math.cos(dA) - PA[m][0] * math.sin(dA)
+            for cc in range(3):
+                B[cc].add_(c_, alpha=float(qB[m][cc]))
+        rho = 1.0
+        E = 1.0 / (gamma - 1.0) + 0.5 * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2) + \
+            0.5 * (B[0] ** 2 + B[1] ** 2 + B[2] ** 2)
+        cons = [None, vel[0], vel[1], vel[2], E]
+        U[0] += w * rho
+        for v in range(1, 5):
+            U[4 * v].add_(cons[v], alpha=w)
+            for d in range(3):
+                U[gv[v][d]].add_(cons[v], alpha=w * r[d])
+        for cc in range(3):
+            U[20 + cc].add_(B[cc], alpha=w)
+        basis = _vb([np.array(r[0]), np.array(r[1]), np.array(r[2])])
+        for j in range(8):
+            for cc in range(3):
+                coef = float(basis[j][cc])
+                if coef != 0.0:
+                    U[23 + j].add_(B[cc], alpha=w * coef)
+            for i in range(8):
+                gram[i, j] += w * sum(float(basis[i][cc]) * float(basis[j][cc]) for cc in range(3))
+        second += w * r[0] ** 2
+    # gradients: first moments over second moments (same on every axis here);
+    # rho is uniform so its gradient stays zero
+    for v in range(1, 5):
+        for d in range(3):
+            U[gv[v][d]] /= second
+    ginv = torch.as_tensor(np.linalg.inv(gram))
+    U[23:31] = ginv @ U[23:31]
+    return U.reshape(-1).numpy()
 
 
 # -------------------------------------------------------------- paper's tests
