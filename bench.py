@@ -28,32 +28,45 @@ if ROOT not in sys.path:
 
 METRIC = "DG cell-updates/s (cells×RK stages) & %HBM roofline; fwd+adjoint/fwd time ratio"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+FP32_VALU_PEAK_TFLOPS = 157.3
 # Algorithmic bytes per cell for each stage kernel of 2D Euler (12 coefficients):
 # stage 1 reads U and writes V1 (24 values); stage 2 reads V1 and U and writes
 # U_next (36 values).  Limiter and CFL minima add no algorithmic traffic.
 STAGE_VALUES = {1: 24, 2: 36}
+# Algorithmic FP64/FP32 flops of one 3D MHD cell-stage (12 HLLD solves at 2x2
+# Gauss points of 3 faces, 8 volume points, accumulation, inverse mass matrix
+# and the RK combination; counted from the kernel's formulation).
+MHD_FLOPS_PER_CELL_STAGE = 8700
 
 
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--n", type=int, default=2048, help="cells per side")
+    p.add_argument("--config", choices=["c2", "c3"], default="c2",
+                   help="c2: 2D Euler shear layer 2048^2 (default); c3: 3D MHD 256^3")
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=None)
+    p.add_argument("--n", type=int, default=None, help="cells per side")
     p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--also-fp32", action="store_true", default=True)
     p.add_argument("--no-fp32", dest="also_fp32", action="store_false")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=2)
-    return p.parse_args()
+    p.add_argument("--cpu-steps", type=int, default=None)
+    a = p.parse_args()
+    dflt = {"c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 2)}[a.config]
+    a.n = a.n or dflt[0]
+    a.steps = a.steps if a.steps is not None else dflt[1]
+    a.warmup = a.warmup if a.warmup is not None else dflt[2]
+    a.cpu_steps = a.cpu_steps or dflt[3]
+    return a
 
 
-def run_gpu(U0, n, precision, steps, warmup, cfl=0.3):
+def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3):
     import torch
 
-    from paper_1305_5536_amd.solver import Solver, cartesian
-    s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), precision=precision, limiter=True,
-               gamma=5.0 / 3.0)
+    from paper_1305_5536_amd.solver import Solver
+    s = Solver(mesh, physics=physics, precision=precision, limiter=True, gamma=gamma)
     U = s.to_device(U0)
     V1 = s.empty()
     Un = s.empty()
@@ -85,19 +98,112 @@ def run_gpu(U0, n, precision, steps, warmup, cfl=0.3):
     return {"wall_s": wall, "event_s": tev, "stage1_s": t1, "stage2_s": t2, "dt_last": final_dt}
 
 
-def cpu_baseline(U0, n, nsteps):
+def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label=""):
     import oracle
-    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
-    dt = oracle.cfl_dt(om, U0, 5.0 / 3.0, 0.3)
+    om = oracle.Mesh.cartesian((n,) * dim, (0.0,) * dim, (1.0,) * dim)
+    dt = oracle.cfl_dt(om, U0, gamma, 0.3, mhd=mhd)
     t0 = time.perf_counter()
     U = U0
     for _ in range(nsteps):
-        U = oracle.step(om, U, dt, 5.0 / 3.0, True)
+        U = oracle.step(om, U, dt, gamma, True, mhd=mhd)
     el = time.perf_counter() - t0
-    return {"value": n * n * 2 * nsteps / el, "unit": "cell-updates/s",
+    return {"value": n ** dim * 2 * nsteps / el, "unit": "cell-updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nsteps} SSP-RK2 steps (limited) of the same {n}x{n} shear-layer state, "
-                      f"FP64, {el:.1f} s"}
+            "sample": f"{nsteps} limited SSP-RK2 steps of {label} at {'x'.join([str(n)] * dim)}, "
+                      f"FP64, {el:.1f} s of CPU time"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_c2(a):
+    import workloads as W
+    from paper_1305_5536_amd.solver import cartesian
+    n = a.n
+    log(f"generating the {n}x{n} shear-layer state")
+    U0 = W.c2_state(n)
+    log("timing the GPU steps")
+    elem = 8 if a.precision == "fp64" else 4
+    mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup)
+    ncells = n * n
+    value = ncells * 2 * a.steps / r["event_s"]
+    stage2_bytes = STAGE_VALUES[2] * elem * ncells
+    achieved = stage2_bytes / r["stage2_s"] / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
+                               "P1 Taylor DG, HLL, limiter on, SSP-RK2 CFL 0.3",
+                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cart2d stage 2 (+ dt reduction)",
+                     "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
+        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
+                    "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
+                       "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / r32["stage1_s"] / 1e9}
+    if not a.no_cpu:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state")
+    return out
+
+
+def bench_c3(a):
+    import workloads as W
+    from paper_1305_5536_amd.solver import cartesian
+    n = a.n
+    t0 = time.perf_counter()
+    log(f"generating the {n}^3 MHD turbulence state")
+    U0 = W.c3_state(n)
+    tgen = time.perf_counter() - t0
+    log(f"generated in {tgen:.0f} s; timing the GPU steps")
+    mesh = cartesian((n, n, n), (0.0,) * 3, (1.0,) * 3)
+    r = run_gpu(U0, mesh, "mhd", 5.0 / 3.0, a.precision, a.steps, a.warmup)
+    ncells = n ** 3
+    value = ncells * 2 * a.steps / r["event_s"]
+    peak = FP64_VALU_PEAK_TFLOPS if a.precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+    # stage 1 = limiter pass + RHS kernel; report the whole stage against the
+    # VALU peak (the RHS kernel dominates it; rocprof splits the two)
+    achieved = MHD_FLOPS_PER_CELL_STAGE * ncells / r["stage1_s"] / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"3D ideal MHD turbulence, periodic Cartesian {n}^3, gamma 5/3, "
+                               "P1 Taylor + divergence-free B basis, HLLD, limiter on, SSP-RK2",
+                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU",
+                   "input_generation_s": tgen},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "stage 1 (k_lim3d + k_rhs3d)",
+                     "flops_per_launch": MHD_FLOPS_PER_CELL_STAGE * ncells,
+                     "avg_launch_s": r["stage1_s"]},
+        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu(U0, mesh, "mhd", 5.0 / 3.0, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "stage1_TFLOPs": MHD_FLOPS_PER_CELL_STAGE * ncells / r32["stage1_s"] / 1e12}
+    if not a.no_cpu:
+        log("timing the CPU oracle")
+        ns = 48
+        out["cpu_baseline"] = cpu_baseline(W.c3_state(ns), ns, a.cpu_steps, dim=3, mhd=True,
+                                           label="the same MHD-turbulence recipe")
+    return out
 
 
 def main():
@@ -106,48 +212,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
-    import workloads as W
-    n = a.n
-    U0 = W.c2_state(n)
-    elem = 8 if a.precision == "fp64" else 4
-    r = run_gpu(U0, n, a.precision, a.steps, a.warmup)
-    ncells = n * n
-    value = ncells * 2 * a.steps / r["event_s"]
-    stage2_bytes = STAGE_VALUES[2] * elem * ncells
-    achieved = stage2_bytes / r["stage2_s"] / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": r["event_s"] / a.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32",
-        "data": "synthetic",
-        "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
-                               "P1 Taylor DG, HLL, limiter on, SSP-RK2 CFL 0.3",
-                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cart2d stage 2 (+ dt reduction)",
-                     "bytes_per_launch": stage2_bytes,
-                     "avg_launch_s": r["stage2_s"]},
-        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
-                    "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9},
-        "wall_s": r["wall_s"],
-    }
-    if a.also_fp32 and a.precision == "fp64":
-        r32 = run_gpu(U0, n, "fp32", a.steps, a.warmup)
-        out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
-                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
-                       "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
-                       "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / r32["stage1_s"] / 1e9}
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps)
+    out = bench_c2(a) if a.config == "c2" else bench_c3(a)
     print(json.dumps(out))
 
 

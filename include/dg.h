@@ -146,7 +146,11 @@ dg_status dg_step(dg_mesh_t mesh, const void* U, void* U_next, double dt, void* 
  *   *dt_next_dev = cfl * min_e (CFL bound of U_next's cell means)
  * (the formula of dg_cfl_dt), from per-wave minima taken inside the stage
  * kernel plus one single-workgroup reduction; it may equal dt_dev.
- * V1 must not alias U; U_next must alias neither U nor V1. */
+ * V1 must not alias U; U_next must alias neither U nor V1.
+ * On 3D MHD meshes the limiter runs as its own pass: dg_stage1 keeps Pi(U) in
+ * the handle's workspace, and a dg_stage2 that immediately follows it on the
+ * same handle with the same U pointer reuses that copy (U must not be
+ * modified in between); any other dg_stage2 limits U again. */
 dg_status dg_stage1(dg_mesh_t mesh, const void* U, void* V1, double dt, const double* dt_dev,
                     void* stream);
 dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next, double dt,

@@ -176,27 +176,32 @@ __global__ __launch_bounds__(256) void k_lim3d(P3<T> p) {
 // States in the lab frame, conserved order rho, mx, my, mz, E, Bx, By, Bz;
 // both carry the same normal field B[D].  Returns the lab-frame flux along
 // +e_D (its B[D] component is zero).
+//
+// Miyoshi & Kusano's fan has outer waves S_L < S_R, Alfven waves S*_L, S*_R
+// and the contact S_M.  The interface lies on the left of the contact exactly
+// when S_M >= 0 (S_L >= 0 implies S_M > 0, S_R <= 0 implies S_M < 0), so the
+// flux is built from one side a only:
+//   F = F_a                                         (outside the fan)
+//     = F_a + S_a (U*_a - U_a)                      (between S_a and S*_a)
+//     = F_a + S_a (U*_a - U_a) + S*_a (U**_a - U*_a)  (between S*_a and S_M)
+// with S_M, p*_T and the double-star states taken from both sides.
 template <typename T, int D>
 __device__ __forceinline__ void hlld(const T* uL, const T* uR, const P3<T>& p, T* F, bool& bad) {
   constexpr int n = D, t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   const T g = p.gamma, gm1 = p.gamma - T(1);
   const T Bn = uL[5 + n];
   const T Bn2 = Bn * Bn;
-  // face-frame primitive variables and fluxes, components
-  // (rho, m_n, m_t1, m_t2, E, B_t1, B_t2)
-  T r[2], u[2], v[2], w[2], pT[2], E[2], b1[2], b2[2], cf[2], Uf[2][7], Ff[2][7];
+  // face-frame primitive variables: normal velocity u, tangential v, w,
+  // tangential field b1, b2, total pressure pT, fast speed cf
+  T u[2], v[2], w[2], pT[2], cf[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const T* q = s == 0 ? uL : uR;
-    r[s] = q[0];
     T ir = rcp(q[0]);
     u[s] = q[1 + n] * ir;
     v[s] = q[1 + t1] * ir;
     w[s] = q[1 + t2] * ir;
-    b1[s] = q[5 + t1];
-    b2[s] = q[5 + t2];
-    E[s] = q[4];
-    T pm = T(0.5) * (Bn2 + b1[s] * b1[s] + b2[s] * b2[s]);
+    T pm = T(0.5) * (Bn2 + q[5 + t1] * q[5 + t1] + q[5 + t2] * q[5 + t2]);
     T pg = gm1 * (q[4] - T(0.5) * (q[1 + n] * u[s] + q[1 + t1] * v[s] + q[1 + t2] * w[s]) - pm);
     bad |= !(q[0] > T(0)) || !(pg > T(0));
     pT[s] = pg + pm;
@@ -204,93 +209,72 @@ __device__ __forceinline__ void hlld(const T* uL, const T* uR, const P3<T>& p, T
     T sb = a2 + T(2) * pm * ir;
     T disc = fmax(sb * sb - T(4) * a2 * Bn2 * ir, T(0));
     cf[s] = sqrt_pos(T(0.5) * (sb + sqrt_nn(disc)));
-    T vB = u[s] * Bn + v[s] * b1[s] + w[s] * b2[s];
-    T mu = q[1 + n];
-    Uf[s][0] = q[0];
-    Uf[s][1] = q[1 + n];
-    Uf[s][2] = q[1 + t1];
-    Uf[s][3] = q[1 + t2];
-    Uf[s][4] = q[4];
-    Uf[s][5] = b1[s];
-    Uf[s][6] = b2[s];
-    Ff[s][0] = mu;
-    Ff[s][1] = mu * u[s] + pT[s] - Bn2;
-    Ff[s][2] = mu * v[s] - Bn * b1[s];
-    Ff[s][3] = mu * w[s] - Bn * b2[s];
-    Ff[s][4] = (q[4] + pT[s]) * u[s] - Bn * vB;
-    Ff[s][5] = b1[s] * u[s] - v[s] * Bn;
-    Ff[s][6] = b2[s] * u[s] - w[s] * Bn;
   }
   const T cmax = fmax(cf[0], cf[1]);
   const T SL = fmin(u[0], u[1]) - cmax;
   const T SR = fmax(u[0], u[1]) + cmax;
-  const T S[2] = {SL, SR};
-  const T dL = (SL - u[0]) * r[0], dR = (SR - u[1]) * r[1];
+  const T dL = (SL - u[0]) * uL[0], dR = (SR - u[1]) * uR[0];  // rho (S - u)
   const T idn = rcp(dR - dL);
   const T SM = (dR * u[1] - dL * u[0] - pT[1] + pT[0]) * idn;
   const T pTs = (dR * pT[0] - dL * pT[1] + dL * dR * (u[1] - u[0])) * idn;
-  T rs[2], vs[2], ws[2], b1s[2], b2s[2], Es[2], vBs[2], sq[2], Us[2][7], Fs[2][7];
+  // single-star tangential states of both sides (needed by the double star)
+  T rs[2], vs[2], ws[2], b1s[2], b2s[2], sq[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const T dS = s == 0 ? dL : dR;  // rho (S - u)
-    const T Su = S[s] - u[s];
-    const T iSM = rcp(S[s] - SM);
-    rs[s] = dS * iSM;
-    const T den = dS * (S[s] - SM) - Bn2;
+    const T* q = s == 0 ? uL : uR;
+    const T S = s == 0 ? SL : SR;
+    const T dS = s == 0 ? dL : dR;
+    const T Su = S - u[s];
+    rs[s] = dS * rcp(S - SM);
+    const T den = dS * (S - SM) - Bn2;
     const T scale = dS * Su + Bn2;
     const bool deg = fabs(den) <= p.eps * scale;
     const T iden = deg ? T(0) : rcp(den);
     const T fv = deg ? T(0) : Bn * (SM - u[s]) * iden;
     const T fb = deg ? T(1) : (dS * Su - Bn2) * iden;
-    vs[s] = v[s] - b1[s] * fv;
-    ws[s] = w[s] - b2[s] * fv;
-    b1s[s] = b1[s] * fb;
-    b2s[s] = b2[s] * fb;
-    const T vB = u[s] * Bn + v[s] * b1[s] + w[s] * b2[s];
-    vBs[s] = SM * Bn + vs[s] * b1s[s] + ws[s] * b2s[s];
-    Es[s] = (Su * E[s] - pT[s] * u[s] + pTs * SM + Bn * (vB - vBs[s])) * iSM;
-    Us[s][0] = rs[s];
-    Us[s][1] = rs[s] * SM;
-    Us[s][2] = rs[s] * vs[s];
-    Us[s][3] = rs[s] * ws[s];
-    Us[s][4] = Es[s];
-    Us[s][5] = b1s[s];
-    Us[s][6] = b2s[s];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) Fs[s][k] = fma(S[s], Us[s][k] - Uf[s][k], Ff[s][k]);
+    vs[s] = v[s] - q[5 + t1] * fv;
+    ws[s] = w[s] - q[5 + t2] * fv;
+    b1s[s] = q[5 + t1] * fb;
+    b2s[s] = q[5 + t2] * fb;
     sq[s] = sqrt_pos(rs[s]);
   }
-  const T aBn = fabs(Bn);
-  const T SsL = SM - aBn * rcp(sq[0]);
-  const T SsR = SM + aBn * rcp(sq[1]);
   const T sgn = Bn < T(0) ? T(-1) : T(1);
   const T isum = rcp(sq[0] + sq[1]);
   const T vss = (sq[0] * vs[0] + sq[1] * vs[1] + (b1s[1] - b1s[0]) * sgn) * isum;
   const T wss = (sq[0] * ws[0] + sq[1] * ws[1] + (b2s[1] - b2s[0]) * sgn) * isum;
   const T b1ss = (sq[0] * b1s[1] + sq[1] * b1s[0] + sq[0] * sq[1] * (vs[1] - vs[0]) * sgn) * isum;
   const T b2ss = (sq[0] * b2s[1] + sq[1] * b2s[0] + sq[0] * sq[1] * (ws[1] - ws[0]) * sgn) * isum;
-  const T vBss = SM * Bn + vss * b1ss + wss * b2ss;
+  // side a
   const bool lft = SM >= T(0);
-  const int a = lft ? 0 : 1;
-  const T ra = lft ? rs[0] : rs[1];
+  const T* q = lft ? uL : uR;
+  const T S = lft ? SL : SR;
+  const T ua = lft ? u[0] : u[1], va = lft ? v[0] : v[1], wa = lft ? w[0] : w[1];
+  const T pTa = lft ? pT[0] : pT[1];
+  const T rsa = lft ? rs[0] : rs[1], vsa = lft ? vs[0] : vs[1], wsa = lft ? ws[0] : ws[1];
+  const T b1sa = lft ? b1s[0] : b1s[1], b2sa = lft ? b2s[0] : b2s[1];
   const T sqa = lft ? sq[0] : sq[1];
-  const T Ea = lft ? Es[0] : Es[1];
-  const T vBa = lft ? vBs[0] : vBs[1];
-  const T Ess = lft ? Ea - sqa * (vBa - vBss) * sgn : Ea + sqa * (vBa - vBss) * sgn;
-  const T Sa = lft ? SsL : SsR;
-  T Uss[7] = {ra, ra * SM, ra * vss, ra * wss, Ess, b1ss, b2ss};
+  const T Ss = lft ? SM - fabs(Bn) * rcp(sqa) : SM + fabs(Bn) * rcp(sqa);
+  const bool outer = lft ? (SL >= T(0)) : (SR <= T(0));
+  const bool single = lft ? (Ss >= T(0)) : (Ss <= T(0));
+  const T b1 = q[5 + t1], b2 = q[5 + t2];
+  const T vB = ua * Bn + va * b1 + wa * b2;
+  const T vBs = SM * Bn + vsa * b1sa + wsa * b2sa;
+  const T Es = ((S - ua) * q[4] - pTa * ua + pTs * SM + Bn * (vB - vBs)) * rcp(S - SM);
+  const T vBss = SM * Bn + vss * b1ss + wss * b2ss;
+  const T Ess = lft ? Es - sqa * (vBs - vBss) * sgn : Es + sqa * (vBs - vBss) * sgn;
+  // outer flux and states of side a, components (rho, m_n, m_t1, m_t2, E, B_t1, B_t2)
+  const T mu = q[1 + n];
+  const T Fa[7] = {mu, mu * ua + pTa - Bn2, mu * va - Bn * b1, mu * wa - Bn * b2,
+                   (q[4] + pTa) * ua - Bn * vB, b1 * ua - va * Bn, b2 * ua - wa * Bn};
+  const T Ua[7] = {q[0], q[1 + n], q[1 + t1], q[1 + t2], q[4], b1, b2};
+  const T Us[7] = {rsa, rsa * SM, rsa * vsa, rsa * wsa, Es, b1sa, b2sa};
+  const T Uss[7] = {rsa, rsa * SM, rsa * vss, rsa * wss, Ess, b1ss, b2ss};
   T Fo[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    const T fsa = a == 0 ? Fs[0][k] : Fs[1][k];
-    const T usa = a == 0 ? Us[0][k] : Us[1][k];
-    const T fss = fma(Sa, Uss[k] - usa, fsa);
-    T f = fss;
-    f = SsR <= T(0) ? Fs[1][k] : f;
-    f = SsL >= T(0) ? Fs[0][k] : f;
-    f = SR <= T(0) ? Ff[1][k] : f;
-    f = SL >= T(0) ? Ff[0][k] : f;
-    Fo[k] = f;
+    const T fs = fma(S, Us[k] - Ua[k], Fa[k]);
+    const T fss = fma(Ss, Uss[k] - Us[k], fs);
+    Fo[k] = outer ? Fa[k] : (single ? fs : fss);
   }
   F[0] = Fo[0];
   F[1 + n] = Fo[1];
@@ -517,8 +501,90 @@ __device__ __forceinline__ double cell_dt3(const T* m, const P3<T>& p) {
   return 1.0 / s;
 }
 
+// Per-wave LDS: the current plane's polynomial of every lane and the -z face
+// sums carried from the previous plane.
+template <typename T>
+struct Lds3 {
+  T cur[kNC][64];
+  T carry[24][64];
+};
+
+template <typename T>
+__device__ __forceinline__ void lds_put_poly(T (*dst)[64], int lane, const Poly<T>& q) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    dst[4 * v][lane] = q.m[v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dst[4 * v + 1 + d][lane] = q.g[v][d];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dst[20 + c][lane] = q.b[c];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) dst[23 + j][lane] = q.a[j];
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_get_poly(const T (*src)[64], int lane, Poly<T>& q) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    q.m[v] = src[4 * v][lane];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q.g[v][d] = src[4 * v + 1 + d][lane];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) q.b[c] = src[20 + c][lane];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) q.a[j] = src[23 + j][lane];
+}
+
+// Face of axis D whose contributions go only to one cell (sigma as in
+// add_face): each Gauss point is accumulated straight into the cell's
+// residual, so no per-face sums stay live.
+template <typename T, int D>
+__device__ __forceinline__ void face_into(const Poly<T>& L, const Poly<T>& R, T sigma,
+                                          const P3<T>& p, Acc<T>& acc, bool& bad) {
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  T bL[8], iL1[8], iL2[8], bR[8], iR1[8], iR2[8];
+  face_trace<T, D>(L, T(1), p, bL, iL1, iL2);
+  face_trace<T, D>(R, T(-1), p, bR, iR1, iR2);
+  const T cm = sigma * p.c4h[D];
+  const T c1 = sigma * p.cs[D][t1], c2 = sigma * p.cs[D][t2];
+  const T p1 = sigma * p.pt[D][t1], p2 = sigma * p.pt[D][t2];
+#pragma unroll 1
+  for (int g = 0; g < 4; ++g) {
+    const T s1 = (g & 2) ? T(1) : T(-1);
+    const T s2 = (g & 1) ? T(1) : T(-1);
+    T uL[8], uR[8], F[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uL[k] = fma(s2, iL2[k], fma(s1, iL1[k], bL[k]));
+      uR[k] = fma(s2, iR2[k], fma(s1, iR1[k], bR[k]));
+    }
+    const T bn = T(0.5) * (uL[5 + D] + uR[5 + D]);
+    uL[5 + D] = bn;
+    uR[5 + D] = bn;
+    hlld<T, D>(uL, uR, p, F, bad);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k != 5 + D) acc.m[k] = fma(cm, F[k], acc.m[k]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      acc.g[v][D] = fma(-p.c15[D], F[v], acc.g[v][D]);
+      acc.g[v][t1] = fma(s1 * c1, F[v], acc.g[v][t1]);
+      acc.g[v][t2] = fma(s2 * c2, F[v], acc.g[v][t2]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c != D) acc.P[c][D] = fma(T(-0.125), F[5 + c], acc.P[c][D]);
+      acc.P[c][t1] = fma(s1 * p1, F[5 + c], acc.P[c][t1]);
+      acc.P[c][t2] = fma(s2 * p2, F[5 + c], acc.P[c][t2]);
+    }
+  }
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
+  __shared__ Lds3<T> sm;
   const int lane = threadIdx.x;
   const int wave = xcd_remap(blockIdx.x, gridDim.x);
   if (wave >= p.ntiles) return;
@@ -539,68 +605,103 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
   auto zw = [nz](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
   bool bad = false;
   double dtmin = 1e300;
+  const int left = lane == 0 ? 0 : lane - 1;
 
-  Poly<T> cur;
-  FaceSums<T> carry;  // -z face of the current plane
   {
-    Poly<T> prv;
+    Poly<T> prv, cur;
     load_poly(p.in, nc, idx(y, zw(z0 - 1)), prv);
     load_poly(p.in, nc, idx(y, z0), cur);
-    face<T, 2>(prv, cur, p, carry, bad);
+    FaceSums<T> fz;
+    face<T, 2>(prv, cur, p, fz, bad);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      sm.carry[k][lane] = fz.S[k];
+      sm.carry[8 + k][lane] = fz.T1[k];
+      sm.carry[16 + k][lane] = fz.T2[k];
+    }
+    lds_put_poly(sm.cur, lane, cur);
   }
   T dt = T(0);
   if (MODE != kRhs) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
 
   for (int z = z0; z < z1; ++z) {
-    // Loads are issued one step ahead of their use so that at most one
-    // neighbour polynomial is in flight while another is being consumed.
-    Poly<T> qs;
-    load_poly(p.in, nc, idx(yS, z), qs);
+    Poly<T> nb;  // neighbour polynomial in flight: y-1, then y+1, then z+1
     Acc<T> acc;
     zero(acc);
-    add_face<T, 2>(acc, carry, T(1), p);
     {
-      // x-faces: this lane solves its -x face, the +x face comes from lane+1
-      Poly<T> left;
-      shfl_up_poly(cur, left);
+      FaceSums<T> fz;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        fz.S[k] = sm.carry[k][lane];
+        fz.T1[k] = sm.carry[8 + k][lane];
+        fz.T2[k] = sm.carry[16 + k][lane];
+      }
+      add_face<T, 2>(acc, fz, T(1), p);
+    }
+    {
+      // x-faces: this lane solves its -x face (left neighbour from LDS), the
+      // +x face comes from lane+1 by shuffle
+      Poly<T> l, c;
+      lds_get_poly(sm.cur, left, l);
+      lds_get_poly(sm.cur, lane, c);
       FaceSums<T> fx;
-      face<T, 0>(left, cur, p, fx, bad);
+      face<T, 0>(l, c, p, fx, bad);
       add_face<T, 0>(acc, fx, T(1), p);
       shfl_down_sums(fx);
       add_face<T, 0>(acc, fx, T(-1), p);
     }
-    add_volume(acc, cur, p, bad);
+    load_poly(p.in, nc, idx(yS, z), nb);
     {
-      Poly<T> qn;
-      load_poly(p.in, nc, idx(yN, z), qn);
-      FaceSums<T> fy;
-      face<T, 1>(qs, cur, p, fy, bad);
-      add_face<T, 1>(acc, fy, T(1), p);
-      Poly<T> nxt;
-      load_poly(p.in, nc, idx(y, zw(z + 1)), nxt);
-      face<T, 1>(cur, qn, p, fy, bad);
-      add_face<T, 1>(acc, fy, T(-1), p);
-      qs = nxt;  // reuse the registers: qs now holds plane z+1
+      Poly<T> c;
+      lds_get_poly(sm.cur, lane, c);
+      add_volume(acc, c, p, bad);
     }
-    Poly<T> ua;
-    if (MODE == kStage2) load_poly(p.ua, nc, idx(y, z), ua);
-    face<T, 2>(cur, qs, p, carry, bad);
-    add_face<T, 2>(acc, carry, T(-1), p);
+    {
+      Poly<T> c;
+      lds_get_poly(sm.cur, lane, c);
+      face_into<T, 1>(nb, c, T(1), p, acc, bad);
+    }
+    load_poly(p.in, nc, idx(yN, z), nb);
+    {
+      Poly<T> c;
+      lds_get_poly(sm.cur, lane, c);
+      face_into<T, 1>(c, nb, T(-1), p, acc, bad);
+    }
+    load_poly(p.in, nc, idx(y, zw(z + 1)), nb);
+    {
+      Poly<T> c;
+      lds_get_poly(sm.cur, lane, c);
+      FaceSums<T> fz;
+      face<T, 2>(c, nb, p, fz, bad);
+      add_face<T, 2>(acc, fz, T(-1), p);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        sm.carry[k][lane] = fz.S[k];
+        sm.carry[8 + k][lane] = fz.T1[k];
+        sm.carry[16 + k][lane] = fz.T2[k];
+      }
+    }
     Poly<T> d;
     finish(acc, p, d);
-    if (MODE != kRhs) {
+    {
+      Poly<T> c;
+      lds_get_poly(sm.cur, lane, c);
+      if (MODE != kRhs) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        d.m[v] = fma(dt, d.m[v], cur.m[v]);
+        for (int v = 0; v < 5; ++v) {
+          d.m[v] = fma(dt, d.m[v], c.m[v]);
 #pragma unroll
-        for (int e = 0; e < 3; ++e) d.g[v][e] = fma(dt, d.g[v][e], cur.g[v][e]);
+          for (int e = 0; e < 3; ++e) d.g[v][e] = fma(dt, d.g[v][e], c.g[v][e]);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) d.b[cc] = fma(dt, d.b[cc], c.b[cc]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) d.a[j] = fma(dt, d.a[j], c.a[j]);
       }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) d.b[c] = fma(dt, d.b[c], cur.b[c]);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) d.a[j] = fma(dt, d.a[j], cur.a[j]);
     }
     if (MODE == kStage2) {
+      Poly<T> ua;
+      load_poly(p.ua, nc, idx(y, z), ua);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         d.m[v] = T(0.5) * (ua.m[v] + d.m[v]);
@@ -608,7 +709,7 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
         for (int e = 0; e < 3; ++e) d.g[v][e] = T(0.5) * (ua.g[v][e] + d.g[v][e]);
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d.b[c] = T(0.5) * (ua.b[c] + d.b[c]);
+      for (int cc = 0; cc < 3; ++cc) d.b[cc] = T(0.5) * (ua.b[cc] + d.b[cc]);
 #pragma unroll
       for (int j = 0; j < 8; ++j) d.a[j] = T(0.5) * (ua.a[j] + d.a[j]);
     }
@@ -619,7 +720,9 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
         dtmin = fmin(dtmin, cell_dt3(mm, p));
       }
     }
-    cur = qs;
+    // the next plane becomes current (all lanes of the wave finished reading
+    // their neighbours' slots above: LDS operations of one wave run in order)
+    lds_put_poly(sm.cur, lane, nb);
   }
   if (bad && own) atomicOr(p.status, 1);
   if (MODE == kStage2 && p.dtpart) {
@@ -765,7 +868,7 @@ hipError_t launch_cart3d(const dg_mesh* m, int mode, const void* in, const void*
       const void* ua = u0;
       const void* b = in;
       if (lim) {
-        if (!m->ws_a_fresh) e = limit(u0, m->ws_a);
+        if (!(m->ws_a_fresh && m->ws_a_src == u0)) e = limit(u0, m->ws_a);
         ua = m->ws_a;
         if (e == hipSuccess) e = limit(in, m->ws_b);
         b = m->ws_b;

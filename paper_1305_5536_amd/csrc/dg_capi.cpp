@@ -211,12 +211,14 @@ int64_t dg_state_len(dg_mesh_t m) { return m ? (int64_t)m->ncoef * m->ncells : -
 int dg_ncoef(dg_mesh_t m) { return m ? m->ncoef : -1; }
 
 dg_status dg_rhs(dg_mesh_t m, const void* U, void* dUdt, void* stream) {
+  if (m) m->ws_a_fresh = false;
   if (!m || !U || !dUdt) return einval("dg_rhs: NULL argument");
   if (U == dUdt) return einval("dg_rhs: U and dUdt must not alias");
   return dispatch(m, kRhs, U, nullptr, dUdt, nullptr, 0.0, (hipStream_t)stream);
 }
 
 dg_status dg_limit(dg_mesh_t m, const void* U, void* Ul, void* stream) {
+  if (m) m->ws_a_fresh = false;
   if (!m || !U || !Ul) return einval("dg_limit: NULL argument");
   if (U == Ul) return einval("dg_limit: U and U_lim must not alias");
   return dispatch(m, kLimit, U, nullptr, Ul, nullptr, 0.0, (hipStream_t)stream);
@@ -236,6 +238,7 @@ static dg_status step_impl(dg_mesh_t m, const void* U, void* Un, const double* d
   if (st != DG_OK) return st;
   // 3D keeps Pi(U) of stage 1 in its workspace for the stage-2 combination
   m->ws_a_fresh = true;
+  m->ws_a_src = U;
   st = dispatch(m, kStage2, m->v1, U, target, dt_dev, dt_host, s);
   m->ws_a_fresh = false;
   if (st != DG_OK) return st;
@@ -258,7 +261,12 @@ dg_status dg_stage1(dg_mesh_t m, const void* U, void* V1, double dt, const doubl
   if (!m || !U || !V1) return einval("dg_stage1: NULL argument");
   if (U == V1) return einval("dg_stage1: U and V1 must not alias");
   if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage1: dt must be finite and >= 0");
-  return dispatch(m, kStage1, U, nullptr, V1, dt_dev, dt, (hipStream_t)stream);
+  dg_status st = dispatch(m, kStage1, U, nullptr, V1, dt_dev, dt, (hipStream_t)stream);
+  // 3D keeps Pi(U) in its workspace; an immediately following dg_stage2 on
+  // the same U reuses it
+  m->ws_a_fresh = st == DG_OK && m->dim == 3;
+  m->ws_a_src = U;
+  return st;
 }
 
 dg_status dg_stage2(dg_mesh_t m, const void* U, const void* V1, void* Un, double dt,
@@ -267,7 +275,9 @@ dg_status dg_stage2(dg_mesh_t m, const void* U, const void* V1, void* Un, double
   if (Un == U || Un == V1) return einval("dg_stage2: U_next must not alias U or V1");
   if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage2: dt must be finite and >= 0");
   if (dt_next_dev && !(cfl > 0 && std::isfinite(cfl))) return einval("dg_stage2: cfl must be > 0");
-  return dispatch(m, kStage2, V1, U, Un, dt_dev, dt, (hipStream_t)stream, cfl, dt_next_dev);
+  dg_status st = dispatch(m, kStage2, V1, U, Un, dt_dev, dt, (hipStream_t)stream, cfl, dt_next_dev);
+  m->ws_a_fresh = false;
+  return st;
 }
 
 dg_status dg_step_devdt(dg_mesh_t m, const void* U, void* Un, const double* dt_dev,
@@ -277,6 +287,7 @@ dg_status dg_step_devdt(dg_mesh_t m, const void* U, void* Un, const double* dt_d
 }
 
 dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void* stream) {
+  if (m) m->ws_a_fresh = false;
   if (!m || !U || !dt_dev) return einval("dg_cfl_dt: NULL argument");
   if (!(cfl > 0) || !std::isfinite(cfl)) return einval("dg_cfl_dt: cfl must be > 0");
   hipError_t e;

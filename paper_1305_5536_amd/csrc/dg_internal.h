@@ -74,7 +74,8 @@ struct dg_mesh {
   void* tmp = nullptr;        // workspace: staging for in-place steps (lazy)
   void* ws_a = nullptr;       // 3D: Pi(U) of stage 1 (reused by stage 2)
   void* ws_b = nullptr;       // 3D: Pi(V1)
-  bool ws_a_fresh = false;    // ws_a holds Pi(U) of the U passed to this stage 2
+  bool ws_a_fresh = false;    // ws_a holds Pi(ws_a_src) from the preceding stage 1
+  const void* ws_a_src = nullptr;
   int* status = nullptr;      // device status word
   double* dtpart = nullptr;   // per-wave partial minima for dg_cfl_dt
   int ndtpart = 0;

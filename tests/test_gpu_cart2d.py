@@ -31,8 +31,8 @@ def _solver(n, lo, hi, gamma, limiter=True, precision="fp64"):
 def field_errors(A, B, n, lo, hi, nvar=4, U=None):
     """Per-field relative error of A against the reference B (means and h-scaled
     gradients, normalised by the largest mean of the field).  With U given the
-    arguments are right-hand sides L(U), whose natural size is |U| c / h
-    (c ~ 1 here), and that is the scale."""
+    arguments are right-hand sides L(U), whose natural size is max|U| c / h
+    over all conserved fields (c ~ 1 here), and that is the scale."""
     dim = len(n)
     h = min((hi[d] - lo[d]) / n[d] for d in range(dim))
     A = A.reshape(nvar * (1 + dim), -1)
@@ -43,7 +43,7 @@ def field_errors(A, B, n, lo, hi, nvar=4, U=None):
         k = v * (1 + dim)
         scale = max(np.abs(B[k]).max(), 1e-300)
         if Us is not None:
-            scale = max(scale, np.abs(Us[k]).max() / h)
+            scale = max(scale, np.abs(Us[0::1 + dim]).max() / h)
         d = np.abs(A[k] - B[k]).max()
         for c in range(1, 1 + dim):
             d = max(d, h * np.abs(A[k + c] - B[k + c]).max())

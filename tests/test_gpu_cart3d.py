@@ -36,7 +36,8 @@ FIELDS = {"rho": (0, [1, 2, 3]), "mx": (4, [5, 6, 7]), "my": (8, [9, 10, 11]),
 
 def field_errors(A, B, n, lo, hi, U=None):
     """U given: the arguments are right-hand sides L(U), whose natural size is
-    |U| c / h (c ~ 1 here); errors are measured against that scale."""
+    max|U| c / h over all conserved fields (fluxes mix them: the momentum flux
+    carries the pressure); errors are measured against that scale (c ~ 1)."""
     h = min((hi[d] - lo[d]) / n[d] for d in range(3))
     A = A.reshape(31, -1)
     B = B.reshape(31, -1)
@@ -45,14 +46,14 @@ def field_errors(A, B, n, lo, hi, U=None):
     for name, (k, gs) in FIELDS.items():
         scale = max(np.abs(B[k]).max(), 1e-300)
         if Us is not None:
-            scale = max(scale, np.abs(Us[k]).max() / h)
+            scale = max(scale, np.abs(Us[[0, 4, 8, 12, 16, 20, 21, 22]]).max() / h)
         d = np.abs(A[k] - B[k]).max()
         for g in gs:
             d = max(d, h * np.abs(A[g] - B[g]).max())
         out[name] = d / scale
     bscale = max(np.abs(B[20:23]).max(), 1e-300)
     if Us is not None:
-        bscale = max(bscale, np.abs(Us[20:23]).max() / h)
+        bscale = max(bscale, np.abs(Us[[0, 4, 8, 12, 16, 20, 21, 22]]).max() / h)
     d = np.abs(A[20:23] - B[20:23]).max()
     d = max(d, h * np.abs(A[23:31] - B[23:31]).max())
     out["B"] = d / bscale
