@@ -173,8 +173,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   }
   const size_t bytes = (size_t)m->ncoef * (size_t)m->ncells * m->elem;
   hipError_t e = hipMalloc(&m->v1, bytes);
-  if (e == hipSuccess && m->dim == 3) e = hipMalloc(&m->ws_a, bytes);
-  if (e == hipSuccess && m->dim == 3) e = hipMalloc(&m->ws_b, bytes);
+  const bool separate_limiter = m->dim == 3 || m->kind == 1;
+  if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_a, bytes);
+  if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_b, bytes);
   if (e == hipSuccess) e = hipMalloc(&m->status, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
@@ -264,7 +265,7 @@ dg_status dg_stage1(dg_mesh_t m, const void* U, void* V1, double dt, const doubl
   dg_status st = dispatch(m, kStage1, U, nullptr, V1, dt_dev, dt, (hipStream_t)stream);
   // 3D keeps Pi(U) in its workspace; an immediately following dg_stage2 on
   // the same U reuses it
-  m->ws_a_fresh = st == DG_OK && m->dim == 3;
+  m->ws_a_fresh = st == DG_OK && (m->dim == 3 || m->kind == 1);
   m->ws_a_src = U;
   return st;
 }

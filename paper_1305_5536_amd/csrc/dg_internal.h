@@ -34,23 +34,12 @@ struct Cart3D {
   int tiles_x, tiles_y, tiles_z;
 };
 
-// Device geometry of a 2D face-list mesh (see facelist2d.hip).
+// Face-list mesh bookkeeping kept on the host side of the handle; the device
+// arrays live in FLDev (facelist2d.hip).
 struct FaceList2D {
-  int64_t ncells, nfaces;
-  int nblocks;              // cell blocks
-  int block_cells;          // cells per block (max)
-  // per block: cell range [cell_ptr[b], cell_ptr[b+1]) and face range
-  int* block_cell_ptr;
-  int* block_face_ptr;
-  // per block-local face slot: face data (blocked order)
-  int* bf_cells;            // [2 * nbf]  global L, R
-  double* bf_geo;           // [8 * nbf]  nx, ny, A, gx0, gy0 (offset of Gauss pt 0 from L centroid), rx, ry (L->R centroid image offset), pad
-  // per cell (cells in block order = original order after host renumbering)
-  int* cell_face_ptr;       // CSR into cell_faces (block-local face slots, signed: +1 L, -1 R)
-  int* cell_faces;
-  double* cell_geo;         // [12 * ncells]: V, Minv(3), quad axes (4), ...
-  int64_t nbf;
+  int nblocks;
 };
+struct FLDev;
 
 template <typename T>
 struct Workspace {
@@ -69,6 +58,7 @@ struct dg_mesh {
   dg::Cart2D c2{};
   dg::Cart3D c3{};
   dg::FaceList2D fl{};
+  dg::FLDev* fld = nullptr;
   size_t elem = 8;            // sizeof(element)
   void* v1 = nullptr;         // workspace: stage-1 output
   void* tmp = nullptr;        // workspace: staging for in-place steps (lazy)
