@@ -38,13 +38,21 @@ STAGE_VALUES = {1: 24, 2: 36}
 # Gauss points of 3 faces, 8 volume points, accumulation, inverse mass matrix
 # and the RK combination; counted from the kernel's formulation).
 MHD_FLOPS_PER_CELL_STAGE = 8700
+# Algorithmic bytes of one 2D Euler cell-stage on a face list: the state (24
+# values per stage on average: 2.5 coefficient sets of 12 per step / 2 stages
+# rounded as in the Cartesian case, 240 B in FP64) plus the static geometry a
+# stage must read (3 faces per cell x (ids 8 B, normal 16 B, length 8 B,
+# centroid 16 B) and per cell V, centroid, M^-1, volume-rule axes: 224 B in
+# FP64, 112 B in FP32).
+FACELIST_BYTES_PER_CELL_STAGE = {"fp64": 464, "fp32": 232}
 
 
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--config", choices=["c2", "c3"], default="c2",
-                   help="c2: 2D Euler shear layer 2048^2 (default); c3: 3D MHD 256^3")
+    p.add_argument("--config", choices=["c1", "c2", "c3", "c4"], default="c2",
+                   help="c2: 2D Euler shear layer 2048^2 (default); c1: isentropic vortex "
+                        "64^2; c3: 3D MHD 256^3; c4: static Voronoi mesh of 1M cells")
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--n", type=int, default=None, help="cells per side")
@@ -54,7 +62,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=None)
     a = p.parse_args()
-    dflt = {"c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 2)}[a.config]
+    # (cells per side or cells, timed steps, warm-up steps, oracle steps of the
+    # CPU baseline sized to about 10-30 s of host work)
+    dflt = {"c1": (64, 100, 10, 8000), "c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 12),
+            "c4": (1000000, 100, 5, 50)}[a.config]
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
@@ -200,9 +211,115 @@ def bench_c3(a):
                        "stage1_TFLOPs": MHD_FLOPS_PER_CELL_STAGE * ncells / r32["stage1_s"] / 1e12}
     if not a.no_cpu:
         log("timing the CPU oracle")
-        ns = 48
+        ns = 96
         out["cpu_baseline"] = cpu_baseline(W.c3_state(ns), ns, a.cpu_steps, dim=3, mhd=True,
                                            label="the same MHD-turbulence recipe")
+    return out
+
+
+def bench_c1(a):
+    import workloads as W
+    from paper_1305_5536_amd.solver import cartesian
+    n = a.n
+    U0 = W.c1_state(n)
+    mesh = cartesian((n, n), (0.0, 0.0), (10.0, 10.0))
+    from paper_1305_5536_amd.solver import Solver
+    log("timing the GPU steps")
+    s = Solver(mesh, physics="euler", precision=a.precision, limiter=False, gamma=1.4)
+    import torch
+    U = s.to_device(U0)
+    V1, Un = s.empty(), s.empty()
+    dt = s.cfl_dt(U, 0.3)
+    for _ in range(a.warmup):
+        s.stage1(U, dt, V1)
+        s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt)
+        U, Un = Un, U
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(a.steps):
+        s.stage1(U, dt, V1)
+        s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt)
+        U, Un = Un, U
+    e1.record(st)
+    torch.cuda.synchronize()
+    s.check()
+    t = e0.elapsed_time(e1) * 1e-3
+    out = {"metric": METRIC, "value": n * n * 2 * a.steps / t, "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": t / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
+           "data": "synthetic",
+           "config": {"workload": f"2D Euler isentropic vortex, periodic Cartesian {n}x{n} on "
+                                  "[0,10]^2, gamma 1.4, HLL, no limiter, SSP-RK2 CFL 0.3",
+                      "cells": n * n, "note": "the state fits in L2: launch-latency bound"}}
+    if not a.no_cpu:
+        import oracle
+        om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (10.0, 10.0))
+        dtc = oracle.cfl_dt(om, U0, 1.4, 0.3)
+        t0 = time.perf_counter()
+        Uc = U0
+        for _ in range(a.cpu_steps):
+            Uc = oracle.step(om, Uc, dtc, 1.4, False)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * n * 2 * a.cpu_steps / el, "unit": "cell-updates/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{a.cpu_steps} SSP-RK2 steps of the same {n}x{n} "
+                                         f"vortex, FP64, {el:.1f} s"}
+    return out
+
+
+def bench_c4(a):
+    from workloads.voronoi import c4_state, periodic_voronoi
+    n = a.n
+    t0 = time.perf_counter()
+    log(f"building the periodic Voronoi mesh of {n} cells (2 Lloyd iterations)")
+    mesh = periodic_voronoi(n, seed=1004)
+    log(f"mesh built in {time.perf_counter() - t0:.0f} s; projecting the initial state")
+    U0 = c4_state(mesh)
+    tgen = time.perf_counter() - t0
+    log("timing the GPU steps")
+    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup)
+    value = n * 2 * a.steps / r["event_s"]
+    per = FACELIST_BYTES_PER_CELL_STAGE[a.precision]
+    achieved = per * n / r["stage1_s"] / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"2D Euler on a static periodic Voronoi mesh of {n} cells "
+                               f"({len(mesh['face_area'])} faces, 2 Lloyd iterations), Gaussian "
+                               "density bump at rest, gamma 5/3, HLL, limiter on, SSP-RK2",
+                   "cells": n, "rk_stages_per_step": 2, "parallelism": "single GPU",
+                   "input_generation_s": tgen},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage 1 (k_fl_lim + k_fl_rhs)",
+                     "bytes_per_launch": per * n, "avg_launch_s": r["stage1_s"]},
+        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": n * 2 * a.steps / r32["event_s"],
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "stage1_GBs": FACELIST_BYTES_PER_CELL_STAGE["fp32"] * n / r32["stage1_s"] / 1e9}
+    if not a.no_cpu:
+        import oracle
+        log("timing the CPU oracle")
+        om = oracle.Mesh.facelist(mesh)
+        dt = oracle.cfl_dt(om, U0, 5.0 / 3.0, 0.3)
+        t1 = time.perf_counter()
+        Uc = U0
+        for _ in range(a.cpu_steps):
+            Uc = oracle.step(om, Uc, dt, 5.0 / 3.0, True)
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": n * 2 * a.cpu_steps / el, "unit": "cell-updates/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{a.cpu_steps} limited SSP-RK2 steps on the same "
+                                         f"{n}-cell mesh and state, FP64, {el:.1f} s"}
     return out
 
 
@@ -212,7 +329,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
-    out = bench_c2(a) if a.config == "c2" else bench_c3(a)
+    out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[a.config](a)
     print(json.dumps(out))
 
 
