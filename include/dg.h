@@ -161,6 +161,19 @@ dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next,
 dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,
                         void* stream);
 
+/* Discrete adjoint of dg_step (vector-Jacobian product), dt frozen:
+ *   lam_n = (d step(U, dt) / d U)^T lam_np1
+ * through both stages, both limiter applications (the branch the forward step
+ * takes: alpha = 1, or alpha = D/dm with its arg-max/arg-min neighbour) and
+ * the HLL flux (the active wave-speed estimates).  Ties follow the first
+ * argument in the order self, -x, +x, -y, +y.  V1 is the stage-1 output of the
+ * forward step from U (dg_stage1 with the same dt), or NULL to recompute it.
+ * Built for 2D Euler on Cartesian meshes (DG_EUNSUPPORTED otherwise).
+ * lam_n must not alias U, V1 or lam_np1.  Allocates two state-sized
+ * workspaces on the first call (kept by the handle). */
+dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double dt,
+                          const void* lam_np1, void* lam_n, void* stream);
+
 /* *dt_dev = cfl * min_e 2 V_e / sum_{f of e} A_f (|v_e . n_f| + c_e(n_f)) from
  * the cell means of U (c the sound speed, or the fast magnetosonic speed along
  * n_f for MHD).  dt_dev is a device pointer to one double. */

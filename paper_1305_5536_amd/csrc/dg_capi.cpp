@@ -148,6 +148,25 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.rows_per_tile = default_rows(m->c2.tiles_x, d->n[1]);
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
+    if (cfg->physics == DG_EULER) {
+      dg::AdjInst ai{};
+      ai.nx = m->c2.nx;
+      ai.ny = m->c2.ny;
+      ai.off = 0;
+      ai.tx0 = 0;
+      ai.tiles_x = (ai.nx + dg::kAdjTile - 1) / dg::kAdjTile;
+      ai.tiles_y = (ai.ny + dg::kAdjTile - 1) / dg::kAdjTile;
+      ai.hx = m->c2.hx;
+      ai.hy = m->c2.hy;
+      m->adj_tiles = ai.tiles_x * ai.tiles_y;
+      hipError_t e2 = hipMalloc(&m->adj_inst, sizeof(dg::AdjInst));
+      if (e2 == hipSuccess)
+        e2 = hipMemcpy(m->adj_inst, &ai, sizeof(dg::AdjInst), hipMemcpyHostToDevice);
+      if (e2 != hipSuccess) {
+        dg_mesh_destroy(m);
+        return hip_fail(e2, "dg_mesh_create: adjoint table");
+      }
+    }
   } else if (d->kind == 0 && d->dim == 3) {
     m->ncoef = 31;
     m->ncells = d->n[0] * d->n[1] * d->n[2];
@@ -201,6 +220,9 @@ void dg_mesh_destroy(dg_mesh_t m) {
   (void)hipFree(m->v1);
   (void)hipFree(m->tmp);
   (void)hipFree(m->ws_a);
+  (void)hipFree(m->adj_inst);
+  (void)hipFree(m->adj_ws1);
+  (void)hipFree(m->adj_ws2);
   (void)hipFree(m->ws_b);
   (void)hipFree(m->status);
   (void)hipFree(m->dtpart);
@@ -300,6 +322,36 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
   else
     e = launch_cart3d_cfl(m, U, cfl, dt_dev, s);
   if (e != hipSuccess) return hip_fail(e, "dg_cfl_dt launch");
+  return DG_OK;
+}
+
+dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
+                          const void* lam_np1, void* lam_n, void* stream) {
+  if (!m || !U || !lam_np1 || !lam_n) return einval("dg_adjoint_step: NULL argument");
+  m->ws_a_fresh = false;
+  if (m->kind != 0 || m->dim != 2 || !m->adj_inst) {
+    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes");
+    return DG_EUNSUPPORTED;
+  }
+  if (!std::isfinite(dt) || dt < 0) return einval("dg_adjoint_step: dt must be finite and >= 0");
+  if (lam_n == lam_np1 || lam_n == U || lam_n == V1)
+    return einval("dg_adjoint_step: lam_n must not alias U, V1 or lam_np1");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)m->ncoef * m->ncells * m->elem;
+  hipError_t e = hipSuccess;
+  if (!m->adj_ws1) e = hipMalloc(&m->adj_ws1, bytes);
+  if (e == hipSuccess && !m->adj_ws2) e = hipMalloc(&m->adj_ws2, bytes);
+  if (e != hipSuccess) return hip_fail(e, "dg_adjoint_step: workspace allocation");
+  if (!V1) {
+    dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, nullptr, dt, s);
+    if (st != DG_OK) return st;
+    V1 = m->v1;
+  }
+  e = launch_adjoint2d(m->adj_inst, nullptr, m->adj_tiles, (int)m->ncells, dg_state_len(m),
+                       m->cfg.precision == DG_FP64, m->cfg.limiter == DG_LIMITER_MINMOD,
+                       m->cfg.gamma, U, V1, nullptr, dt, lam_np1, lam_n, m->adj_ws1, m->adj_ws2,
+                       s);
+  if (e != hipSuccess) return hip_fail(e, "dg_adjoint_step launch");
   return DG_OK;
 }
 

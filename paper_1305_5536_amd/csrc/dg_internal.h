@@ -41,6 +41,16 @@ struct FaceList2D {
 };
 struct FLDev;
 
+// One 2D Cartesian instance of the adjoint (and batched) kernels: a mesh of
+// nx x ny cells starting at cell `off` of the global state arrays, whose
+// 16 x 16 adjoint tiles start at tile `tx0` of the tile list.
+constexpr int kAdjTile = 16;
+struct AdjInst {
+  int nx, ny, off, tx0;
+  int tiles_x, tiles_y, pad0, pad1;
+  double hx, hy;
+};
+
 template <typename T>
 struct Workspace {
   T* v1 = nullptr;       // stage-1 output
@@ -70,6 +80,10 @@ struct dg_mesh {
   double* dtpart = nullptr;   // per-wave partial minima for dg_cfl_dt
   int ndtpart = 0;
   int device = 0;
+  dg::AdjInst* adj_inst = nullptr;  // device copy (2D Cartesian meshes)
+  int adj_tiles = 0;
+  void* adj_ws1 = nullptr;          // adjoint workspaces (lazy)
+  void* adj_ws2 = nullptr;
 };
 
 namespace dg {
@@ -85,5 +99,10 @@ hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void*
                          hipStream_t s);
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
+hipError_t launch_adjoint2d(const void* inst, const int* tile_inst, int ntiles, int nc,
+                            int64_t total, bool f64, bool lim, double gamma, const void* U,
+                            const void* V1, const double* dt_dev, double dt_host,
+                            const void* lam_np1, void* lam_n, void* ws1, void* ws2,
+                            hipStream_t s);
 
 }  // namespace dg

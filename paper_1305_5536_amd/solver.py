@@ -156,6 +156,18 @@ class Solver:
                                   _stream()), "dg_stage2")
         return out
 
+    def adjoint_step(self, U: torch.Tensor, dt: float, lam_next: torch.Tensor,
+                     V1: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        """lam_n = (d step(U, dt)/dU)^T lam_next (dt frozen)."""
+        self._check_state(U)
+        self._check_state(lam_next, "lam_next")
+        out = self.empty() if out is None else out
+        self._check_state(out, "out")
+        v1 = None if V1 is None else _ptr(V1)
+        C.check(C.lib().dg_adjoint_step(self._h, _ptr(U), v1, float(dt), _ptr(lam_next),
+                                        _ptr(out), _stream()), "dg_adjoint_step")
+        return out
+
     def cfl_dt(self, U: torch.Tensor, cfl: float, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check_state(U)
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
