@@ -23,6 +23,14 @@
  * Cartesian cells are numbered x fastest: cell = (k*ny + j)*nx + i.
  * Element type is double (DG_FP64) or float (DG_FP32), per dg_config.
  *
+ * Batches (mesh kind 2).  A handle can hold many independent periodic 2D
+ * Cartesian Euler instances of uneven sizes, stored one after another in the
+ * same coefficient-major arrays: instance i owns cells [off_i, off_i+1) of
+ *   U[k * ncells + cell],  ncells = sum_i nx_i ny_i
+ * (dg_instance_offsets).  Every entry point works on a batch; each instance
+ * has its own step size, so a device step-size argument (dt_dev, dt_next_dev)
+ * points to ninst doubles, one per instance, and a host dt applies to all.
+ *
  * Ownership.  State, derivative and adjoint buffers are DEVICE pointers owned
  * by the caller (at least 16-byte aligned, contiguous, dg_state_len elements).
  * The library owns the mesh handle, its device geometry and its workspace
@@ -87,7 +95,10 @@ typedef struct {
  *   face_centroid[nfaces][2] (edge midpoint, in L's periodic frame),
  *   face_shift[nfaces][2] in {-1, 0, 1}: R's image next to L sits at
  *     centroid[R] + shift * box.
- *   Every cell must be closed: sum over its faces of A n = 0 (checked). */
+ *   Every cell must be closed: sum over its faces of A n = 0 (checked).
+ * kind 2: a batch of ninst periodic 2D Cartesian Euler instances (dim = 2):
+ *   inst_n[ninst][2] = (nx, ny), inst_box[ninst][4] = (lo_x, lo_y, hi_x, hi_y),
+ *   host arrays copied at create. */
 typedef struct {
   int dim;
   int kind;
@@ -103,6 +114,9 @@ typedef struct {
   const double* face_normal;
   const double* face_centroid;
   const int8_t* face_shift;
+  int32_t ninst;
+  const int32_t* inst_n;
+  const double* inst_box;
 } dg_mesh_desc;
 
 /* Create a mesh handle: validates the descriptor and configuration, uploads
@@ -166,21 +180,65 @@ dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const doubl
  * through both stages, both limiter applications (the branch the forward step
  * takes: alpha = 1, or alpha = D/dm with its arg-max/arg-min neighbour) and
  * the HLL flux (the active wave-speed estimates).  Ties follow the first
- * argument in the order self, -x, +x, -y, +y.  V1 is the stage-1 output of the
- * forward step from U (dg_stage1 with the same dt), or NULL to recompute it.
- * Built for 2D Euler on Cartesian meshes (DG_EUNSUPPORTED otherwise).
- * lam_n must not alias U, V1 or lam_np1.  Allocates two state-sized
- * workspaces on the first call (kept by the handle). */
+ * argument in the order self, -x, +x, -y, +y.  The step size is *dt_dev (one
+ * per instance on a batch) when dt_dev is not NULL, else dt.  V1 is the
+ * stage-1 output of the forward step from U (dg_stage1 with the same step
+ * size), or NULL to recompute it.  Built for 2D Euler on Cartesian meshes and
+ * batches (DG_EUNSUPPORTED otherwise).  lam_n must not alias U, V1 or
+ * lam_np1.  Allocates two state-sized workspaces on the first call (kept by
+ * the handle). */
 dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double dt,
-                          const void* lam_np1, void* lam_n, void* stream);
+                          const double* dt_dev, const void* lam_np1, void* lam_n, void* stream);
+
+/* Flag of dg_run: capture the launch sequence into a hipGraph. */
+#define DG_RUN_GRAPH 1
+
+/* nsteps SSP-RK2 steps (the dg_stage1/dg_stage2 pair of each step) from U_in
+ * to U_out, with per-step (per-instance) step sizes in the device array
+ * dt_hist, nd = dg_ninst doubles per step:
+ *   cfl > 0: adaptive.  dt_hist[0..nd) = the CFL step of U_in (dg_cfl_dt) and
+ *            step n's stage 2 writes step n+1's into dt_hist[(n+1) nd ...],
+ *            so dt_hist holds (nsteps + 1) nd doubles, the history of the run.
+ *   cfl = 0: dt_hist[n nd ...] is read as the step size of step n.
+ * ckpt_every > 0: ckpt is a HOST array of floor((nsteps - 1) / ckpt_every)
+ *   state-sized DEVICE buffers; ckpt[j] receives the state after step
+ *   (j + 1) ckpt_every (written by that step's stage 2, no extra copy).
+ * v1_keep: NULL, or a HOST array of nsteps DEVICE buffers that receive each
+ *   step's stage-1 output (the V1 of dg_adjoint_step).
+ * U_in is not modified (unless it is U_out); U_out may equal U_in only when
+ * nsteps >= 2; U_out, the checkpoints and v1_keep buffers must be distinct.
+ * Intermediate states ping-pong through two state-sized workspaces of the
+ * handle (allocated on the first call).
+ * flags & DG_RUN_GRAPH: the whole sequence is captured once into a hipGraph,
+ * cached on the handle for these arguments (pointer values included), and
+ * replayed with one graph launch; the capture uses no memset or allocation.
+ * A call with other arguments, dg_set_tiling or dg_set_launch re-captures. */
+dg_status dg_run(dg_mesh_t mesh, const void* U_in, void* U_out, int nsteps, double cfl,
+                 double* dt_hist, int ckpt_every, void* const* ckpt, void* const* v1_keep,
+                 int flags, void* stream);
+
+/* Number of instances (1 for a single mesh), or -1 for a NULL handle. */
+int dg_ninst(dg_mesh_t mesh);
+
+/* off[0..ninst] = first cell of each instance and the total cell count
+ * (host array of dg_ninst + 1 elements). */
+dg_status dg_instance_offsets(dg_mesh_t mesh, int64_t* off);
+
+/* Launch shape of the batched stage kernel: waves per workgroup (1, 2 or 4)
+ * and, when grid_waves > 0, a persistent launch of that many waves, each
+ * walking the tile list with a stride of grid_waves (0: one wave per tile).
+ * Results do not depend on it.  Ignored (DG_OK) for single meshes. */
+dg_status dg_set_launch(dg_mesh_t mesh, int waves_per_group, int grid_waves);
+dg_status dg_get_launch(dg_mesh_t mesh, int* waves_per_group, int* grid_waves);
 
 /* *dt_dev = cfl * min_e 2 V_e / sum_{f of e} A_f (|v_e . n_f| + c_e(n_f)) from
  * the cell means of U (c the sound speed, or the fast magnetosonic speed along
  * n_f for MHD).  dt_dev is a device pointer to one double. */
 dg_status dg_cfl_dt(dg_mesh_t mesh, const void* U, double cfl, double* dt_dev, void* stream);
 
-/* Launch shape of the Cartesian stage kernels: the number of rows (2D) or
- * z-planes (3D) one wave marches through.  0 restores the library default.
+/* Launch shape of the Cartesian stage kernels: the number of rows (2D, and
+ * every instance of a batch) or z-planes (3D) one wave marches through.  0
+ * restores the library default.
  * Results do not depend on it (every face and cell is computed with the same
  * arithmetic whatever the tiling); only speed does.  Face-list meshes ignore
  * it.  Returns DG_EINVAL for a negative value. */

@@ -16,6 +16,7 @@ DG_EULER, DG_MHD = 0, 1
 DG_FP64, DG_FP32 = 0, 1
 DG_FLUX_HLL, DG_FLUX_HLLD = 0, 1
 DG_LIMITER_NONE, DG_LIMITER_MINMOD = 0, 1
+DG_RUN_GRAPH = 1
 
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ENOMEM", 3: "DG_EHIP", 4: "DG_EUNSUPPORTED",
                 5: "DG_ENONPHYSICAL"}
@@ -48,6 +49,8 @@ class dg_mesh_desc(ctypes.Structure):
         ("face_cells", ctypes.POINTER(ctypes.c_int32)), ("face_area", _dp),
         ("face_normal", _dp), ("face_centroid", _dp),
         ("face_shift", ctypes.POINTER(ctypes.c_int8)),
+        ("ninst", ctypes.c_int32), ("inst_n", ctypes.POINTER(ctypes.c_int32)),
+        ("inst_box", _dp),
     ]
 
 
@@ -73,7 +76,16 @@ SYMBOLS = [
                                      ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_adjoint_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_void_p]),
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_run", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                              ctypes.c_int, ctypes.c_void_p]),
+    ("dg_ninst", ctypes.c_int, [ctypes.c_void_p]),
+    ("dg_instance_offsets", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    ("dg_set_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    ("dg_get_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]),
     ("dg_cfl_dt", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_set_tiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),

@@ -253,11 +253,9 @@ __device__ __forceinline__ double cell_dt(const T* m, const P2<T>& p) {
   return 1.0 / s;
 }
 
+// One wave's tile (tile index `wave` of the mesh described by p).
 template <typename T, int MODE, bool LIM>
-__global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
-  const int lane = threadIdx.x & (kLanes - 1);
-  const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-  if (wave >= p.ntiles) return;
+__device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) {
   const int tx = wave % p.tiles_x, ty = wave / p.tiles_x;
   const int colu = tx * kCols + lane - 2;
   const bool own = lane >= 2 && lane < 2 + kCols && colu < p.nx;
@@ -398,6 +396,120 @@ __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
   }
 }
 
+template <typename T, int MODE, bool LIM>
+__global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (wave >= p.ntiles) return;
+  cart2d_tile<T, MODE, LIM>(p, wave, lane);
+}
+
+// ---------------------------------------------------------------- batches --
+// A batch of independent meshes stored one after another in the same
+// coefficient-major arrays (stride nc = total cells of the batch).  Tile t
+// belongs to instance tile_inst[t]; the instance record gives its geometry
+// constants (precomputed on the host, in T), its first cell and first tile.
+// The kernel is persistent when launched with fewer waves than tiles: each
+// wave then walks the tile list with a stride of the launched wave count.
+template <typename T>
+struct BInst {
+  int nx, ny, tiles_x, rows;
+  int off, tile0, ntiles, pad;
+  T cmx, cmy, cgx, cgy, ccr, hx2, hy2, qx, qy;
+  double ihx, ihy;
+};
+
+template <typename T>
+struct PB {
+  P2<T> base;               // pointers, nc, gamma, status, dtpart, dt_next
+  const BInst<T>* inst;
+  const int* tile_inst;
+  int ntiles;               // tiles of the whole batch
+  int wpb;                  // waves per workgroup
+};
+
+template <typename T>
+__device__ __forceinline__ P2<T> inst_params(const PB<T>& b, int i) {
+  const BInst<T>& in = b.inst[i];
+  P2<T> p = b.base;
+  p.in = b.base.in + in.off;
+  p.u0 = b.base.u0 ? b.base.u0 + in.off : nullptr;
+  p.out = b.base.out + in.off;
+  p.dt_dev = b.base.dt_dev ? b.base.dt_dev + i : nullptr;
+  p.dtpart = b.base.dtpart + in.tile0;
+  p.nx = in.nx;
+  p.ny = in.ny;
+  p.rows = in.rows;
+  p.tiles_x = in.tiles_x;
+  p.ntiles = in.ntiles;
+  p.cmx = in.cmx;
+  p.cmy = in.cmy;
+  p.cgx = in.cgx;
+  p.cgy = in.cgy;
+  p.ccr = in.ccr;
+  p.hx2 = in.hx2;
+  p.hy2 = in.hy2;
+  p.qx = in.qx;
+  p.qy = in.qy;
+  p.ihx = in.ihx;
+  p.ihy = in.ihy;
+  return p;
+}
+
+template <typename T, int MODE, bool LIM>
+__global__ __launch_bounds__(256) void k_cart2d_batch(PB<T> b) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int nw = gridDim.x * b.wpb;
+  int w = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * b.wpb +
+                                         (threadIdx.x >> 6));
+  for (int t = w; t < b.ntiles; t += nw) {
+    const int i = __builtin_amdgcn_readfirstlane(b.tile_inst[t]);
+    const P2<T> p = inst_params(b, i);
+    cart2d_tile<T, MODE, LIM>(p, t - b.inst[i].tile0, lane);
+  }
+}
+
+// Per-tile CFL minima of a batch state (the tile decomposition of the stage
+// kernels; each lane walks its column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cart2d_batch_cfl(PB<T> b) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int nw = gridDim.x * b.wpb;
+  int w = __builtin_amdgcn_readfirstlane(blockIdx.x * b.wpb + (threadIdx.x >> 6));
+  for (int t = w; t < b.ntiles; t += nw) {
+    const int i = __builtin_amdgcn_readfirstlane(b.tile_inst[t]);
+    const P2<T> p = inst_params(b, i);
+    const int lt = t - b.inst[i].tile0;
+    const int tx = lt % p.tiles_x, ty = lt / p.tiles_x;
+    const int col = tx * kCols + lane - 2;
+    double d = 1e300;
+    if (lane >= 2 && lane < 2 + kCols && col < p.nx) {
+      const int y1 = min(ty * p.rows + p.rows, p.ny);
+      for (int y = ty * p.rows; y < y1; ++y) {
+        T m[4];
+        load_means(p.in, p.nc, y * p.nx + col, m);
+        d = fmin(d, cell_dt(m, p));
+      }
+    }
+    d = wave_min(d);
+    if (lane == 0) b.base.dtpart[t] = d;
+  }
+}
+
+// dt[i] = cfl * min over instance i's tiles [first[i], first[i+1]).
+__global__ __launch_bounds__(256) void k_min_finalize_batch(const double* part,
+                                                            const int* first, double cfl,
+                                                            double* dt) {
+  __shared__ double s[4];
+  const int i = blockIdx.x;
+  double d = 1e300;
+  for (int t = first[i] + threadIdx.x; t < first[i + 1]; t += 256) d = fmin(d, part[t]);
+  d = wave_min(d);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) dt[i] = cfl * fmin(fmin(s[0], s[1]), fmin(s[2], s[3]));
+}
+
 // Per-wave CFL minima of a state's cell means (stand-alone dg_cfl_dt).
 template <typename T>
 __global__ __launch_bounds__(256) void k_cart2d_cfl(P2<T> p) {
@@ -514,7 +626,154 @@ hipError_t cfl_t(const dg_mesh* m, const void* U, double cfl, double* dt_dev, hi
   return hipGetLastError();
 }
 
+template <typename T>
+PB<T> make_batch_params(const dg_mesh* m, const void* in, const void* u0, void* out,
+                        const double* dt_dev, double dt_host) {
+  PB<T> b;
+  b.base = P2<T>{};
+  b.base.in = static_cast<const T*>(in);
+  b.base.u0 = static_cast<const T*>(u0);
+  b.base.out = static_cast<T*>(out);
+  b.base.dt_dev = dt_dev;
+  b.base.dt_host = dt_host;
+  b.base.status = m->status;
+  b.base.dtpart = m->dtpart;
+  b.base.dt_next = nullptr;
+  b.base.nc = (int)m->ncells;
+  b.base.gamma = (T)m->cfg.gamma;
+  b.inst = static_cast<const BInst<T>*>(m->bt.inst);
+  b.tile_inst = m->bt.tile_inst;
+  b.ntiles = m->bt.ntiles;
+  b.wpb = m->bt.wpb;
+  return b;
+}
+
+template <typename T>
+hipError_t launch_batch_t(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
+                          const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                          hipStream_t s) {
+  PB<T> b = make_batch_params<T>(m, in, u0, out, dt_dev, dt_host);
+  const int wpb = b.wpb;
+  int waves = b.ntiles;
+  if (m->bt.grid_waves > 0 && m->bt.grid_waves < waves) waves = m->bt.grid_waves;
+  const int nblocks = (waves + wpb - 1) / wpb;
+  const dim3 grid(nblocks), block(64 * wpb);
+  const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
+  if (mode == kStage2) {
+    b.base.dt_next = dt_next;
+    b.base.cfl = cfl;
+  }
+  switch (mode) {
+    case kRhs:
+      hipLaunchKernelGGL((k_cart2d_batch<T, kRhs, false>), grid, block, 0, s, b);
+      break;
+    case kLimit:
+      hipLaunchKernelGGL((k_cart2d_batch<T, kLimit, true>), grid, block, 0, s, b);
+      break;
+    case kStage1:
+      if (lim)
+        hipLaunchKernelGGL((k_cart2d_batch<T, kStage1, true>), grid, block, 0, s, b);
+      else
+        hipLaunchKernelGGL((k_cart2d_batch<T, kStage1, false>), grid, block, 0, s, b);
+      break;
+    case kStage2:
+      if (lim)
+        hipLaunchKernelGGL((k_cart2d_batch<T, kStage2, true>), grid, block, 0, s, b);
+      else
+        hipLaunchKernelGGL((k_cart2d_batch<T, kStage2, false>), grid, block, 0, s, b);
+      if (dt_next)
+        hipLaunchKernelGGL(k_min_finalize_batch, dim3(m->bt.ninst), dim3(256), 0, s, m->dtpart,
+                           m->bt.inst_tile0, cfl, dt_next);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_cfl_t(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                       hipStream_t s) {
+  PB<T> b = make_batch_params<T>(m, U, nullptr, nullptr, nullptr, 0.0);
+  b.wpb = 4;
+  const int nblocks = (b.ntiles + 3) / 4;
+  hipLaunchKernelGGL((k_cart2d_batch_cfl<T>), dim3(nblocks), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_min_finalize_batch, dim3(m->bt.ninst), dim3(256), 0, s, m->dtpart,
+                     m->bt.inst_tile0, cfl, dt_dev);
+  return hipGetLastError();
+}
+
+template <typename T>
+void fill_inst(const BatchDesc& d, int rows, void* out_records) {
+  BInst<T>* r = static_cast<BInst<T>*>(out_records);
+  const double s3 = 1.7320508075688772;
+  int off = 0, tile0 = 0;
+  for (int i = 0; i < d.ninst; ++i) {
+    const int nx = d.nx[i], ny = d.ny[i];
+    const double hx = d.hx[i], hy = d.hy[i];
+    BInst<T> b{};
+    b.nx = nx;
+    b.ny = ny;
+    b.tiles_x = (nx + kCols - 1) / kCols;
+    b.rows = rows < ny ? rows : ny;
+    b.off = off;
+    b.tile0 = tile0;
+    b.ntiles = b.tiles_x * ((ny + b.rows - 1) / b.rows);
+    b.cmx = (T)(0.5 / hx);
+    b.cmy = (T)(0.5 / hy);
+    b.cgx = (T)(3.0 / (hx * hx));
+    b.cgy = (T)(3.0 / (hy * hy));
+    b.ccr = (T)(s3 / (hx * hy));
+    b.hx2 = (T)(0.5 * hx);
+    b.hy2 = (T)(0.5 * hy);
+    b.qx = (T)(0.5 * hx / s3);
+    b.qy = (T)(0.5 * hy / s3);
+    b.ihx = 1.0 / hx;
+    b.ihy = 1.0 / hy;
+    r[i] = b;
+    off += nx * ny;
+    tile0 += b.ntiles;
+  }
+}
+
 }  // namespace
+
+// Host-side instance records and tile tables of a batch for `rows` rows per
+// tile.  records: ninst records of the precision's layout (batch_record_size
+// bytes each); tile_inst[ntiles]; tile0[ninst + 1].  Returns the tile count.
+size_t batch_record_size(bool f64) { return f64 ? sizeof(BInst<double>) : sizeof(BInst<float>); }
+
+int batch_tables(const BatchDesc& d, bool f64, int rows, void* records,
+                 std::vector<int>& tile_inst, std::vector<int>& tile0) {
+  if (f64)
+    fill_inst<double>(d, rows, records);
+  else
+    fill_inst<float>(d, rows, records);
+  tile_inst.clear();
+  tile0.assign(1, 0);
+  for (int i = 0; i < d.ninst; ++i) {
+    const int tx = (d.nx[i] + kCols - 1) / kCols;
+    const int r = rows < d.ny[i] ? rows : d.ny[i];
+    const int nt = tx * ((d.ny[i] + r - 1) / r);
+    for (int t = 0; t < nt; ++t) tile_inst.push_back(i);
+    tile0.push_back(tile0.back() + nt);
+  }
+  return (int)tile_inst.size();
+}
+
+hipError_t launch_cart2d_batch(const dg_mesh* m, int mode, const void* in, const void* u0,
+                               void* out, const double* dt_dev, double dt_host, double cfl,
+                               double* dt_next, hipStream_t s) {
+  if (m->cfg.precision == DG_FP64)
+    return launch_batch_t<double>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+  return launch_batch_t<float>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+}
+
+hipError_t launch_cart2d_batch_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                                   hipStream_t s) {
+  if (m->cfg.precision == DG_FP64) return batch_cfl_t<double>(m, U, cfl, dt_dev, s);
+  return batch_cfl_t<float>(m, U, cfl, dt_dev, s);
+}
 
 hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                          const double* dt_dev, double dt_host, double cfl, double* dt_next,

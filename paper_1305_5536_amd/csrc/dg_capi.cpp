@@ -3,10 +3,13 @@
 // update happens here; every step runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 #include <string>
 
 #include "dg.h"
@@ -66,12 +69,71 @@ static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void
   hipError_t e;
   if (m->kind == 1)
     e = launch_facelist(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+  else if (m->kind == 2)
+    e = launch_cart2d_batch(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else if (m->dim == 2)
     e = launch_cart2d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else
     e = launch_cart3d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return DG_OK;
+}
+
+// Forward tile tables of a batch at its current rows per tile.
+static dg_status batch_upload(dg_mesh* m) {
+  Batch& b = m->bt;
+  const bool f64 = m->cfg.precision == DG_FP64;
+  std::vector<char> rec(batch_record_size(f64) * b.ninst);
+  std::vector<int> ti, t0;
+  b.ntiles = batch_tables(b.d, f64, b.rows, rec.data(), ti, t0);
+  hipError_t e = hipMemcpy(b.inst, rec.data(), rec.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b.tile_inst, ti.data(), sizeof(int) * ti.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b.inst_tile0, t0.data(), sizeof(int) * t0.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch tables");
+  return DG_OK;
+}
+
+// Adjoint tables (16 x 16 tiles) of one or more 2D Cartesian instances.
+static dg_status adjoint_tables(dg_mesh* m, const BatchDesc& d, bool batched) {
+  std::vector<AdjInst> ai(d.ninst);
+  std::vector<int> ti;
+  int tile0 = 0;
+  for (int i = 0; i < d.ninst; ++i) {
+    AdjInst a{};
+    a.nx = d.nx[i];
+    a.ny = d.ny[i];
+    a.off = (int)d.off[i];
+    a.tx0 = tile0;
+    a.tiles_x = (a.nx + kAdjTile - 1) / kAdjTile;
+    a.tiles_y = (a.ny + kAdjTile - 1) / kAdjTile;
+    a.hx = d.hx[i];
+    a.hy = d.hy[i];
+    ai[i] = a;
+    for (int t = 0; t < a.tiles_x * a.tiles_y; ++t) ti.push_back(i);
+    tile0 += a.tiles_x * a.tiles_y;
+  }
+  m->adj_tiles = tile0;
+  hipError_t e = hipMalloc(&m->adj_inst, sizeof(AdjInst) * ai.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(m->adj_inst, ai.data(), sizeof(AdjInst) * ai.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && batched) {
+    e = hipMalloc(&m->bt.adj_tile_inst, sizeof(int) * ti.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(m->bt.adj_tile_inst, ti.data(), sizeof(int) * ti.size(),
+                    hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "dg_mesh_create: adjoint tables");
+  return DG_OK;
+}
+
+static void drop_graph(dg_mesh* m) {
+  if (m->run.exec) (void)hipGraphExecDestroy(m->run.exec);
+  if (m->run.graph) (void)hipGraphDestroy(m->run.graph);
+  m->run.exec = nullptr;
+  m->run.graph = nullptr;
+  m->run.key.clear();
 }
 
 }  // namespace dg
@@ -109,7 +171,25 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   } else {
     return einval("dg_mesh_create: unknown physics");
   }
-  if (d->kind != 0 && d->kind != 1) return einval("dg_mesh_create: unknown mesh kind");
+  if (d->kind != 0 && d->kind != 1 && d->kind != 2)
+    return einval("dg_mesh_create: unknown mesh kind");
+  if (d->kind == 2) {
+    if (cfg->physics != DG_EULER) {
+      set_error("dg_mesh_create: batches are built for 2D Euler only");
+      return DG_EUNSUPPORTED;
+    }
+    if (d->dim != 2) return einval("dg_mesh_create: batch instances are 2D (dim = 2)");
+    if (d->ninst < 1 || d->ninst > (1 << 20) || !d->inst_n || !d->inst_box)
+      return einval("dg_mesh_create: batch needs ninst >= 1, inst_n and inst_box");
+    for (int i = 0; i < d->ninst; ++i) {
+      if (d->inst_n[2 * i] < 1 || d->inst_n[2 * i + 1] < 1 || d->inst_n[2 * i] > (1 << 16) ||
+          d->inst_n[2 * i + 1] > (1 << 16))
+        return einval("dg_mesh_create: bad instance cell count");
+      const double* bx = d->inst_box + 4 * i;
+      if (!(bx[2] > bx[0]) || !(bx[3] > bx[1]))
+        return einval("dg_mesh_create: instance box needs hi > lo");
+    }
+  }
   if (d->kind == 1 && d->dim != 2) {
     set_error("dg_mesh_create: face-list meshes are 2D only");
     return DG_EUNSUPPORTED;
@@ -149,22 +229,17 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
     if (cfg->physics == DG_EULER) {
-      dg::AdjInst ai{};
-      ai.nx = m->c2.nx;
-      ai.ny = m->c2.ny;
-      ai.off = 0;
-      ai.tx0 = 0;
-      ai.tiles_x = (ai.nx + dg::kAdjTile - 1) / dg::kAdjTile;
-      ai.tiles_y = (ai.ny + dg::kAdjTile - 1) / dg::kAdjTile;
-      ai.hx = m->c2.hx;
-      ai.hy = m->c2.hy;
-      m->adj_tiles = ai.tiles_x * ai.tiles_y;
-      hipError_t e2 = hipMalloc(&m->adj_inst, sizeof(dg::AdjInst));
-      if (e2 == hipSuccess)
-        e2 = hipMemcpy(m->adj_inst, &ai, sizeof(dg::AdjInst), hipMemcpyHostToDevice);
-      if (e2 != hipSuccess) {
+      BatchDesc one;
+      one.ninst = 1;
+      one.nx = {m->c2.nx};
+      one.ny = {m->c2.ny};
+      one.hx = {m->c2.hx};
+      one.hy = {m->c2.hy};
+      one.off = {0, m->ncells};
+      dg_status st = adjoint_tables(m, one, false);
+      if (st != DG_OK) {
         dg_mesh_destroy(m);
-        return hip_fail(e2, "dg_mesh_create: adjoint table");
+        return st;
       }
     }
   } else if (d->kind == 0 && d->dim == 3) {
@@ -181,6 +256,45 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c3.planes_per_tile = default_rows((int64_t)m->c3.tiles_x * d->n[1], d->n[2]);
     m->c3.tiles_z = (int)((d->n[2] + m->c3.planes_per_tile - 1) / m->c3.planes_per_tile);
     nwaves = (int64_t)m->c3.tiles_x * m->c3.tiles_y * m->c3.tiles_z;
+  } else if (d->kind == 2) {
+    m->ncoef = 12;
+    BatchDesc& bd = m->bt.d;
+    bd.ninst = d->ninst;
+    bd.off.assign(1, 0);
+    int64_t maxtiles = 0;
+    for (int i = 0; i < d->ninst; ++i) {
+      const int nx = d->inst_n[2 * i], ny = d->inst_n[2 * i + 1];
+      const double* bx = d->inst_box + 4 * i;
+      bd.nx.push_back(nx);
+      bd.ny.push_back(ny);
+      bd.hx.push_back((bx[2] - bx[0]) / nx);
+      bd.hy.push_back((bx[3] - bx[1]) / ny);
+      bd.off.push_back(bd.off.back() + (int64_t)nx * ny);
+      maxtiles += (int64_t)((nx + 59) / 60) * ny;  // one row per tile
+    }
+    m->ncells = bd.off.back();
+    if (m->ncells * 12 >= ((int64_t)1 << 31)) {
+      delete m;
+      return einval("dg_mesh_create: batch too large for 32-bit indexing");
+    }
+    m->bt.ninst = d->ninst;
+    const char* env = std::getenv("DG_TILE_ROWS");
+    m->bt.rows = env && std::atoi(env) > 0 ? std::atoi(env) : 16;
+    const bool f64 = cfg->precision == DG_FP64;
+    hipError_t e2 = hipMalloc(&m->bt.inst, batch_record_size(f64) * d->ninst);
+    if (e2 == hipSuccess) e2 = hipMalloc(&m->bt.tile_inst, sizeof(int) * maxtiles);
+    if (e2 == hipSuccess) e2 = hipMalloc(&m->bt.inst_tile0, sizeof(int) * (d->ninst + 1));
+    if (e2 != hipSuccess) {
+      dg_mesh_destroy(m);
+      return hip_fail(e2, "dg_mesh_create: batch tables");
+    }
+    dg_status st = batch_upload(m);
+    if (st == DG_OK) st = adjoint_tables(m, bd, true);
+    if (st != DG_OK) {
+      dg_mesh_destroy(m);
+      return st;
+    }
+    nwaves = maxtiles;
   } else {
     m->ncoef = 12;
     dg_status st = facelist_create(m, d);
@@ -200,7 +314,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   // partial minima: one per wave of the fused stage, or one per 64 cells of
   // the stand-alone CFL kernel (whole 256-thread blocks write)
   // (the finest tiling, one row per wave, has at most ncells/60 + rows waves)
-  nwaves = std::max<int64_t>(nwaves, (m->ncells + 59) / 60 + (m->dim == 2 ? m->c2.ny : m->c3.ny * m->c3.nz));
+  if (m->kind == 0)
+    nwaves = std::max<int64_t>(nwaves, (m->ncells + 59) / 60 +
+                                           (m->dim == 2 ? m->c2.ny : m->c3.ny * m->c3.nz));
   m->ndtpart = (int)std::max<int64_t>(nwaves, 4 * ((m->ncells + 255) / 256));
   if (e == hipSuccess) e = hipMalloc(&m->dtpart, sizeof(double) * m->ndtpart);
 
@@ -217,6 +333,13 @@ void dg_mesh_destroy(dg_mesh_t m) {
   if (!m) return;
   (void)hipDeviceSynchronize();
   if (m->kind == 1) facelist_destroy(m);
+  drop_graph(m);
+  if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  (void)hipFree(m->run_ws);
+  (void)hipFree(m->bt.inst);
+  (void)hipFree(m->bt.tile_inst);
+  (void)hipFree(m->bt.inst_tile0);
+  (void)hipFree(m->bt.adj_tile_inst);
   (void)hipFree(m->v1);
   (void)hipFree(m->tmp);
   (void)hipFree(m->ws_a);
@@ -317,6 +440,8 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
   hipStream_t s = (hipStream_t)stream;
   if (m->kind == 1)
     e = launch_facelist_cfl(m, U, cfl, dt_dev, s);
+  else if (m->kind == 2)
+    e = launch_cart2d_batch_cfl(m, U, cfl, dt_dev, s);
   else if (m->dim == 2)
     e = launch_cart2d_cfl(m, U, cfl, dt_dev, s);
   else
@@ -326,14 +451,15 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
 }
 
 dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
-                          const void* lam_np1, void* lam_n, void* stream) {
+                          const double* dt_dev, const void* lam_np1, void* lam_n, void* stream) {
   if (!m || !U || !lam_np1 || !lam_n) return einval("dg_adjoint_step: NULL argument");
   m->ws_a_fresh = false;
-  if (m->kind != 0 || m->dim != 2 || !m->adj_inst) {
-    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes");
+  if (!m->adj_inst) {
+    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes and batches");
     return DG_EUNSUPPORTED;
   }
-  if (!std::isfinite(dt) || dt < 0) return einval("dg_adjoint_step: dt must be finite and >= 0");
+  if (!dt_dev && (!std::isfinite(dt) || dt < 0))
+    return einval("dg_adjoint_step: dt must be finite and >= 0");
   if (lam_n == lam_np1 || lam_n == U || lam_n == V1)
     return einval("dg_adjoint_step: lam_n must not alias U, V1 or lam_np1");
   hipStream_t s = (hipStream_t)stream;
@@ -343,21 +469,150 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
   if (e == hipSuccess && !m->adj_ws2) e = hipMalloc(&m->adj_ws2, bytes);
   if (e != hipSuccess) return hip_fail(e, "dg_adjoint_step: workspace allocation");
   if (!V1) {
-    dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, nullptr, dt, s);
+    dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, dt_dev, dt, s);
     if (st != DG_OK) return st;
     V1 = m->v1;
   }
-  e = launch_adjoint2d(m->adj_inst, nullptr, m->adj_tiles, (int)m->ncells, dg_state_len(m),
-                       m->cfg.precision == DG_FP64, m->cfg.limiter == DG_LIMITER_MINMOD,
-                       m->cfg.gamma, U, V1, nullptr, dt, lam_np1, lam_n, m->adj_ws1, m->adj_ws2,
-                       s);
+  e = launch_adjoint2d(m->adj_inst, m->kind == 2 ? m->bt.adj_tile_inst : nullptr, m->adj_tiles,
+                       (int)m->ncells, dg_state_len(m), m->cfg.precision == DG_FP64,
+                       m->cfg.limiter == DG_LIMITER_MINMOD, m->cfg.gamma, U, V1, dt_dev, dt,
+                       lam_np1, lam_n, m->adj_ws1, m->adj_ws2, s);
   if (e != hipSuccess) return hip_fail(e, "dg_adjoint_step launch");
+  return DG_OK;
+}
+
+dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double cfl,
+                 double* dt_hist, int ckpt_every, void* const* ckpt, void* const* v1_keep,
+                 int flags, void* stream) {
+  if (!m || !U_in || !U_out || !dt_hist) return einval("dg_run: NULL argument");
+  if (nsteps < 1) return einval("dg_run: nsteps must be >= 1");
+  if (!(cfl >= 0) || !std::isfinite(cfl)) return einval("dg_run: cfl must be finite and >= 0");
+  if (ckpt_every < 0 || (ckpt_every > 0 && nsteps > ckpt_every && !ckpt))
+    return einval("dg_run: checkpoints need ckpt_every >= 0 and a ckpt array");
+  if (nsteps == 1 && U_out == U_in) return einval("dg_run: U_out may equal U_in only for >= 2 steps");
+  if (flags & ~DG_RUN_GRAPH) return einval("dg_run: unknown flag");
+  m->ws_a_fresh = false;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)m->ncoef * m->ncells * m->elem;
+  hipError_t e = hipSuccess;
+  if (!m->tmp) e = hipMalloc(&m->tmp, bytes);
+  if (e == hipSuccess && !m->run_ws) e = hipMalloc(&m->run_ws, bytes);
+  if (e != hipSuccess) return hip_fail(e, "dg_run: workspace allocation");
+  const int nd = m->kind == 2 ? m->bt.ninst : 1;
+  const int nck = ckpt_every > 0 ? (nsteps - 1) / ckpt_every : 0;
+
+  auto enqueue = [&](hipStream_t q) -> dg_status {
+    if (cfl > 0) {
+      dg_status st = dg_cfl_dt(m, U_in, cfl, dt_hist, q);
+      if (st != DG_OK) return st;
+    }
+    const void* cur = U_in;
+    for (int n = 0; n < nsteps; ++n) {
+      void* V1 = v1_keep ? v1_keep[n] : m->v1;
+      void* out;
+      if (n + 1 == nsteps)
+        out = U_out;
+      else if (ckpt_every > 0 && (n + 1) % ckpt_every == 0)
+        out = ckpt[(n + 1) / ckpt_every - 1];
+      else
+        out = cur == m->tmp ? m->run_ws : m->tmp;
+      const double* dtn = dt_hist + (int64_t)n * nd;
+      dg_status st = dispatch(m, kStage1, cur, nullptr, V1, dtn, 0.0, q);
+      if (st != DG_OK) return st;
+      m->ws_a_fresh = true;
+      m->ws_a_src = cur;
+      st = dispatch(m, kStage2, V1, cur, out, dtn, 0.0, q, cfl,
+                    cfl > 0 ? dt_hist + (int64_t)(n + 1) * nd : nullptr);
+      m->ws_a_fresh = false;
+      if (st != DG_OK) return st;
+      cur = out;
+    }
+    return DG_OK;
+  };
+
+  if (!(flags & DG_RUN_GRAPH)) return enqueue(s);
+
+  std::vector<const void*> key = {U_in, U_out, dt_hist, (const void*)(intptr_t)nsteps,
+                                  (const void*)(intptr_t)ckpt_every, (const void*)(intptr_t)flags};
+  int64_t cbits;
+  std::memcpy(&cbits, &cfl, sizeof(cbits));
+  key.push_back((const void*)(intptr_t)cbits);
+  for (int j = 0; j < nck; ++j) key.push_back(ckpt[j]);
+  if (v1_keep)
+    for (int n = 0; n < nsteps; ++n) key.push_back(v1_keep[n]);
+  else
+    key.push_back(nullptr);
+  if (!m->run.exec || key != m->run.key) {
+    drop_graph(m);
+    if (!m->cap_stream) {
+      e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "dg_run: capture stream");
+    }
+    e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "dg_run: begin capture");
+    dg_status st = enqueue(m->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(m->cap_stream, &g);
+    if (st != DG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "dg_run: end capture");
+    m->run.graph = g;
+    e = hipGraphInstantiate(&m->run.exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(m);
+      return hip_fail(e, "dg_run: instantiate graph");
+    }
+    m->run.key = key;
+  }
+  e = hipGraphLaunch(m->run.exec, s);
+  if (e != hipSuccess) return hip_fail(e, "dg_run: graph launch");
+  return DG_OK;
+}
+
+int dg_ninst(dg_mesh_t m) { return m ? (m->kind == 2 ? m->bt.ninst : 1) : -1; }
+
+dg_status dg_instance_offsets(dg_mesh_t m, int64_t* off) {
+  if (!m || !off) return einval("dg_instance_offsets: NULL argument");
+  if (m->kind != 2) {
+    off[0] = 0;
+    off[1] = m->ncells;
+    return DG_OK;
+  }
+  for (int i = 0; i <= m->bt.ninst; ++i) off[i] = m->bt.d.off[i];
+  return DG_OK;
+}
+
+dg_status dg_set_launch(dg_mesh_t m, int waves_per_group, int grid_waves) {
+  if (!m) return einval("dg_set_launch: NULL handle");
+  if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+    return einval("dg_set_launch: waves_per_group must be 1, 2 or 4");
+  if (grid_waves < 0) return einval("dg_set_launch: grid_waves must be >= 0");
+  if (m->kind != 2) return DG_OK;
+  m->bt.wpb = waves_per_group;
+  m->bt.grid_waves = grid_waves;
+  drop_graph(m);
+  return DG_OK;
+}
+
+dg_status dg_get_launch(dg_mesh_t m, int* waves_per_group, int* grid_waves) {
+  if (!m || !waves_per_group || !grid_waves) return einval("dg_get_launch: NULL argument");
+  *waves_per_group = m->kind == 2 ? m->bt.wpb : 4;
+  *grid_waves = m->kind == 2 ? m->bt.grid_waves : 0;
   return DG_OK;
 }
 
 dg_status dg_set_tiling(dg_mesh_t m, int rows) {
   if (!m) return einval("dg_set_tiling: NULL handle");
   if (rows < 0) return einval("dg_set_tiling: rows must be >= 0");
+  drop_graph(m);
+  if (m->kind == 2) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "dg_set_tiling: synchronise");
+    m->bt.rows = rows ? rows : 16;
+    return batch_upload(m);
+  }
   if (m->kind != 0) return DG_OK;
   if (m->dim == 2) {
     int r = rows ? std::min(rows, m->c2.ny) : default_rows(m->c2.tiles_x, m->c2.ny);
@@ -374,6 +629,7 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
 
 int dg_get_tiling(dg_mesh_t m) {
   if (!m) return -1;
+  if (m->kind == 2) return m->bt.rows;
   if (m->kind != 0) return 0;
   return m->dim == 2 ? m->c2.rows_per_tile : m->c3.planes_per_tile;
 }

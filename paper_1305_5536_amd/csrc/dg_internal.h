@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "dg.h"
 
@@ -51,10 +52,34 @@ struct AdjInst {
   double hx, hy;
 };
 
-template <typename T>
-struct Workspace {
-  T* v1 = nullptr;       // stage-1 output
-  T* tmp = nullptr;      // staging for in-place steps
+// Host copy of a batch of 2D Cartesian instances (mesh kind 2).
+struct BatchDesc {
+  int ninst = 0;
+  std::vector<int> nx, ny;
+  std::vector<double> hx, hy;
+  std::vector<int64_t> off;  // first cell of each instance, plus the total
+};
+
+// Device tables and launch shape of a batch.
+struct Batch {
+  BatchDesc d;
+  int ninst = 0;
+  int rows = 16;          // rows per forward tile (all instances)
+  int ntiles = 0;         // forward tiles at the current rows
+  int wpb = 4;            // waves per workgroup of the batched stage kernel
+  int grid_waves = 0;     // > 0: persistent launch of this many waves
+  void* inst = nullptr;   // device instance records (BInst<T>[ninst])
+  int* tile_inst = nullptr;   // device, forward tile -> instance
+  int* inst_tile0 = nullptr;  // device, first forward tile of each instance (+ total)
+  int* adj_tile_inst = nullptr;  // device, adjoint tile -> instance
+};
+
+// Cached hipGraph of a dg_run launch sequence and the arguments it was
+// captured with.
+struct RunGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
 };
 
 }  // namespace dg
@@ -84,6 +109,10 @@ struct dg_mesh {
   int adj_tiles = 0;
   void* adj_ws1 = nullptr;          // adjoint workspaces (lazy)
   void* adj_ws2 = nullptr;
+  dg::Batch bt;                     // kind 2
+  void* run_ws = nullptr;           // dg_run: second ping-pong buffer (lazy)
+  hipStream_t cap_stream = nullptr; // dg_run: capture stream (lazy)
+  dg::RunGraph run;
 };
 
 namespace dg {
@@ -99,6 +128,14 @@ hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void*
                          hipStream_t s);
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
+hipError_t launch_cart2d_batch(const dg_mesh* m, int mode, const void* in, const void* u0,
+                               void* out, const double* dt_dev, double dt_host, double cfl,
+                               double* dt_next, hipStream_t s);
+hipError_t launch_cart2d_batch_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                                   hipStream_t s);
+size_t batch_record_size(bool f64);
+int batch_tables(const BatchDesc& d, bool f64, int rows, void* records,
+                 std::vector<int>& tile_inst, std::vector<int>& tile0);
 hipError_t launch_adjoint2d(const void* inst, const int* tile_inst, int ntiles, int nc,
                             int64_t total, bool f64, bool lim, double gamma, const void* U,
                             const void* V1, const double* dt_dev, double dt_host,

@@ -74,6 +74,21 @@ class Solver:
             d.box[0], d.box[1] = float(mesh["box"][0]), float(mesh["box"][1])
             self._keep = [arrs, fc, fs]
             self.ncells = int(d.ncells)
+        elif mesh["kind"] == "batch":
+            n = np.ascontiguousarray(mesh["n"], dtype=np.int32).reshape(-1, 2)
+            box = mesh.get("box")
+            if box is None:
+                box = np.tile(np.array([0.0, 0.0, 1.0, 1.0]), (len(n), 1))
+            box = np.ascontiguousarray(box, dtype=np.float64).reshape(-1, 4)
+            if len(box) != len(n):
+                raise ValueError("batch: one box per instance")
+            d.dim = 2
+            d.kind = 2
+            d.ninst = len(n)
+            d.inst_n = n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.inst_box = _f64p(box)
+            self._keep = [n, box]
+            self.ncells = int((n[:, 0].astype(np.int64) * n[:, 1]).sum())
         else:
             raise ValueError(f"unknown mesh kind {mesh['kind']!r}")
         h = ctypes.c_void_p()
@@ -84,6 +99,10 @@ class Solver:
         self._keep = []
         self.ncoef = C.lib().dg_ncoef(h)
         self.state_len = C.lib().dg_state_len(h)
+        self.ninst = C.lib().dg_ninst(h)
+        off = (ctypes.c_int64 * (self.ninst + 1))()
+        C.check(C.lib().dg_instance_offsets(h, off), "dg_instance_offsets")
+        self.offsets = np.array(off[:], dtype=np.int64)
 
     # -------------------------------------------------------------- helpers
     def _check_state(self, U: torch.Tensor, name: str = "U") -> None:
@@ -98,6 +117,19 @@ class Solver:
 
     def to_device(self, U: np.ndarray) -> torch.Tensor:
         return torch.as_tensor(np.ascontiguousarray(U).reshape(-1)).to(self.device, self.dtype)
+
+    def pack(self, states) -> torch.Tensor:
+        """Device state of a batch from one (ncoef * n_i) host array per instance."""
+        parts = [np.asarray(u, dtype=np.float64).reshape(self.ncoef, -1) for u in states]
+        if len(parts) != self.ninst:
+            raise ValueError(f"expected {self.ninst} instance states")
+        return self.to_device(np.concatenate(parts, axis=1))
+
+    def unpack(self, U: torch.Tensor):
+        """Per-instance host arrays (ncoef * n_i, float64) of a batch state."""
+        A = U.double().cpu().numpy().reshape(self.ncoef, -1)
+        return [A[:, self.offsets[i]:self.offsets[i + 1]].reshape(-1).copy()
+                for i in range(self.ninst)]
 
     # ---------------------------------------------------------- entry points
     def rhs(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -120,19 +152,22 @@ class Solver:
         out = self.empty() if out is None else out
         self._check_state(out, "out")
         if isinstance(dt, torch.Tensor):
-            if dt.dtype != torch.float64 or dt.device != self.device or dt.numel() != 1:
-                raise ValueError("device dt must be a one-element float64 tensor")
+            self._check_dt(dt)
             st = C.lib().dg_step_devdt(self._h, _ptr(U), _ptr(out), _ptr(dt), _stream())
         else:
             st = C.lib().dg_step(self._h, _ptr(U), _ptr(out), float(dt), _stream())
         C.check(st, "dg_step")
         return out
 
-    @staticmethod
-    def _dt_args(dt):
+    def _check_dt(self, dt: torch.Tensor, n: int = 1) -> None:
+        if (dt.dtype != torch.float64 or dt.device != self.device or not dt.is_contiguous()
+                or dt.numel() < n * self.ninst):
+            raise ValueError(f"device dt must be a contiguous float64 tensor of "
+                             f"{n * self.ninst} elements on {self.device}")
+
+    def _dt_args(self, dt):
         if isinstance(dt, torch.Tensor):
-            if dt.dtype != torch.float64 or dt.numel() != 1:
-                raise ValueError("device dt must be a one-element float64 tensor")
+            self._check_dt(dt)
             return 0.0, _ptr(dt)
         return float(dt), None
 
@@ -156,21 +191,61 @@ class Solver:
                                   _stream()), "dg_stage2")
         return out
 
-    def adjoint_step(self, U: torch.Tensor, dt: float, lam_next: torch.Tensor,
+    def adjoint_step(self, U: torch.Tensor, dt, lam_next: torch.Tensor,
                      V1: torch.Tensor | None = None, out: torch.Tensor | None = None):
-        """lam_n = (d step(U, dt)/dU)^T lam_next (dt frozen)."""
+        """lam_n = (d step(U, dt)/dU)^T lam_next (dt frozen; a float, or a device
+        float64 tensor with one value per instance)."""
         self._check_state(U)
         self._check_state(lam_next, "lam_next")
         out = self.empty() if out is None else out
         self._check_state(out, "out")
         v1 = None if V1 is None else _ptr(V1)
-        C.check(C.lib().dg_adjoint_step(self._h, _ptr(U), v1, float(dt), _ptr(lam_next),
-                                        _ptr(out), _stream()), "dg_adjoint_step")
+        h, d = self._dt_args(dt)
+        C.check(C.lib().dg_adjoint_step(self._h, _ptr(U), v1, h, d, _ptr(lam_next), _ptr(out),
+                                        _stream()), "dg_adjoint_step")
         return out
+
+    def run(self, U: torch.Tensor, nsteps: int, cfl: float = 0.0,
+            dt_hist: torch.Tensor | None = None, out: torch.Tensor | None = None,
+            ckpt_every: int = 0, ckpts=None, v1_keep=None, graph: bool = True):
+        """nsteps steps from U (dg_run).  cfl > 0: adaptive step sizes, written
+        to dt_hist ((nsteps + 1) x ninst); cfl = 0: dt_hist (nsteps x ninst) is
+        read.  Returns (U_out, dt_hist)."""
+        self._check_state(U)
+        out = self.empty() if out is None else out
+        self._check_state(out, "out")
+        if dt_hist is None:
+            if cfl <= 0:
+                raise ValueError("a fixed-step run needs dt_hist")
+            dt_hist = torch.empty((nsteps + 1) * self.ninst, dtype=torch.float64,
+                                  device=self.device)
+        self._check_dt(dt_hist, nsteps + (1 if cfl > 0 else 0))
+        ck = None
+        if ckpt_every > 0:
+            need = (nsteps - 1) // ckpt_every
+            ckpts = list(ckpts or [])
+            if len(ckpts) < need:
+                raise ValueError(f"need {need} checkpoint buffers")
+            for c in ckpts:
+                self._check_state(c, "checkpoint")
+            ck = (ctypes.c_void_p * max(need, 1))(*[_ptr(c) for c in ckpts[:need]])
+        v1 = None
+        if v1_keep is not None:
+            if len(v1_keep) < nsteps:
+                raise ValueError(f"need {nsteps} V1 buffers")
+            for c in v1_keep:
+                self._check_state(c, "v1_keep")
+            v1 = (ctypes.c_void_p * nsteps)(*[_ptr(c) for c in v1_keep[:nsteps]])
+        C.check(C.lib().dg_run(self._h, _ptr(U), _ptr(out), int(nsteps), float(cfl),
+                               _ptr(dt_hist), int(ckpt_every), ck, v1,
+                               C.DG_RUN_GRAPH if graph else 0, _stream()), "dg_run")
+        return out, dt_hist
 
     def cfl_dt(self, U: torch.Tensor, cfl: float, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check_state(U)
-        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        if out is None:
+            out = torch.empty(self.ninst, dtype=torch.float64, device=self.device)
+        self._check_dt(out)
         C.check(C.lib().dg_cfl_dt(self._h, _ptr(U), float(cfl), _ptr(out), _stream()),
                 "dg_cfl_dt")
         return out
@@ -182,6 +257,17 @@ class Solver:
     @tiling.setter
     def tiling(self, rows: int) -> None:
         C.check(C.lib().dg_set_tiling(self._h, int(rows)), "dg_set_tiling")
+
+    @property
+    def launch(self):
+        """(waves per workgroup, persistent grid waves) of the batched stage kernel."""
+        w, g = ctypes.c_int(), ctypes.c_int()
+        C.check(C.lib().dg_get_launch(self._h, ctypes.byref(w), ctypes.byref(g)), "dg_get_launch")
+        return w.value, g.value
+
+    @launch.setter
+    def launch(self, wg) -> None:
+        C.check(C.lib().dg_set_launch(self._h, int(wg[0]), int(wg[1])), "dg_set_launch")
 
     def check(self) -> None:
         """Synchronise and raise NonPhysicalState if a kernel met one."""
@@ -197,6 +283,12 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def batch(sizes, boxes=None) -> dict:
+    """Batch of periodic 2D Cartesian instances: sizes [(nx, ny), ...], boxes
+    [(lo_x, lo_y, hi_x, hi_y), ...] (default: the unit square)."""
+    return {"kind": "batch", "n": [tuple(int(v) for v in n) for n in sizes], "box": boxes}
 
 
 def cartesian(n, lo, hi) -> dict:
