@@ -210,9 +210,10 @@ dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double 
  * Intermediate states ping-pong through two state-sized workspaces of the
  * handle (allocated on the first call).
  * flags & DG_RUN_GRAPH: the whole sequence is captured once into a hipGraph,
- * cached on the handle for these arguments (pointer values included), and
- * replayed with one graph launch; the capture uses no memset or allocation.
- * A call with other arguments, dg_set_tiling or dg_set_launch re-captures. */
+ * cached on the handle for these arguments (pointer values included; up to 32
+ * argument sets, least recently used evicted), and replayed with one graph
+ * launch; the capture uses no memset or allocation.  dg_set_tiling and
+ * dg_set_launch drop the cache. */
 dg_status dg_run(dg_mesh_t mesh, const void* U_in, void* U_out, int nsteps, double cfl,
                  double* dt_hist, int ckpt_every, void* const* ckpt, void* const* v1_keep,
                  int flags, void* stream);

@@ -128,12 +128,16 @@ static dg_status adjoint_tables(dg_mesh* m, const BatchDesc& d, bool batched) {
   return DG_OK;
 }
 
+static void free_graph(RunGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
 static void drop_graph(dg_mesh* m) {
-  if (m->run.exec) (void)hipGraphExecDestroy(m->run.exec);
-  if (m->run.graph) (void)hipGraphDestroy(m->run.graph);
-  m->run.exec = nullptr;
-  m->run.graph = nullptr;
-  m->run.key.clear();
+  for (RunGraph& g : m->runs) free_graph(g);
+  m->runs.clear();
 }
 
 }  // namespace dg
@@ -542,8 +546,18 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
     for (int n = 0; n < nsteps; ++n) key.push_back(v1_keep[n]);
   else
     key.push_back(nullptr);
-  if (!m->run.exec || key != m->run.key) {
-    drop_graph(m);
+  RunGraph* hit = nullptr;
+  for (RunGraph& g : m->runs)
+    if (g.key == key) hit = &g;
+  if (!hit) {
+    if ((int)m->runs.size() >= kMaxRunGraphs) {
+      auto old = std::min_element(m->runs.begin(), m->runs.end(),
+                                  [](const RunGraph& a, const RunGraph& b) {
+                                    return a.last_use < b.last_use;
+                                  });
+      free_graph(*old);
+      m->runs.erase(old);
+    }
     if (!m->cap_stream) {
       e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "dg_run: capture stream");
@@ -551,22 +565,24 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
     e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "dg_run: begin capture");
     dg_status st = enqueue(m->cap_stream);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(m->cap_stream, &g);
+    RunGraph g;
+    e = hipStreamEndCapture(m->cap_stream, &g.graph);
     if (st != DG_OK) {
-      if (g) (void)hipGraphDestroy(g);
+      free_graph(g);
       return st;
     }
     if (e != hipSuccess) return hip_fail(e, "dg_run: end capture");
-    m->run.graph = g;
-    e = hipGraphInstantiate(&m->run.exec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-      drop_graph(m);
+      free_graph(g);
       return hip_fail(e, "dg_run: instantiate graph");
     }
-    m->run.key = key;
+    g.key = key;
+    m->runs.push_back(g);
+    hit = &m->runs.back();
   }
-  e = hipGraphLaunch(m->run.exec, s);
+  hit->last_use = ++m->run_clock;
+  e = hipGraphLaunch(hit->exec, s);
   if (e != hipSuccess) return hip_fail(e, "dg_run: graph launch");
   return DG_OK;
 }

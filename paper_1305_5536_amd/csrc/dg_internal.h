@@ -80,7 +80,9 @@ struct RunGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> key;
+  uint64_t last_use = 0;
 };
+constexpr int kMaxRunGraphs = 32;
 
 }  // namespace dg
 
@@ -112,7 +114,8 @@ struct dg_mesh {
   dg::Batch bt;                     // kind 2
   void* run_ws = nullptr;           // dg_run: second ping-pong buffer (lazy)
   hipStream_t cap_stream = nullptr; // dg_run: capture stream (lazy)
-  dg::RunGraph run;
+  std::vector<dg::RunGraph> runs;  // dg_run graph cache (least recently used evicted)
+  uint64_t run_clock = 0;
 };
 
 namespace dg {
