@@ -50,9 +50,10 @@ FACELIST_BYTES_PER_CELL_STAGE = {"fp64": 464, "fp32": 232}
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--config", choices=["c1", "c2", "c3", "c4"], default="c2",
+    p.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5"], default="c2",
                    help="c2: 2D Euler shear layer 2048^2 (default); c1: isentropic vortex "
-                        "64^2; c3: 3D MHD 256^3; c4: static Voronoi mesh of 1M cells")
+                        "64^2; c3: 3D MHD 256^3; c4: static Voronoi mesh of 1M cells; c5: "
+                        "256 batched instances N^2, N in {64..512}, with the adjoint")
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--n", type=int, default=None, help="cells per side")
@@ -65,7 +66,7 @@ def parse():
     # (cells per side or cells, timed steps, warm-up steps, oracle steps of the
     # CPU baseline sized to about 10-30 s of host work)
     dflt = {"c1": (64, 100, 10, 8000), "c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 12),
-            "c4": (1000000, 100, 5, 50)}[a.config]
+            "c4": (1000000, 100, 5, 50), "c5": (256, 200, 20, 800)}[a.config]
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
@@ -323,13 +324,218 @@ def bench_c4(a):
     return out
 
 
+def _pool_map(fn, args):
+    """Run host-side input generation in worker processes (forked before the
+    GPU is touched; the workers only run numpy)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.starmap(fn, args)
+
+
+def bench_c5(a):
+    """256 batched instances: forward throughput (one graph of batched launches)
+    against one launch per instance, then the differentiable rollout
+    (fwd+adj/fwd), the FP32-vs-FP64 gradient error and a central difference."""
+    import workloads as W
+    ninst, K, kseg = a.n, a.steps, 20
+    sizes = W.batched_instances(ninst)
+    t0 = time.perf_counter()
+    log(f"generating {ninst} instance states ({sum(n * n for n in sizes)} cells)")
+    states = _pool_map(W.batched_state, [(N, 2005 + i) for i, N in enumerate(sizes)])
+    uniq = sorted(set(sizes))
+    tg = dict(zip(uniq, _pool_map(W.batched_state, [(N, 3005) for N in uniq])))
+    targets = [tg[N][:N * N] for N in sizes]
+    tgen = time.perf_counter() - t0
+    log(f"generated in {tgen:.0f} s")
+
+    import numpy as np
+    import torch
+
+    from paper_1305_5536_amd import autotune
+    from paper_1305_5536_amd.rollout import rollout
+    from paper_1305_5536_amd.solver import Solver, batch, cartesian
+    G = 5.0 / 3.0
+    shapes = [(N, N) for N in sizes]
+    ncells = sum(N * N for N in sizes)
+    st = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def loss_fn(s):
+        tgt = torch.as_tensor(np.concatenate(targets)).to(s.device, s.dtype)
+        vol = torch.cat([torch.full((N * N,), 1.0 / (N * N), dtype=s.dtype) for N in sizes])
+        vol = vol.to(s.device)
+        return lambda out: 0.5 * (vol * (out[:ncells] - tgt) ** 2).sum()
+
+    s = Solver(batch(shapes), precision="fp32", limiter=True, gamma=G)
+    U0 = s.pack(states)
+    log("autotuning the batched launch")
+    tune = autotune.autotune_batch(s, U0, shapes)
+    log(f"tuned: rows {tune['rows']}, waves/group {tune['wpb']}, grid {tune['grid']}")
+    # forward: the whole K-step sequence as one graph of batched launches
+    out, dth = s.run(U0, K, cfl=0.3, graph=True)  # captures the graph
+    torch.cuda.synchronize()
+    e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+    e0.record(st)
+    s.run(U0, K, cfl=0.3, out=out, dt_hist=dth, graph=True)
+    e1.record(st)
+    s.run(U0, K, cfl=0.3, out=out, dt_hist=dth, graph=False)
+    e2.record(st)
+    torch.cuda.synchronize()
+    s.check()
+    t_fwd = e0.elapsed_time(e1) * 1e-3
+    t_fwd_nograph = e1.elapsed_time(e2) * 1e-3
+    value = ncells * 2 * K / t_fwd
+    # per-stage kernel times for the roofline (batched stage kernels, device dt)
+    V1, Un, U = s.empty(), s.empty(), U0.clone()
+    dt = s.cfl_dt(U, 0.3)
+    for _ in range(a.warmup):
+        s.stage1(U, dt, V1)
+        s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt)
+        U, Un = Un, U
+    nst = 20
+    evs = [ev() for _ in range(3 * nst)]
+    for k in range(nst):
+        evs[3 * k].record(st)
+        s.stage1(U, dt, V1)
+        evs[3 * k + 1].record(st)
+        s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt)
+        evs[3 * k + 2].record(st)
+        U, Un = Un, U
+    torch.cuda.synchronize()
+    t1 = sum(evs[3 * k].elapsed_time(evs[3 * k + 1]) for k in range(nst)) / nst * 1e-3
+    t2 = sum(evs[3 * k + 1].elapsed_time(evs[3 * k + 2]) for k in range(nst)) / nst * 1e-3
+    del V1, Un, U
+    # one launch per instance per stage: the same kernels on 256 single meshes
+    log("timing one launch per instance")
+    singles = [Solver(cartesian((N, N), (0.0, 0.0), (1.0, 1.0)), precision="fp32",
+                      limiter=True, gamma=G) for N in sizes]
+    Ui = [sg.to_device(u) for sg, u in zip(singles, states)]
+    Oi = [sg.empty() for sg in singles]
+    Di = [torch.empty(K + 1, dtype=torch.float64, device=s.device) for _ in singles]
+    for sg, u, o, d in zip(singles, Ui, Oi, Di):
+        sg.run(u, 2, cfl=0.3, out=o, dt_hist=d, graph=False)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for sg, u, o, d in zip(singles, Ui, Oi, Di):
+        sg.run(u, K, cfl=0.3, out=o, dt_hist=d, graph=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_per = e0.elapsed_time(e1) * 1e-3
+    same = all(np.array_equal(o.cpu().numpy(), b) for o, b in zip(Oi[:4], s.unpack(out)[:4]))
+    for sg in singles:
+        sg.close()
+    del singles, Ui, Oi, Di
+    torch.cuda.empty_cache()
+    # differentiable rollout: forward with checkpoints + backward with recompute
+    log("timing forward + adjoint")
+    loss = loss_fn(s)
+    for rep in range(2):  # the first pass captures the segment graphs
+        U = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        o, _ = rollout(s, U, K, k=kseg)
+        L = loss(o)
+        e1.record(st)
+        L.backward()
+        e2.record(st)
+        torch.cuda.synchronize()
+    t_ckfwd = e0.elapsed_time(e1) * 1e-3
+    t_bwd = e1.elapsed_time(e2) * 1e-3
+    g32 = U.grad.double().cpu().numpy().reshape(4, 3, -1)
+    dth_fixed = dth[:K * ninst].clone()
+    del U, o, L, loss
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    # FP64 check run on the FP32 run's step schedule, and a central difference
+    log("FP64 gradient check run")
+    s64 = Solver(batch(shapes), precision="fp64", limiter=True, gamma=G)
+    s64.tiling = tune["rows"]
+    U0d = s64.pack(states)
+    loss64 = loss_fn(s64)
+    U = U0d.clone().requires_grad_(True)
+    e0.record(st)
+    o, _ = rollout(s64, U, K, k=kseg, dt_hist=dth_fixed)
+    L = loss64(o)
+    L.backward()
+    e1.record(st)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1) * 1e-3
+    g64 = U.grad.cpu().numpy()
+    rng = np.random.default_rng(4005)
+    v = s64.to_device(rng.standard_normal(s64.state_len)) * U0d.abs()
+    gv = float((U.grad * v).sum())
+    del U, o, L
+    eps = 1e-6
+    with torch.no_grad():
+        Lp = float(loss64(s64.run(U0d + eps * v, K, dt_hist=dth_fixed)[0]))
+        Lm = float(loss64(s64.run(U0d - eps * v, K, dt_hist=dth_fixed)[0]))
+    fd = (Lp - Lm) / (2 * eps)
+    s64.check()
+    g64 = g64.reshape(4, 3, -1)
+    l2m = float(np.linalg.norm(g32[:, 0] - g64[:, 0]) / np.linalg.norm(g64[:, 0]))
+    l2g = float(np.linalg.norm(g32[:, 1:] - g64[:, 1:]) / np.linalg.norm(g64[:, 1:]))
+    s64.close()
+    achieved = STAGE_VALUES[2] * 4 * ncells / t2 / 1e9
+    out_j = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": a.warmup, "ms_per_step": t_fwd / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{ninst} batched periodic 2D Euler instances N x N, N in "
+                               "{64,...,512} (seeded), gamma 5/3, HLL, limiter on, SSP-RK2 CFL 0.3, "
+                               f"{K} steps as one hipGraph; adjoint with checkpoints every {kseg}",
+                   "cells": ncells, "instances": ninst, "rk_stages_per_step": 2,
+                   "parallelism": "single GPU", "input_generation_s": tgen,
+                   "launch": {"rows": tune["rows"], "waves_per_group": tune["wpb"],
+                              "grid_waves": tune["grid"]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cart2d_batch stage 2 (+ per-instance dt reduction)",
+                     "bytes_per_launch": STAGE_VALUES[2] * 4 * ncells, "avg_launch_s": t2},
+        "kernels": {"stage1_avg_ms": t1 * 1e3, "stage2_avg_ms": t2 * 1e3,
+                    "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / t1 / 1e9},
+        "batched_vs_per_instance": {
+            "batched_graph_s": t_fwd, "batched_no_graph_s": t_fwd_nograph,
+            "per_instance_s": t_per, "speedup": t_per / t_fwd,
+            "per_instance_launches": ninst * K * 3, "results_identical": bool(same)},
+        "adjoint": {"fwd_s": t_fwd, "fwd_with_checkpoints_s": t_ckfwd, "bwd_s": t_bwd,
+                    "fwd_adj_over_fwd": (t_ckfwd + t_bwd) / t_fwd, "checkpoint_every": kseg,
+                    "grad_fp32_vs_fp64_rel_l2": {"means": l2m, "gradients": l2g},
+                    "fp64_fwd_adj_s": t64,
+                    "central_difference_fp64": {"eps": eps, "fd": fd, "adjoint": gv,
+                                                "rel": abs(fd - gv) / abs(gv)}},
+    }
+    if not a.no_cpu:
+        import oracle
+        log("timing the CPU oracle")
+        N0 = sizes[0]
+        om = oracle.Mesh.cartesian((N0, N0), (0.0, 0.0), (1.0, 1.0))
+        dtc = oracle.cfl_dt(om, states[0], G, 0.3)
+        tc = time.perf_counter()
+        Uc = states[0]
+        for _ in range(a.cpu_steps):
+            Uc = oracle.step(om, Uc, dtc, G, True)
+        el = time.perf_counter() - tc
+        out_j["cpu_baseline"] = {"value": N0 * N0 * 2 * a.cpu_steps / el,
+                                 "unit": "cell-updates/s", "cores": oracle.num_threads(),
+                                 "kind": "oracle",
+                                 "sample": f"{a.cpu_steps} limited SSP-RK2 steps of instance 0 "
+                                           f"({N0}x{N0}), FP64, {el:.1f} s"}
+    return out_j
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
-    out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4}[a.config](a)
+    out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+           "c5": bench_c5}[a.config](a)
     print(json.dumps(out))
 
 

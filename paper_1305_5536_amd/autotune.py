@@ -1,8 +1,11 @@
 """Autotuner for the launch shape of the stage kernels.
 
-The only tunable of the Cartesian kernels is how many rows (2D) or z-planes (3D)
-one wave marches through: more rows amortise the halo rows and the pipeline
-fill, fewer rows give more waves to fill the 256 CUs.  The tuner times one
+The tunable of the single-mesh Cartesian kernels is how many rows (2D) or
+z-planes (3D) one wave marches through: more rows amortise the halo rows and
+the pipeline fill, fewer rows give more waves to fill the 256 CUs.  Batches
+add the workgroup size (waves per workgroup) and the grid: one wave per tile,
+or a persistent grid of fewer waves that walk the tile list (tuned by
+coordinate descent: rows, then workgroup size, then grid).  The tuner times one
 SSP-RK2 step (stage 1 + stage 2, HIP events on the current stream) for each
 candidate on the caller's own state and keeps the fastest.  Results are cached
 in a JSON file keyed by GPU architecture, mesh shape, physics and precision
@@ -11,6 +14,7 @@ Results of the solver do not depend on the choice, only its speed.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
@@ -89,6 +93,49 @@ def autotune(solver, U, shape, candidates=DEFAULT_CANDIDATES, reps: int = 10,
     best = min(times, key=times.get)
     solver.tiling = best
     entry = {"rows": int(best), "times": {str(k): v for k, v in times.items()}}
+    if use_cache:
+        db[key] = entry
+        _store(db)
+    return entry
+
+
+BATCH_ROWS = (4, 8, 16, 32)
+BATCH_WPB = (1, 2, 4)
+BATCH_GRID = (0, 2048, 4096, 8192, 16384)
+
+
+def autotune_batch(solver, U, sizes, reps: int = 5, use_cache: bool = True) -> dict:
+    """Pick rows per tile, waves per workgroup and grid size for a batch solver
+    on state ``U`` (sizes: the instances' (nx, ny)); returns ``{"rows", "wpb",
+    "grid", "times"}`` and leaves the solver set to the choice."""
+    h = hashlib.sha1(repr([tuple(int(v) for v in n) for n in sizes]).encode()).hexdigest()[:16]
+    key = _key(solver, (len(sizes),)) + "|batch|" + h
+    db = _load() if use_cache else {}
+    if key in db:
+        e = db[key]
+        solver.tiling = int(e["rows"])
+        solver.launch = (int(e["wpb"]), int(e["grid"]))
+        return e
+    V1 = solver.empty()
+    Un = solver.empty()
+    dt = solver.cfl_dt(U, 0.3)
+    times = {}
+
+    def t(rows, wpb, grid):
+        solver.tiling = rows
+        solver.launch = (wpb, grid)
+        k = f"{rows},{wpb},{grid}"
+        if k not in times:
+            times[k] = time_step(solver, U, V1, Un, dt, reps)
+        return times[k]
+
+    best = (16, 4, 0)
+    best = min(((r, best[1], best[2]) for r in BATCH_ROWS), key=lambda c: t(*c))
+    best = min(((best[0], w, best[2]) for w in BATCH_WPB), key=lambda c: t(*c))
+    best = min(((best[0], best[1], g) for g in BATCH_GRID), key=lambda c: t(*c))
+    solver.tiling = best[0]
+    solver.launch = (best[1], best[2])
+    entry = {"rows": best[0], "wpb": best[1], "grid": best[2], "times": times}
     if use_cache:
         db[key] = entry
         _store(db)

@@ -198,3 +198,18 @@ def test_batch_arguments(torch_cuda):
     U = b.pack(_states([(8, 8), (5, 9)]))
     with pytest.raises(DGError):
         b.run(U, 1, cfl=0.3, out=U)
+
+
+def test_batch_autotuner(torch_cuda, tmp_path, monkeypatch):
+    from paper_1305_5536_amd import autotune
+    monkeypatch.setenv("DG_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    sizes = [(64, 64), (96, 96), (130, 40)]
+    b = _batch(sizes, precision="fp32")
+    U = b.pack(_states(sizes, seed0=900))
+    e = autotune.autotune_batch(b, U, sizes, reps=2)
+    assert e["rows"] in autotune.BATCH_ROWS and e["wpb"] in autotune.BATCH_WPB
+    assert e["grid"] in autotune.BATCH_GRID
+    assert b.tiling == e["rows"] and b.launch == (e["wpb"], e["grid"])
+    b2 = _batch(sizes, precision="fp32")
+    assert autotune.autotune_batch(b2, U, sizes)["rows"] == e["rows"]  # from the cache
+    assert b2.launch == (e["wpb"], e["grid"])
