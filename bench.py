@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--no-fp32", dest="also_fp32", action="store_false")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=None)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run 5 device copies of 1 GiB (the reference kernel that scales "
+                        "rocprofv3 FETCH_SIZE / WRITE_SIZE counts to bytes) and exit")
     a = p.parse_args()
     # (cells per side or cells, timed steps, warm-up steps, oracle steps of the
     # CPU baseline sized to about 10-30 s of host work)
@@ -72,6 +75,26 @@ def parse():
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
     a.cpu_steps = a.cpu_steps or dflt[3]
     return a
+
+
+def pmc_traffic(profile: str, kernel: str, shape: str, source: str):
+    """HBM bytes per launch of ``kernel`` measured with rocprofv3 --pmc
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated) as recorded in the committed
+    profile summary, or None when the kernel source has changed since."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    want = f"pmc_traffic_bytes_per_launch({kernel}, {shape}): "
+    traffic = None
+    for line in text.splitlines():
+        if line.startswith(want):
+            traffic = float(line[len(want):])
+        if line.startswith(f"kernel_source_sha256({source}): ") and line.split()[-1] != sha:
+            return None
+    return traffic
 
 
 def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3):
@@ -152,7 +175,10 @@ def bench_c2(a):
                                "P1 Taylor DG, HLL, limiter on, SSP-RK2 CFL 0.3",
                    "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, true>",
+                                             "2048x2048", "paper_1305_5536_amd/csrc/cart2d.hip")
+                                 if n == 2048 and a.precision == "fp64" else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
                      "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
         "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
@@ -528,12 +554,28 @@ def bench_c5(a):
     return out_j
 
 
+def copy_calibration():
+    """Five copies of a 1 GiB buffer: under rocprofv3 --pmc their FETCH_SIZE and
+    WRITE_SIZE per dispatch give the counters' reading for 1 GiB moved."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 5}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
     out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
            "c5": bench_c5}[a.config](a)
     print(json.dumps(out))

@@ -9,11 +9,15 @@
 //   lam    = Pi_U^T  [ lam_V1 + dt L_Ua^T lam_V1 + lam'/2 ]            (stage 1)
 // so both stages are one "adjoint stage":  out = Pi_P^T [c_id lam + c_L
 // L_W^T lam + extra],  W = Pi(P), run by two kernels:
-//   k_adj_lt  : lam_W = c_id lam + c_L (dL/dW)^T lam + extra    (16x16 tiles)
-//   k_adj_pit : out = (dPi/dP)^T lam_W                           (16x16 tiles)
-// Each tile stages its halo in LDS.  k_adj_lt solves every face's VJP once per
-// tile in two rounds (x faces, then y faces) whose per-side results are
-// gathered by the owning cells (no atomics); boundary faces of a tile are
+//   k_adj_lt  : lam_W = c_id lam + c_L (dL/dW)^T lam + extra    (15x16 tiles)
+//   k_adj_pit : out = (dPi/dP)^T lam_W                           (15x16 tiles)
+// Each tile stages its halo in LDS (coefficient records padded to an odd
+// stride, so lanes reading consecutive cells hit distinct banks).  k_adj_lt
+// solves every face's VJP once per tile in two rounds, x faces (16 per row x
+// 16 rows) then y faces (17 per column x 15 columns), so each round fills the
+// 256 threads once; per face it keeps, for each side, the sum over the two
+// Gauss points of the state adjoint and of its tangentially weighted sum,
+// which the owning cells gather (no atomics).  Boundary faces of a tile are
 // recomputed by the neighbouring tile.  k_adj_pit computes the limiter data of
 // the tile and its halo, then gathers, for each cell, the contributions of the
 // neighbours whose max/min it supplied.
@@ -28,8 +32,21 @@
 namespace dg {
 namespace {
 
-constexpr int TS = kAdjTile;  // tile side (interior cells)
-constexpr int H1 = TS + 2;    // with a halo of 1
+constexpr int TX = kAdjTileX;         // interior columns of a tile
+constexpr int TY = kAdjTileY;         // interior rows
+constexpr int HX = TX + 2;            // with a halo of 1
+constexpr int HY = TY + 2;
+constexpr int NH = HX * HY;
+constexpr int NCELL = TX * TY;        // 240 of the 256 threads own a cell
+constexpr int CS = 13;                // LDS stride of a 12-coefficient record
+constexpr int NFX = (TX + 1) * TY;    // x faces of a tile (256)
+constexpr int NFY = (TY + 1) * TX;    // y faces of a tile (255)
+constexpr int FS = 17;                // LDS stride of a face record (16 values)
+static_assert(NFX <= 256 && NFY <= 256, "one face per thread and round");
+constexpr int GX = TX + 4;            // with a halo of 2 (limiter stencils of the halo)
+constexpr int GY = TY + 4;
+constexpr int NG = GX * GY;
+constexpr int MS = 5;                 // LDS stride of a 4-mean record
 
 template <typename T>
 struct PA {
@@ -254,12 +271,12 @@ __device__ __forceinline__ void flux_xy_vjp(const T* u, T gamma, const T* a, con
   lu[3] += lE;
 }
 
-// ---------------------------------------------------- L^T kernel (16x16) --
+// ------------------------------------------------------------ L^T kernel --
 template <typename T>
 struct LtSmem {
-  T W[H1 * H1][12];     // limited state, tile + halo 1
-  T lam[H1 * H1][12];   // adjoint of the stage output, tile + halo 1
-  T f[TS * (TS + 1)][2][12];  // per face, the L-side and R-side results
+  T W[NH * CS];     // limited state, tile + halo 1
+  T lam[NH * CS];   // adjoint of the stage output, tile + halo 1
+  T f[256 * FS];    // per face of the current round: (A_L, B_L, A_R, B_R) x 4
 };
 
 template <typename T, bool LIM>
@@ -268,7 +285,7 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const Geo g = tile_geo(p, tile);
   const int nc = p.nc;
-  const int x0 = g.tx * TS, y0 = g.ty * TS;
+  const int x0 = g.tx * TX, y0 = g.ty * TY;
   const T hx = (T)g.hx, hy = (T)g.hy;
   const T hx2 = T(0.5) * hx, hy2 = T(0.5) * hy;
   const T s3 = T(1.7320508075688772);
@@ -279,19 +296,31 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
   auto gidx = [&](int lx, int ly) {  // tile-local (may be negative) -> global
     return g.off + wrapi(y0 + ly, g.ny) * g.nx + wrapi(x0 + lx, g.nx);
   };
+  // means of P on the tile + halo 2 (the limiter stencils of the halo cells),
+  // staged in the face area, which is free until the face rounds
+  T* mean = sm.f;
+  if (LIM) {
+    static_assert(NG * MS <= 256 * FS, "means fit in the face area");
+    for (int i = tid; i < NG; i += 256) {
+      const int e = gidx(i % GX - 2, i / GX - 2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mean[i * MS + v] = p.P[3 * v * nc + e];
+    }
+    __syncthreads();
+  }
   // W = Pi(P) and lam on the tile + halo 1
-  for (int i = tid; i < H1 * H1; i += 256) {
-    const int lx = i % H1 - 1, ly = i / H1 - 1;
+  for (int i = tid; i < NH; i += 256) {
+    const int lx = i % HX - 1, ly = i / HX - 1;
     const int e = gidx(lx, ly);
     T q[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) q[k] = p.P[k * nc + e];
     if (LIM) {
-      const int nbi[4] = {gidx(lx - 1, ly), gidx(lx + 1, ly), gidx(lx, ly - 1), gidx(lx, ly + 1)};
+      const int gi = ((ly + 2) * GX + lx + 2) * MS;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        T nb[5] = {q[3 * v], p.P[3 * v * nc + nbi[0]], p.P[3 * v * nc + nbi[1]],
-                   p.P[3 * v * nc + nbi[2]], p.P[3 * v * nc + nbi[3]]};
+        T nb[5] = {q[3 * v], mean[gi - MS + v], mean[gi + MS + v], mean[gi - GX * MS + v],
+                   mean[gi + GX * MS + v]};
         LimInfo<T> li = lim_info(nb, q[3 * v + 1], q[3 * v + 2], hx2, hy2);
         q[3 * v + 1] *= li.alpha;
         q[3 * v + 2] *= li.alpha;
@@ -299,28 +328,38 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      sm.W[i][k] = q[k];
-      sm.lam[i][k] = p.lam[k * nc + e];
+      sm.W[i * CS + k] = q[k];
+      sm.lam[i * CS + k] = p.lam[k * nc + e];
     }
   }
   __syncthreads();
-  auto li1 = [](int lx, int ly) { return (ly + 1) * H1 + (lx + 1); };
+  auto li1 = [](int lx, int ly) { return ((ly + 1) * HX + (lx + 1)) * CS; };
   T acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = T(0);
-  const int cx = tid % TS, cy = tid / TS;  // this thread's interior cell
-  // two rounds: x faces (AX = 0) then y faces (AX = 1); face j of row r joins
-  // tile-local cells (j-1, r) and (j, r) (x) or (r, j-1) and (r, j) (y)
+  const int cx = tid % TX, cy = tid / TX;  // this thread's interior cell (tid < NCELL)
+  // two rounds: x faces (AX = 0) then y faces (AX = 1).  x face j of row r
+  // joins tile-local cells (j-1, r) and (j, r); y face j of column c joins
+  // (c, j-1) and (c, j).
 #pragma unroll
   for (int ax = 0; ax < 2; ++ax) {
-    for (int f = tid; f < TS * (TS + 1); f += 256) {
-      const int r = f / (TS + 1), j = f % (TS + 1);
-      const int iL = ax == 0 ? li1(j - 1, r) : li1(r, j - 1);
-      const int iR = ax == 0 ? li1(j, r) : li1(r, j);
-      const T* WL = sm.W[iL];
-      const T* WR = sm.W[iR];
-      const T* lL = sm.lam[iL];
-      const T* lR = sm.lam[iR];
+    const int nf = ax == 0 ? NFX : NFY;
+    if (tid < nf) {
+      const int f = tid;
+      int iL, iR;
+      if (ax == 0) {
+        const int r = f / (TX + 1), j = f % (TX + 1);
+        iL = li1(j - 1, r);
+        iR = li1(j, r);
+      } else {
+        const int c = f / (TY + 1), j = f % (TY + 1);
+        iL = li1(c, j - 1);
+        iR = li1(c, j);
+      }
+      const T* WL = sm.W + iL;
+      const T* WR = sm.W + iR;
+      const T* lL = sm.lam + iL;
+      const T* lR = sm.lam + iR;
       T lamF[2][4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -336,9 +375,9 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
           lamF[1][v] = a + b;
         }
       }
-      T outL[12], outR[12];
+      T AL[4], BL[4], AR[4], BR[4];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) outL[k] = outR[k] = T(0);
+      for (int v = 0; v < 4; ++v) AL[v] = BL[v] = AR[v] = BR[v] = T(0);
 #pragma unroll
       for (int gp = 0; gp < 2; ++gp) {
         const T sg = gp == 0 ? T(-1) : T(1);
@@ -359,42 +398,44 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
           hll_vjp<T, 1>(uL, uR, p.gamma, lamF[gp], lu_L, lu_R);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          outL[3 * v] += lu_L[v];
-          outR[3 * v] += lu_R[v];
-          if (ax == 0) {
-            outL[3 * v + 1] += hx2 * lu_L[v];
-            outR[3 * v + 1] -= hx2 * lu_R[v];
-            outL[3 * v + 2] += sg * qy * lu_L[v];
-            outR[3 * v + 2] += sg * qy * lu_R[v];
-          } else {
-            outL[3 * v + 2] += hy2 * lu_L[v];
-            outR[3 * v + 2] -= hy2 * lu_R[v];
-            outL[3 * v + 1] += sg * qx * lu_L[v];
-            outR[3 * v + 1] += sg * qx * lu_R[v];
-          }
+          AL[v] += lu_L[v];
+          AR[v] += lu_R[v];
+          BL[v] += sg * lu_L[v];
+          BR[v] += sg * lu_R[v];
         }
       }
+      T* rec = sm.f + f * FS;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        sm.f[f][0][k] = outL[k];
-        sm.f[f][1][k] = outR[k];
+      for (int v = 0; v < 4; ++v) {
+        rec[v] = AL[v];
+        rec[4 + v] = BL[v];
+        rec[8 + v] = AR[v];
+        rec[12 + v] = BR[v];
       }
     }
     __syncthreads();
-    // gather: the cell is R of face j = c (its -face) and L of face c+1
-    {
-      const int r = ax == 0 ? cy : cx;
-      const int c = ax == 0 ? cx : cy;
-      const int fm = r * (TS + 1) + c, fp = r * (TS + 1) + c + 1;
+    // gather: the cell is the R side of its lower face and the L side of its
+    // upper face along the axis
+    if (tid < NCELL) {
+      const int fm = ax == 0 ? cy * (TX + 1) + cx : cx * (TY + 1) + cy;
+      const T* m = sm.f + fm * FS;        // cell on the R side
+      const T* pl = sm.f + (fm + 1) * FS; // cell on the L side
+      const T hn = ax == 0 ? hx2 : hy2, qt = ax == 0 ? qy : qx;
+      const int kn = ax == 0 ? 1 : 2, kt = ax == 0 ? 2 : 1;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] += sm.f[fm][1][k] + sm.f[fp][0][k];
+      for (int v = 0; v < 4; ++v) {
+        acc[3 * v] += m[8 + v] + pl[v];
+        acc[3 * v + kn] += hn * (pl[v] - m[8 + v]);
+        acc[3 * v + kt] += qt * (m[12 + v] + pl[4 + v]);
+      }
     }
     __syncthreads();
   }
+  if (tid >= NCELL) return;
   // volume term
   {
-    const T* Wc = sm.W[li1(cx, cy)];
-    const T* lc = sm.lam[li1(cx, cy)];
+    const T* Wc = sm.W + li1(cx, cy);
+    const T* lc = sm.lam + li1(cx, cy);
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
       const T ox = (q & 2) ? qx : -qx, oy = (q & 1) ? qy : -qy;
@@ -419,7 +460,7 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
     const double dt = p.dt_dev ? p.dt_dev[i] : p.dt_host;
     const T cL = (T)(p.c_L_over_dt * dt), cI = (T)p.c_id;
     const int e = g.off + (y0 + cy) * g.nx + (x0 + cx);
-    const T* lc = sm.lam[li1(cx, cy)];
+    const T* lc = sm.lam + li1(cx, cy);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       T v = cI * lc[k] + cL * acc[k];
@@ -432,9 +473,11 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
 // ----------------------------------------------- limiter transpose kernel --
 template <typename T>
 struct PitSmem {
-  T lhi[H1 * H1][4];   // adjoint routed to the arg-max / arg-min means
-  T llo[H1 * H1][4];
-  unsigned char code[H1 * H1][4];  // amax | amin << 3
+  T mean[NG * MS];        // means of P, tile + halo 2
+  T lhi[NH * MS];         // adjoint routed to the arg-max / arg-min means
+  T llo[NH * MS];
+  T own[NH * MS];         // interior cells: the mean adjoint from the cell's own alpha
+  unsigned char code[NH][4];  // amax | amin << 3
 };
 
 template <typename T>
@@ -443,88 +486,82 @@ __global__ __launch_bounds__(256) void k_adj_pit(PA<T> p) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const Geo g = tile_geo(p, tile);
   const int nc = p.nc;
-  const int x0 = g.tx * TS, y0 = g.ty * TS;
+  const int x0 = g.tx * TX, y0 = g.ty * TY;
   const T hx2 = T(0.5) * (T)g.hx, hy2 = T(0.5) * (T)g.hy;
   const int tid = threadIdx.x;
   auto gidx = [&](int lx, int ly) {
     return g.off + wrapi(y0 + ly, g.ny) * g.nx + wrapi(x0 + lx, g.nx);
   };
-  auto li1 = [](int lx, int ly) { return (ly + 1) * H1 + (lx + 1); };
-  // limiter data of the tile and its halo; the cell's own part is kept for
-  // interior cells in registers of the owning thread (recomputed below)
-  for (int i = tid; i < H1 * H1; i += 256) {
-    const int lx = i % H1 - 1, ly = i / H1 - 1;
+  for (int i = tid; i < NG; i += 256) {
+    const int e = gidx(i % GX - 2, i / GX - 2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sm.mean[i * MS + v] = p.P[3 * v * nc + e];
+  }
+  __syncthreads();
+  // limiter data of the tile and its halo: what each cell routes to its
+  // arg-max / arg-min neighbours; interior cells also finish their gradient
+  // adjoints and the own part of their mean adjoint
+  for (int i = tid; i < NH; i += 256) {
+    const int lx = i % HX - 1, ly = i / HX - 1;
     const int e = gidx(lx, ly);
-    const int nbi[4] = {gidx(lx - 1, ly), gidx(lx + 1, ly), gidx(lx, ly - 1), gidx(lx, ly + 1)};
+    const bool inner = lx >= 0 && ly >= 0 && lx < TX && ly < TY && x0 + lx < g.nx &&
+                       y0 + ly < g.ny;
+    const int gi = ((ly + 2) * GX + lx + 2) * MS;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const T gx = p.P[(3 * v + 1) * nc + e], gy = p.P[(3 * v + 2) * nc + e];
-      T nb[5] = {p.P[3 * v * nc + e], p.P[3 * v * nc + nbi[0]], p.P[3 * v * nc + nbi[1]],
-                 p.P[3 * v * nc + nbi[2]], p.P[3 * v * nc + nbi[3]]};
+      T nb[5] = {sm.mean[gi + v], sm.mean[gi - MS + v], sm.mean[gi + MS + v],
+                 sm.mean[gi - GX * MS + v], sm.mean[gi + GX * MS + v]};
       LimInfo<T> li = lim_info(nb, gx, gy, hx2, hy2);
-      T lhi = T(0), llo = T(0);
+      const T lgx = p.lamW[(3 * v + 1) * nc + e], lgy = p.lamW[(3 * v + 2) * nc + e];
+      T lhi = T(0), llo = T(0), om = T(0), ogx = li.alpha * lgx, ogy = li.alpha * lgy;
       if (li.active) {
-        const T la = gx * p.lamW[(3 * v + 1) * nc + e] + gy * p.lamW[(3 * v + 2) * nc + e];
-        const T lD = la * rcp(li.dm);
+        const T la = gx * lgx + gy * lgy;
+        const T idm = rcp(li.dm);
+        const T lD = la * idm;
+        const T ldm = -la * li.alpha * idm;
         if (li.dplus)
           lhi = lD;
         else
           llo = -lD;
+        // D = hi - phi (dplus) or phi - lo: the phi part
+        om = li.dplus ? -lD : lD;
+        if (li.xaxis)
+          ogx += ldm * hx2 * (gx < T(0) ? T(-1) : T(1));
+        else
+          ogy += ldm * hy2 * (gy < T(0) ? T(-1) : T(1));
       }
-      sm.lhi[i][v] = lhi;
-      sm.llo[i][v] = llo;
+      sm.lhi[i * MS + v] = lhi;
+      sm.llo[i * MS + v] = llo;
       sm.code[i][v] = (unsigned char)(li.amax | (li.amin << 3));
+      if (inner) {
+        sm.own[i * MS + v] = om + p.lamW[3 * v * nc + e];
+        p.out[(3 * v + 1) * nc + e] = ogx;
+        p.out[(3 * v + 2) * nc + e] = ogy;
+      }
     }
   }
   __syncthreads();
-  const int cx = tid % TS, cy = tid / TS;
-  if (x0 + cx >= g.nx || y0 + cy >= g.ny) return;
+  const int cx = tid % TX, cy = tid / TX;
+  if (tid >= NCELL || x0 + cx >= g.nx || y0 + cy >= g.ny) return;
   const int e = g.off + (y0 + cy) * g.nx + (x0 + cx);
-  const int nbi[4] = {gidx(cx - 1, cy), gidx(cx + 1, cy), gidx(cx, cy - 1), gidx(cx, cy + 1)};
+  auto li1 = [](int lx, int ly) { return (ly + 1) * HX + (lx + 1); };
   // neighbour slots in LDS and the code that names this cell from each of them
   const int sl[5] = {li1(cx, cy), li1(cx - 1, cy), li1(cx + 1, cy), li1(cx, cy - 1),
                      li1(cx, cy + 1)};
-  const int back[5] = {0, 2, 1, 4, 3};  // from -x neighbour, this cell is its +x
+  const int back[5] = {0, 2, 1, 4, 3};  // from the -x neighbour, this cell is its +x
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const T gx = p.P[(3 * v + 1) * nc + e], gy = p.P[(3 * v + 2) * nc + e];
-    T nb[5] = {p.P[3 * v * nc + e], p.P[3 * v * nc + nbi[0]], p.P[3 * v * nc + nbi[1]],
-               p.P[3 * v * nc + nbi[2]], p.P[3 * v * nc + nbi[3]]};
-    LimInfo<T> li = lim_info(nb, gx, gy, hx2, hy2);
-    const T lm = p.lamW[3 * v * nc + e];
-    const T lgx = p.lamW[(3 * v + 1) * nc + e], lgy = p.lamW[(3 * v + 2) * nc + e];
-    T om = lm, ogx = li.alpha * lgx, ogy = li.alpha * lgy;
-    if (li.active) {
-      const T la = gx * lgx + gy * lgy;
-      const T idm = rcp(li.dm);
-      const T lD = la * idm;
-      const T ldm = -la * li.alpha * idm;
-      // D = hi - phi (dplus) or phi - lo: the phi part
-      om += li.dplus ? -lD : lD;
-      if (li.xaxis)
-        ogx += ldm * hx2 * (gx < T(0) ? T(-1) : T(1));
-      else
-        ogy += ldm * hy2 * (gy < T(0) ? T(-1) : T(1));
-    }
+    T om = sm.own[sl[0] * MS + v];
     // means that supplied a max or min (self included)
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const unsigned char cd = sm.code[sl[k]][v];
-      if ((cd & 7) == back[k]) om += sm.lhi[sl[k]][v];
-      if ((cd >> 3) == back[k]) om += sm.llo[sl[k]][v];
+      if ((cd & 7) == back[k]) om += sm.lhi[sl[k] * MS + v];
+      if ((cd >> 3) == back[k]) om += sm.llo[sl[k] * MS + v];
     }
     p.out[3 * v * nc + e] = om;
-    p.out[(3 * v + 1) * nc + e] = ogx;
-    p.out[(3 * v + 2) * nc + e] = ogy;
   }
-}
-
-// out = lamW (no limiter): the transpose of the identity
-template <typename T>
-__global__ __launch_bounds__(256) void k_copy(const T* __restrict__ a, T* __restrict__ b,
-                                              int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) b[i] = a[i];
 }
 
 template <typename T>

@@ -95,7 +95,7 @@ static dg_status batch_upload(dg_mesh* m) {
   return DG_OK;
 }
 
-// Adjoint tables (16 x 16 tiles) of one or more 2D Cartesian instances.
+// Adjoint tables (15 x 16-cell tiles) of one or more 2D Cartesian instances.
 static dg_status adjoint_tables(dg_mesh* m, const BatchDesc& d, bool batched) {
   std::vector<AdjInst> ai(d.ninst);
   std::vector<int> ti;
@@ -106,8 +106,8 @@ static dg_status adjoint_tables(dg_mesh* m, const BatchDesc& d, bool batched) {
     a.ny = d.ny[i];
     a.off = (int)d.off[i];
     a.tx0 = tile0;
-    a.tiles_x = (a.nx + kAdjTile - 1) / kAdjTile;
-    a.tiles_y = (a.ny + kAdjTile - 1) / kAdjTile;
+    a.tiles_x = (a.nx + kAdjTileX - 1) / kAdjTileX;
+    a.tiles_y = (a.ny + kAdjTileY - 1) / kAdjTileY;
     a.hx = d.hx[i];
     a.hy = d.hy[i];
     ai[i] = a;

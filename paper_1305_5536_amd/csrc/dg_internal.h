@@ -42,10 +42,11 @@ struct FaceList2D {
 };
 struct FLDev;
 
-// One 2D Cartesian instance of the adjoint (and batched) kernels: a mesh of
-// nx x ny cells starting at cell `off` of the global state arrays, whose
-// 16 x 16 adjoint tiles start at tile `tx0` of the tile list.
-constexpr int kAdjTile = 16;
+// One 2D Cartesian instance of the adjoint kernels: a mesh of nx x ny cells
+// starting at cell `off` of the global state arrays, whose adjoint tiles
+// (kAdjTileX x kAdjTileY cells) start at tile `tx0` of the tile list.
+constexpr int kAdjTileX = 15;
+constexpr int kAdjTileY = 16;
 struct AdjInst {
   int nx, ny, off, tx0;
   int tiles_x, tiles_y, pad0, pad1;
