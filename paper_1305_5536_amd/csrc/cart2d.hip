@@ -60,33 +60,49 @@ struct Cell {
   T m[4], gx[4], gy[4];
 };
 
+// Coefficient arrays are addressed as (uniform array base, 32-bit byte offset
+// of the cell): the base k*nc is scalar, so each load or store is one memory
+// instruction with a scalar base and the row's vector offset, and no per-array
+// 64-bit address arithmetic in the vector unit.
+template <typename T>
+__device__ __forceinline__ const T& at(const T* __restrict__ U, int nc, int k, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(U + (size_t)k * nc) + off);
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* __restrict__ U, int nc, int k, unsigned off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(U + (size_t)k * nc) + off);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_cell(const T* __restrict__ U, int nc, int e, Cell<T>& c) {
+  const unsigned off = (unsigned)e * sizeof(T);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    c.m[v] = U[(3 * v) * nc + e];
-    c.gx[v] = U[(3 * v + 1) * nc + e];
-    c.gy[v] = U[(3 * v + 2) * nc + e];
+    c.m[v] = at(U, nc, 3 * v, off);
+    c.gx[v] = at(U, nc, 3 * v + 1, off);
+    c.gy[v] = at(U, nc, 3 * v + 2, off);
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void load_means(const T* __restrict__ U, int nc, int e, T* m) {
+  const unsigned off = (unsigned)e * sizeof(T);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) m[v] = U[(3 * v) * nc + e];
+  for (int v = 0; v < 4; ++v) m[v] = at(U, nc, 3 * v, off);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_cell(T* __restrict__ U, int nc, int e, const Cell<T>& c) {
+  const unsigned off = (unsigned)e * sizeof(T);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    U[(3 * v) * nc + e] = c.m[v];
-    U[(3 * v + 1) * nc + e] = c.gx[v];
-    U[(3 * v + 2) * nc + e] = c.gy[v];
+    at(U, nc, 3 * v, off) = c.m[v];
+    at(U, nc, 3 * v + 1, off) = c.gx[v];
+    at(U, nc, 3 * v + 2, off) = c.gy[v];
   }
 }
 
-// Limiter of one cell from its x-neighbour means (shuffled) and y-neighbour
+// Limiter of one cell from its x-neighbour means (lane exchange) and y-neighbour
 // means.  On a Cartesian cell the +d and -d face centroids sit at -+ h_d/2,
 // so the two psi of an axis reduce to min(max-phi, phi-min)/|g_d h_d/2| and
 // alpha = min(1, D / max_d |g_d h_d / 2|).
@@ -94,8 +110,8 @@ template <typename T>
 __device__ __forceinline__ void limit_cell(Cell<T>& c, const T* mS, const T* mN, const P2<T>& p) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    T mW = __shfl_up(c.m[v], 1);
-    T mE = __shfl_down(c.m[v], 1);
+    T mW = lane_up(c.m[v]);
+    T mE = lane_down(c.m[v]);
     T phi = c.m[v];
     T hi = fmax(fmax(fmax(phi, mW), fmax(mE, mS[v])), mN[v]);
     T lo = fmin(fmin(fmin(phi, mW), fmin(mE, mS[v])), mN[v]);
@@ -332,9 +348,9 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
         Cell<T> left;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          left.m[v] = __shfl_up(prev.m[v], 1);
-          left.gx[v] = __shfl_up(prev.gx[v], 1);
-          left.gy[v] = __shfl_up(prev.gy[v], 1);
+          left.m[v] = lane_up(prev.m[v]);
+          left.gx[v] = lane_up(prev.gx[v]);
+          left.gy[v] = lane_up(prev.gy[v]);
         }
         T Sm[4], Dm[4], sx[4], sy[4];
         xface(left, prev, p, Sm, Dm, bad);
@@ -342,8 +358,8 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
         Cell<T> o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          T Sp = __shfl_down(Sm[v], 1);
-          T Dp = __shfl_down(Dm[v], 1);
+          T Sp = lane_down(Sm[v]);
+          T Dp = lane_down(Dm[v]);
           T dm = (Sm[v] - Sp) * p.cmx + (ySm[v] - Sy[v]) * p.cmy;
           T dgx = (sx[v] - Sm[v] - Sp) * p.cgx + (yDm[v] - Dy[v]) * p.ccr;
           T dgy = (sy[v] - ySm[v] - Sy[v]) * p.cgy + (Dm[v] - Dp) * p.ccr;

@@ -461,23 +461,23 @@ template <typename T>
 __device__ __forceinline__ void shfl_up_poly(const Poly<T>& q, Poly<T>& o) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    o.m[v] = __shfl_up(q.m[v], 1);
+    o.m[v] = lane_up(q.m[v]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) o.g[v][d] = __shfl_up(q.g[v][d], 1);
+    for (int d = 0; d < 3; ++d) o.g[v][d] = lane_up(q.g[v][d]);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) o.b[c] = __shfl_up(q.b[c], 1);
+  for (int c = 0; c < 3; ++c) o.b[c] = lane_up(q.b[c]);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) o.a[j] = __shfl_up(q.a[j], 1);
+  for (int j = 0; j < 8; ++j) o.a[j] = lane_up(q.a[j]);
 }
 
 template <typename T>
 __device__ __forceinline__ void shfl_down_sums(FaceSums<T>& f) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    f.S[k] = __shfl_down(f.S[k], 1);
-    f.T1[k] = __shfl_down(f.T1[k], 1);
-    f.T2[k] = __shfl_down(f.T2[k], 1);
+    f.S[k] = lane_down(f.S[k]);
+    f.T1[k] = lane_down(f.T1[k]);
+    f.T2[k] = lane_down(f.T2[k]);
   }
 }
 

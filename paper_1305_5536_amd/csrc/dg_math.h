@@ -64,6 +64,33 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return b;
 }
 
+// Neighbour-lane exchange along the whole wave with DPP (wave_shr:1 and
+// wave_shl:1), a VALU move with no LDS round trip: lane_up(v) gives lane l the
+// value of lane l-1, lane_down(v) that of lane l+1; the end lane (0, resp. 63)
+// keeps its own value.  Doubles move as two 32-bit halves.
+__device__ __forceinline__ int dpp_shr1(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_shl1(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float lane_up(float v) {
+  return __int_as_float(dpp_shr1(__float_as_int(v)));
+}
+__device__ __forceinline__ float lane_down(float v) {
+  return __int_as_float(dpp_shl1(__float_as_int(v)));
+}
+__device__ __forceinline__ double lane_up(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_shr1((int)(b & 0xffffffffLL)), hi = dpp_shr1((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_down(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_shl1((int)(b & 0xffffffffLL)), hi = dpp_shl1((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Wave-wide minimum of a double (lanes exchange through DPP/permute).
 __device__ __forceinline__ double wave_min(double d) {
   for (int o = 32; o > 0; o >>= 1) d = fmin(d, __shfl_xor(d, o));
