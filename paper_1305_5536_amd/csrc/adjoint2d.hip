@@ -7,20 +7,24 @@
 // Backward, given lam' = dJ/dU':
 //   lam_V1 = Pi_V1^T [ lam'/2 + (dt/2) L_Ub^T lam' ]                 (stage 2)
 //   lam    = Pi_U^T  [ lam_V1 + dt L_Ua^T lam_V1 + lam'/2 ]            (stage 1)
-// so both stages are one "adjoint stage":  out = Pi_P^T [c_id lam + c_L
-// L_W^T lam + extra],  W = Pi(P), run by two kernels:
-//   k_adj_lt  : lam_W = c_id lam + c_L (dL/dW)^T lam + extra    (15x16 tiles)
-//   k_adj_pit : out = (dPi/dP)^T lam_W                           (15x16 tiles)
-// Each tile stages its halo in LDS (coefficient records padded to an odd
-// stride, so lanes reading consecutive cells hit distinct banks).  k_adj_lt
-// solves every face's VJP once per tile in two rounds, x faces (16 per row x
-// 16 rows) then y faces (17 per column x 15 columns), so each round fills the
-// 256 threads once; per face it keeps, for each side, the sum over the two
-// Gauss points of the state adjoint and of its tangentially weighted sum,
-// which the owning cells gather (no atomics).  Boundary faces of a tile are
-// recomputed by the neighbouring tile.  k_adj_pit computes the limiter data of
-// the tile and its halo, then gathers, for each cell, the contributions of the
-// neighbours whose max/min it supplied.
+// so both stages are one "adjoint stage"
+//   out = Pi_P^T lamW,   lamW = c_id lam + c_L (dL/dW)^T lam + c_extra extra,
+//   W = Pi(P),
+// and each adjoint stage is one kernel (k_adj_row_*), laid out like the forward
+// stage kernels: one wave owns 58 columns (lanes 3..60; three halo lanes on
+// each side) and marches up `rows` rows with its rows in registers.  x
+// neighbours come from DPP lane shifts, y neighbours from the row window; no
+// LDS, no barriers, no atomics.  Per row the wave
+//   S1  limits P (W and the limiter's branch data) one row behind the loads,
+//   S2  solves the VJP of the row's -x faces (the left side's share goes to
+//       the left lane by a lane shift), of the y face below it and of the
+//       volume term, accumulating lamW of that row and of the row below,
+//   S3  finishes lamW two rows behind, applies the cell's own part of the
+//       limiter transpose (gradient scale, D and dm branches) and writes the
+//       gradient adjoints,
+//   S4  three rows behind, adds to each mean adjoint what the cell received as
+//       its neighbours' arg-max / arg-min, and writes it.
+// A tile of R output rows marches R + 4 rows.
 //
 // Ties (min/max arguments, the limiter's branch) take the first argument in
 // the order self, -x, +x, -y, +y, as the CPU oracle's dual numbers do.
@@ -32,61 +36,26 @@
 namespace dg {
 namespace {
 
-constexpr int TX = kAdjTileX;         // interior columns of a tile
-constexpr int TY = kAdjTileY;         // interior rows
-constexpr int HX = TX + 2;            // with a halo of 1
-constexpr int HY = TY + 2;
-constexpr int NH = HX * HY;
-constexpr int NCELL = TX * TY;        // 240 of the 256 threads own a cell
-constexpr int CS = 13;                // LDS stride of a 12-coefficient record
-constexpr int NFX = (TX + 1) * TY;    // x faces of a tile (256)
-constexpr int NFY = (TY + 1) * TX;    // y faces of a tile (255)
-constexpr int FS = 17;                // LDS stride of a face record (16 values)
-static_assert(NFX <= 256 && NFY <= 256, "one face per thread and round");
-constexpr int GX = TX + 4;            // with a halo of 2 (limiter stencils of the halo)
-constexpr int GY = TY + 4;
-constexpr int NG = GX * GY;
-constexpr int MS = 5;                 // LDS stride of a 4-mean record
+constexpr int kLanesA = 64;
+constexpr int kHaloA = 3;
+static_assert(kLanesA - 2 * kHaloA == kAdjCols, "adjoint tile width");
 
 template <typename T>
 struct PA {
-  const T* __restrict__ P;     // pre-limit state
+  const T* __restrict__ P;     // pre-limit state of the stage
   const T* __restrict__ lam;   // adjoint of the stage output
-  const T* __restrict__ extra; // added to lam_W (may be NULL)
-  const T* __restrict__ lamW;  // k_adj_pit input
+  const T* __restrict__ extra; // added to lamW with weight c_extra (may be NULL)
   T* __restrict__ out;
   const AdjInst* inst;
   const int* tile_inst;        // tile -> instance (batched); NULL: one instance
-  const double* dt_dev;        // per instance (batched) or one value
+  const double* dt_dev;        // per instance (batched) or one value; NULL: dt_host
   double dt_host;
   double c_id, c_L_over_dt;    // c_L = c_L_over_dt * dt
   double c_extra;
   int nc;                      // global stride of the coefficient arrays
   int ntiles;
   T gamma;
-  int limiter;
 };
-
-struct Geo {
-  int nx, ny, off, tx, ty;
-  double hx, hy;
-};
-
-template <typename T>
-__device__ __forceinline__ Geo tile_geo(const PA<T>& p, int tile) {
-  const int i = p.tile_inst ? p.tile_inst[tile] : 0;
-  const AdjInst in = p.inst[i];
-  Geo g;
-  g.nx = in.nx;
-  g.ny = in.ny;
-  g.off = in.off;
-  const int t = tile - in.tx0;
-  g.tx = t % in.tiles_x;
-  g.ty = t / in.tiles_x;
-  g.hx = in.hx;
-  g.hy = in.hy;
-  return g;
-}
 
 __device__ __forceinline__ int wrapi(int a, int n) {
   a %= n;
@@ -271,109 +240,197 @@ __device__ __forceinline__ void flux_xy_vjp(const T* u, T gamma, const T* a, con
   lu[3] += lE;
 }
 
-// ------------------------------------------------------------ L^T kernel --
+// ------------------------------------------------------------ row kernel --
+// Limiter branch data of one row (per lane): alpha and dm per variable, the
+// arg-max / arg-min codes (6 bits per variable) and the active / D-from-max /
+// dm-from-x flags (3 bits per variable).
 template <typename T>
-struct LtSmem {
-  T W[NH * CS];     // limited state, tile + halo 1
-  T lam[NH * CS];   // adjoint of the stage output, tile + halo 1
-  T f[256 * FS];    // per face of the current round: (A_L, B_L, A_R, B_R) x 4
+struct LimRow {
+  T alpha[4], dm[4];
+  unsigned code, flag;
 };
 
+// Limiter transpose data of one row: what the cell routes to its arg-max and
+// arg-min means, and the codes naming them.
+template <typename T>
+struct PitRow {
+  T lhi[4], llo[4];
+  unsigned code;
+};
+
+// Array k of a state: a uniform array base (k * nc) plus the cell's 32-bit
+// byte offset.
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ U, int nc, int k, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(U + (size_t)k * nc) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* __restrict__ U, int nc, int k, unsigned off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(U + (size_t)k * nc) + off) = v;
+}
+
+__device__ __forceinline__ unsigned lane_up_u(unsigned v) { return (unsigned)dpp_shr1((int)v); }
+__device__ __forceinline__ unsigned lane_down_u(unsigned v) { return (unsigned)dpp_shl1((int)v); }
+
 template <typename T, bool LIM>
-__global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
-  __shared__ LtSmem<T> sm;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const Geo g = tile_geo(p, tile);
-  const int nc = p.nc;
-  const int x0 = g.tx * TX, y0 = g.ty * TY;
-  const T hx = (T)g.hx, hy = (T)g.hy;
+__device__ __forceinline__ void adj_row_body(const PA<T>& p) {
+  const int lane = threadIdx.x & (kLanesA - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 +
+                                                  (threadIdx.x >> 6));
+  if (wave >= p.ntiles) return;
+  const int ii = p.tile_inst ? __builtin_amdgcn_readfirstlane(p.tile_inst[wave]) : 0;
+  const AdjInst& in = p.inst[ii];
+  const int nx = in.nx, ny = in.ny, nc = p.nc, rows = in.rows;
+  const int t = wave - in.tx0;
+  const int tx = t % in.tiles_x, ty = t / in.tiles_x;
+  const int colu = tx * kAdjCols + lane - kHaloA;
+  const bool own = lane >= kHaloA && lane < kHaloA + kAdjCols && colu < nx;
+  const int col = wrapi(colu, nx);
+  const int y0 = ty * rows, y1 = min(y0 + rows, ny);
+  const T* __restrict__ P = p.P + in.off;
+  const T* __restrict__ L = p.lam + in.off;
+  const T* __restrict__ X = p.extra ? p.extra + in.off : nullptr;
+  T* __restrict__ O = p.out + in.off;
+  const T hx = (T)in.hx, hy = (T)in.hy;
   const T hx2 = T(0.5) * hx, hy2 = T(0.5) * hy;
   const T s3 = T(1.7320508075688772);
   const T qx = hx2 / s3, qy = hy2 / s3;
   const T cmx = T(0.5) / hx, cmy = T(0.5) / hy, cgx = T(3) / (hx * hx), cgy = T(3) / (hy * hy),
           ccr = s3 / (hx * hy);
-  const int tid = threadIdx.x;
-  auto gidx = [&](int lx, int ly) {  // tile-local (may be negative) -> global
-    return g.off + wrapi(y0 + ly, g.ny) * g.nx + wrapi(x0 + lx, g.nx);
-  };
-  // means of P on the tile + halo 2 (the limiter stencils of the halo cells),
-  // staged in the face area, which is free until the face rounds
-  T* mean = sm.f;
-  if (LIM) {
-    static_assert(NG * MS <= 256 * FS, "means fit in the face area");
-    for (int i = tid; i < NG; i += 256) {
-      const int e = gidx(i % GX - 2, i / GX - 2);
+  const double dt = p.dt_dev ? p.dt_dev[ii] : p.dt_host;
+  const T cI = (T)p.c_id, cL = (T)(p.c_L_over_dt * dt), cX = (T)p.c_extra;
+  const T gam = p.gamma;
+  auto roff = [&](int r) { return (unsigned)(wrapi(r, ny) * nx + col) * (unsigned)sizeof(T); };
+
+  // Row window (rows relative to the iteration j): means m2 = j-2, m1 = j-1,
+  // m0 = j (mn = j+1 in flight); gradients g2 = j-2, g1 = j-1 (gn = j in
+  // flight); adjoint l2 = j-2, l1 = j-1 (ln = j in flight); extra x1 = j-1.
+  T m2[4], m1[4], m0[4], mn[4];
+  T g2[8], g1[8], gn[8];
+  T l2[12], l1[12], ln[12], x1[12], xn[12];
+  LimRow<T> lr2, lr1;
+  T acc2[12], acc1[12];
+  PitRow<T> pr4, pr3;
+  T own3[4];
+  const int jb = y0 - 1, je = y1 + 2;
+  {
+    const unsigned o3 = roff(jb - 2), o2 = roff(jb - 1), o1 = roff(jb);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) mean[i * MS + v] = p.P[3 * v * nc + e];
-    }
-    __syncthreads();
-  }
-  // W = Pi(P) and lam on the tile + halo 1
-  for (int i = tid; i < NH; i += 256) {
-    const int lx = i % HX - 1, ly = i / HX - 1;
-    const int e = gidx(lx, ly);
-    T q[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) q[k] = p.P[k * nc + e];
-    if (LIM) {
-      const int gi = ((ly + 2) * GX + lx + 2) * MS;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        T nb[5] = {q[3 * v], mean[gi - MS + v], mean[gi + MS + v], mean[gi - GX * MS + v],
-                   mean[gi + GX * MS + v]};
-        LimInfo<T> li = lim_info(nb, q[3 * v + 1], q[3 * v + 2], hx2, hy2);
-        q[3 * v + 1] *= li.alpha;
-        q[3 * v + 2] *= li.alpha;
-      }
+    for (int v = 0; v < 4; ++v) {
+      m1[v] = ld(P, nc, 3 * v, o3);  // rotated into m2 below (row jb-2)
+      m0[v] = ld(P, nc, 3 * v, o2);  // row jb-1
+      mn[v] = ld(P, nc, 3 * v, o1);  // row jb
+      gn[2 * v] = ld(P, nc, 3 * v + 1, o2);
+      gn[2 * v + 1] = ld(P, nc, 3 * v + 2, o2);
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      sm.W[i * CS + k] = q[k];
-      sm.lam[i * CS + k] = p.lam[k * nc + e];
+      ln[k] = ld(L, nc, k, o2);
+      xn[k] = T(0);
+      l1[k] = T(0);
+      acc1[k] = T(0);
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      g1[2 * v] = g1[2 * v + 1] = T(0);
+      lr1.alpha[v] = T(1);
+      lr1.dm[v] = T(0);
+      pr3.lhi[v] = pr3.llo[v] = T(0);
+      own3[v] = T(0);
+    }
+    lr1.code = lr1.flag = 0;
+    pr3.code = 0;
   }
-  __syncthreads();
-  auto li1 = [](int lx, int ly) { return ((ly + 1) * HX + (lx + 1)) * CS; };
-  T acc[12];
+
+  for (int j = jb; j <= je; ++j) {
+    // rotate the window: arrivals of the previous iteration's loads
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = T(0);
-  const int cx = tid % TX, cy = tid / TX;  // this thread's interior cell (tid < NCELL)
-  // two rounds: x faces (AX = 0) then y faces (AX = 1).  x face j of row r
-  // joins tile-local cells (j-1, r) and (j, r); y face j of column c joins
-  // (c, j-1) and (c, j).
+    for (int v = 0; v < 4; ++v) {
+      m2[v] = m1[v];
+      m1[v] = m0[v];
+      m0[v] = mn[v];
+    }
 #pragma unroll
-  for (int ax = 0; ax < 2; ++ax) {
-    const int nf = ax == 0 ? NFX : NFY;
-    if (tid < nf) {
-      const int f = tid;
-      int iL, iR;
-      if (ax == 0) {
-        const int r = f / (TX + 1), j = f % (TX + 1);
-        iL = li1(j - 1, r);
-        iR = li1(j, r);
-      } else {
-        const int c = f / (TY + 1), j = f % (TY + 1);
-        iL = li1(c, j - 1);
-        iR = li1(c, j);
+    for (int k = 0; k < 8; ++k) {
+      g2[k] = g1[k];
+      g1[k] = gn[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      l2[k] = l1[k];
+      l1[k] = ln[k];
+      x1[k] = xn[k];
+      acc2[k] = acc1[k];
+    }
+    lr2 = lr1;
+    const int r1 = j - 1;
+    const bool s2_cell = r1 >= y0 - 1 && r1 <= y1;
+    if (s2_cell) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc1[k] = cI * l1[k] + cX * x1[k];
+    }
+    // issue this iteration's loads (used from the next iteration on)
+    if (j < je) {
+      const unsigned o = roff(j + 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mn[v] = ld(P, nc, 3 * v, o);
+    }
+    if (j <= y1 + 1) {
+      const unsigned o = roff(j);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        gn[2 * v] = ld(P, nc, 3 * v + 1, o);
+        gn[2 * v + 1] = ld(P, nc, 3 * v + 2, o);
       }
-      const T* WL = sm.W + iL;
-      const T* WR = sm.W + iR;
-      const T* lL = sm.lam + iL;
-      const T* lR = sm.lam + iR;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) ln[k] = ld(L, nc, k, o);
+      if (X && j <= y1) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) xn[k] = ld(X, nc, k, o);
+      }
+    }
+
+    // S1: limit row j-1 (W = mean, alpha * gradient) and keep its branch data
+    lr1.code = lr1.flag = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (LIM) {
+        T nb[5] = {m1[v], lane_up(m1[v]), lane_down(m1[v]), m2[v], m0[v]};
+        LimInfo<T> li = lim_info(nb, g1[2 * v], g1[2 * v + 1], hx2, hy2);
+        lr1.alpha[v] = li.alpha;
+        lr1.dm[v] = li.dm;
+        lr1.code |= (unsigned)(li.amax | (li.amin << 3)) << (6 * v);
+        lr1.flag |= (unsigned)((li.active ? 1 : 0) | (li.dplus ? 2 : 0) | (li.xaxis ? 4 : 0))
+                    << (3 * v);
+      } else {
+        lr1.alpha[v] = T(1);
+        lr1.dm[v] = T(0);
+      }
+    }
+
+    // S2: faces and volume of row j-1
+    T W1[12];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      W1[3 * v] = m1[v];
+      W1[3 * v + 1] = lr1.alpha[v] * g1[2 * v];
+      W1[3 * v + 2] = lr1.alpha[v] * g1[2 * v + 1];
+    }
+    if (s2_cell) {
+      // -x face of this lane: L = lane - 1, R = this lane
+      T WL[12], lL[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        WL[k] = lane_up(W1[k]);
+        lL[k] = lane_up(l1[k]);
+      }
       T lamF[2][4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (ax == 0) {
-          const T a = cmx * (lR[3 * v] - lL[3 * v]) - cgx * (lR[3 * v + 1] + lL[3 * v + 1]);
-          const T b = ccr * (lR[3 * v + 2] - lL[3 * v + 2]);
-          lamF[0][v] = a - b;
-          lamF[1][v] = a + b;
-        } else {
-          const T a = cmy * (lR[3 * v] - lL[3 * v]) - cgy * (lR[3 * v + 2] + lL[3 * v + 2]);
-          const T b = ccr * (lR[3 * v + 1] - lL[3 * v + 1]);
-          lamF[0][v] = a - b;
-          lamF[1][v] = a + b;
-        }
+        const T a = cmx * (l1[3 * v] - lL[3 * v]) - cgx * (l1[3 * v + 1] + lL[3 * v + 1]);
+        const T b = ccr * (l1[3 * v + 2] - lL[3 * v + 2]);
+        lamF[0][v] = a - b;
+        lamF[1][v] = a + b;
       }
       T AL[4], BL[4], AR[4], BR[4];
 #pragma unroll
@@ -381,200 +438,233 @@ __global__ __launch_bounds__(256) void k_adj_lt(PA<T> p) {
 #pragma unroll
       for (int gp = 0; gp < 2; ++gp) {
         const T sg = gp == 0 ? T(-1) : T(1);
-        T uL[4], uR[4], lu_L[4] = {T(0), T(0), T(0), T(0)}, lu_R[4] = {T(0), T(0), T(0), T(0)};
+        T uL[4], uR[4], luL[4] = {T(0), T(0), T(0), T(0)}, luR[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          if (ax == 0) {
-            uL[v] = WL[3 * v] + WL[3 * v + 1] * hx2 + sg * WL[3 * v + 2] * qy;
-            uR[v] = WR[3 * v] - WR[3 * v + 1] * hx2 + sg * WR[3 * v + 2] * qy;
-          } else {
-            uL[v] = WL[3 * v] + WL[3 * v + 2] * hy2 + sg * WL[3 * v + 1] * qx;
-            uR[v] = WR[3 * v] - WR[3 * v + 2] * hy2 + sg * WR[3 * v + 1] * qx;
+          uL[v] = WL[3 * v] + WL[3 * v + 1] * hx2 + sg * WL[3 * v + 2] * qy;
+          uR[v] = W1[3 * v] - W1[3 * v + 1] * hx2 + sg * W1[3 * v + 2] * qy;
+        }
+        hll_vjp<T, 0>(uL, uR, gam, lamF[gp], luL, luR);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          AL[v] += luL[v];
+          BL[v] += sg * luL[v];
+          AR[v] += luR[v];
+          BR[v] += sg * luR[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // this lane is the R side of its -x face; its +x face's L share comes
+        // from the right lane
+        const T aL = lane_down(AL[v]), bL = lane_down(BL[v]);
+        acc1[3 * v] += cL * (AR[v] + aL);
+        acc1[3 * v + 1] += cL * hx2 * (aL - AR[v]);
+        acc1[3 * v + 2] += cL * qy * (BR[v] + bL);
+      }
+      // volume term
+#pragma unroll 1
+      for (int q = 0; q < 4; ++q) {
+        const T ox = (q & 2) ? qx : -qx, oy = (q & 1) ? qy : -qy;
+        T u[4], a[4], b[4], lu[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          u[v] = W1[3 * v] + W1[3 * v + 1] * ox + W1[3 * v + 2] * oy;
+          a[v] = cgx * l1[3 * v + 1];
+          b[v] = cgy * l1[3 * v + 2];
+        }
+        flux_xy_vjp(u, gam, a, b, lu);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc1[3 * v] += cL * lu[v];
+          acc1[3 * v + 1] += cL * ox * lu[v];
+          acc1[3 * v + 2] += cL * oy * lu[v];
+        }
+      }
+    }
+    if (r1 >= y0 - 1 && r1 <= y1 + 1) {
+      // y face between rows j-2 (L) and j-1 (R)
+      T W2[12];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        W2[3 * v] = m2[v];
+        W2[3 * v + 1] = lr2.alpha[v] * g2[2 * v];
+        W2[3 * v + 2] = lr2.alpha[v] * g2[2 * v + 1];
+      }
+      T lamF[2][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T a = cmy * (l1[3 * v] - l2[3 * v]) - cgy * (l1[3 * v + 2] + l2[3 * v + 2]);
+        const T b = ccr * (l1[3 * v + 1] - l2[3 * v + 1]);
+        lamF[0][v] = a - b;
+        lamF[1][v] = a + b;
+      }
+      T AL[4], BL[4], AR[4], BR[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) AL[v] = BL[v] = AR[v] = BR[v] = T(0);
+#pragma unroll
+      for (int gp = 0; gp < 2; ++gp) {
+        const T sg = gp == 0 ? T(-1) : T(1);
+        T uL[4], uR[4], luL[4] = {T(0), T(0), T(0), T(0)}, luR[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          uL[v] = W2[3 * v] + W2[3 * v + 2] * hy2 + sg * W2[3 * v + 1] * qx;
+          uR[v] = W1[3 * v] - W1[3 * v + 2] * hy2 + sg * W1[3 * v + 1] * qx;
+        }
+        hll_vjp<T, 1>(uL, uR, gam, lamF[gp], luL, luR);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          AL[v] += luL[v];
+          BL[v] += sg * luL[v];
+          AR[v] += luR[v];
+          BR[v] += sg * luR[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc1[3 * v] += cL * AR[v];
+        acc1[3 * v + 2] -= cL * hy2 * AR[v];
+        acc1[3 * v + 1] += cL * qx * BR[v];
+        acc2[3 * v] += cL * AL[v];
+        acc2[3 * v + 2] += cL * hy2 * AL[v];
+        acc2[3 * v + 1] += cL * qx * BL[v];
+      }
+    }
+
+    // S3: row j-2 is complete: lamW = acc2
+    const int r2 = j - 2;
+    PitRow<T> pr2;
+    T own2[4];
+    pr2.code = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pr2.lhi[v] = pr2.llo[v] = own2[v] = T(0);
+    if (r2 >= y0 - 1 && r2 <= y1) {
+      const bool wr = own && r2 >= y0 && r2 < y1;
+      const unsigned o = roff(r2);
+      if (!LIM) {
+        if (wr) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) st(O, nc, k, o, acc2[k]);
+        }
+      } else {
+        pr2.code = lr2.code;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T gx = g2[2 * v], gy = g2[2 * v + 1];
+          const T lgx = acc2[3 * v + 1], lgy = acc2[3 * v + 2];
+          const T al = lr2.alpha[v];
+          const unsigned fl = (lr2.flag >> (3 * v)) & 7u;
+          T om = acc2[3 * v], ogx = al * lgx, ogy = al * lgy;
+          if (fl & 1u) {
+            const T la = gx * lgx + gy * lgy;
+            const T idm = rcp(lr2.dm[v]);
+            const T lD = la * idm;
+            const T ldm = -la * al * idm;
+            if (fl & 2u) {
+              pr2.lhi[v] = lD;
+              om -= lD;
+            } else {
+              pr2.llo[v] = -lD;
+              om += lD;
+            }
+            if (fl & 4u)
+              ogx += ldm * hx2 * (gx < T(0) ? T(-1) : T(1));
+            else
+              ogy += ldm * hy2 * (gy < T(0) ? T(-1) : T(1));
+          }
+          own2[v] = om;
+          if (wr) {
+            st(O, nc, 3 * v + 1, o, ogx);
+            st(O, nc, 3 * v + 2, o, ogy);
           }
         }
-        if (ax == 0)
-          hll_vjp<T, 0>(uL, uR, p.gamma, lamF[gp], lu_L, lu_R);
-        else
-          hll_vjp<T, 1>(uL, uR, p.gamma, lamF[gp], lu_L, lu_R);
+      }
+    }
+
+    // S4: row j-3's mean adjoints (self, -x, +x, -y = row j-4, +y = row j-2)
+    if (LIM) {
+      const int r3 = j - 3;
+      PitRow<T> pl, pr;
+      pl.code = lane_up_u(pr3.code);
+      pr.code = lane_down_u(pr3.code);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        pl.lhi[v] = lane_up(pr3.lhi[v]);
+        pl.llo[v] = lane_up(pr3.llo[v]);
+        pr.lhi[v] = lane_down(pr3.lhi[v]);
+        pr.llo[v] = lane_down(pr3.llo[v]);
+      }
+      if (own && r3 >= y0 && r3 < y1) {
+        const unsigned o = roff(r3);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          AL[v] += lu_L[v];
-          AR[v] += lu_R[v];
-          BL[v] += sg * lu_L[v];
-          BR[v] += sg * lu_R[v];
+          const int sh = 6 * v;
+          T om = own3[v];
+          // the code a neighbour uses for this cell: self 0, from -x it is +x (2),
+          // from +x it is -x (1), from -y (row below) +y (4), from +y -y (3)
+          const unsigned cs = (pr3.code >> sh) & 63u, cl = (pl.code >> sh) & 63u,
+                         cr = (pr.code >> sh) & 63u, cd = (pr4.code >> sh) & 63u,
+                         cu = (pr2.code >> sh) & 63u;
+          if ((cs & 7u) == 0u) om += pr3.lhi[v];
+          if ((cs >> 3) == 0u) om += pr3.llo[v];
+          if ((cl & 7u) == 2u) om += pl.lhi[v];
+          if ((cl >> 3) == 2u) om += pl.llo[v];
+          if ((cr & 7u) == 1u) om += pr.lhi[v];
+          if ((cr >> 3) == 1u) om += pr.llo[v];
+          if ((cd & 7u) == 4u) om += pr4.lhi[v];
+          if ((cd >> 3) == 4u) om += pr4.llo[v];
+          if ((cu & 7u) == 3u) om += pr2.lhi[v];
+          if ((cu >> 3) == 3u) om += pr2.llo[v];
+          st(O, nc, 3 * v, o, om);
         }
       }
-      T* rec = sm.f + f * FS;
+      pr4 = pr3;
+      pr3 = pr2;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        rec[v] = AL[v];
-        rec[4 + v] = BL[v];
-        rec[8 + v] = AR[v];
-        rec[12 + v] = BR[v];
-      }
-    }
-    __syncthreads();
-    // gather: the cell is the R side of its lower face and the L side of its
-    // upper face along the axis
-    if (tid < NCELL) {
-      const int fm = ax == 0 ? cy * (TX + 1) + cx : cx * (TY + 1) + cy;
-      const T* m = sm.f + fm * FS;        // cell on the R side
-      const T* pl = sm.f + (fm + 1) * FS; // cell on the L side
-      const T hn = ax == 0 ? hx2 : hy2, qt = ax == 0 ? qy : qx;
-      const int kn = ax == 0 ? 1 : 2, kt = ax == 0 ? 2 : 1;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        acc[3 * v] += m[8 + v] + pl[v];
-        acc[3 * v + kn] += hn * (pl[v] - m[8 + v]);
-        acc[3 * v + kt] += qt * (m[12 + v] + pl[4 + v]);
-      }
-    }
-    __syncthreads();
-  }
-  if (tid >= NCELL) return;
-  // volume term
-  {
-    const T* Wc = sm.W + li1(cx, cy);
-    const T* lc = sm.lam + li1(cx, cy);
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-      const T ox = (q & 2) ? qx : -qx, oy = (q & 1) ? qy : -qy;
-      T u[4], a[4], b[4], lu[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        u[v] = Wc[3 * v] + Wc[3 * v + 1] * ox + Wc[3 * v + 2] * oy;
-        a[v] = cgx * lc[3 * v + 1];
-        b[v] = cgy * lc[3 * v + 2];
-      }
-      flux_xy_vjp(u, p.gamma, a, b, lu);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        acc[3 * v] += lu[v];
-        acc[3 * v + 1] += ox * lu[v];
-        acc[3 * v + 2] += oy * lu[v];
-      }
-    }
-  }
-  if (x0 + cx < g.nx && y0 + cy < g.ny) {
-    const int i = p.tile_inst ? p.tile_inst[tile] : 0;
-    const double dt = p.dt_dev ? p.dt_dev[i] : p.dt_host;
-    const T cL = (T)(p.c_L_over_dt * dt), cI = (T)p.c_id;
-    const int e = g.off + (y0 + cy) * g.nx + (x0 + cx);
-    const T* lc = sm.lam + li1(cx, cy);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      T v = cI * lc[k] + cL * acc[k];
-      if (p.extra) v += (T)p.c_extra * p.extra[k * nc + e];
-      p.out[k * nc + e] = v;
+      for (int v = 0; v < 4; ++v) own3[v] = own2[v];
     }
   }
 }
 
-// ----------------------------------------------- limiter transpose kernel --
-template <typename T>
-struct PitSmem {
-  T mean[NG * MS];        // means of P, tile + halo 2
-  T lhi[NH * MS];         // adjoint routed to the arg-max / arg-min means
-  T llo[NH * MS];
-  T own[NH * MS];         // interior cells: the mean adjoint from the cell's own alpha
-  unsigned char code[NH][4];  // amax | amin << 3
-};
+template <bool LIM>
+__global__ __launch_bounds__(256) void k_adj_row_f64(PA<double> p) {
+  adj_row_body<double, LIM>(p);
+}
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_pit(PA<T> p) {
-  __shared__ PitSmem<T> sm;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const Geo g = tile_geo(p, tile);
-  const int nc = p.nc;
-  const int x0 = g.tx * TX, y0 = g.ty * TY;
-  const T hx2 = T(0.5) * (T)g.hx, hy2 = T(0.5) * (T)g.hy;
-  const int tid = threadIdx.x;
-  auto gidx = [&](int lx, int ly) {
-    return g.off + wrapi(y0 + ly, g.ny) * g.nx + wrapi(x0 + lx, g.nx);
-  };
-  for (int i = tid; i < NG; i += 256) {
-    const int e = gidx(i % GX - 2, i / GX - 2);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sm.mean[i * MS + v] = p.P[3 * v * nc + e];
-  }
-  __syncthreads();
-  // limiter data of the tile and its halo: what each cell routes to its
-  // arg-max / arg-min neighbours; interior cells also finish their gradient
-  // adjoints and the own part of their mean adjoint
-  for (int i = tid; i < NH; i += 256) {
-    const int lx = i % HX - 1, ly = i / HX - 1;
-    const int e = gidx(lx, ly);
-    const bool inner = lx >= 0 && ly >= 0 && lx < TX && ly < TY && x0 + lx < g.nx &&
-                       y0 + ly < g.ny;
-    const int gi = ((ly + 2) * GX + lx + 2) * MS;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T gx = p.P[(3 * v + 1) * nc + e], gy = p.P[(3 * v + 2) * nc + e];
-      T nb[5] = {sm.mean[gi + v], sm.mean[gi - MS + v], sm.mean[gi + MS + v],
-                 sm.mean[gi - GX * MS + v], sm.mean[gi + GX * MS + v]};
-      LimInfo<T> li = lim_info(nb, gx, gy, hx2, hy2);
-      const T lgx = p.lamW[(3 * v + 1) * nc + e], lgy = p.lamW[(3 * v + 2) * nc + e];
-      T lhi = T(0), llo = T(0), om = T(0), ogx = li.alpha * lgx, ogy = li.alpha * lgy;
-      if (li.active) {
-        const T la = gx * lgx + gy * lgy;
-        const T idm = rcp(li.dm);
-        const T lD = la * idm;
-        const T ldm = -la * li.alpha * idm;
-        if (li.dplus)
-          lhi = lD;
-        else
-          llo = -lD;
-        // D = hi - phi (dplus) or phi - lo: the phi part
-        om = li.dplus ? -lD : lD;
-        if (li.xaxis)
-          ogx += ldm * hx2 * (gx < T(0) ? T(-1) : T(1));
-        else
-          ogy += ldm * hy2 * (gy < T(0) ? T(-1) : T(1));
-      }
-      sm.lhi[i * MS + v] = lhi;
-      sm.llo[i * MS + v] = llo;
-      sm.code[i][v] = (unsigned char)(li.amax | (li.amin << 3));
-      if (inner) {
-        sm.own[i * MS + v] = om + p.lamW[3 * v * nc + e];
-        p.out[(3 * v + 1) * nc + e] = ogx;
-        p.out[(3 * v + 2) * nc + e] = ogy;
-      }
-    }
-  }
-  __syncthreads();
-  const int cx = tid % TX, cy = tid / TX;
-  if (tid >= NCELL || x0 + cx >= g.nx || y0 + cy >= g.ny) return;
-  const int e = g.off + (y0 + cy) * g.nx + (x0 + cx);
-  auto li1 = [](int lx, int ly) { return (ly + 1) * HX + (lx + 1); };
-  // neighbour slots in LDS and the code that names this cell from each of them
-  const int sl[5] = {li1(cx, cy), li1(cx - 1, cy), li1(cx + 1, cy), li1(cx, cy - 1),
-                     li1(cx, cy + 1)};
-  const int back[5] = {0, 2, 1, 4, 3};  // from the -x neighbour, this cell is its +x
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    T om = sm.own[sl[0] * MS + v];
-    // means that supplied a max or min (self included)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const unsigned char cd = sm.code[sl[k]][v];
-      if ((cd & 7) == back[k]) om += sm.lhi[sl[k] * MS + v];
-      if ((cd >> 3) == back[k]) om += sm.llo[sl[k] * MS + v];
-    }
-    p.out[3 * v * nc + e] = om;
-  }
+template <bool LIM>
+__global__ __launch_bounds__(256) void k_adj_row_f32(PA<float> p) {
+  adj_row_body<float, LIM>(p);
+}
+
+template <typename T, bool LIM>
+void launch_row(const dim3& grid, const dim3& block, hipStream_t s, const PA<T>& p);
+template <>
+void launch_row<double, true>(const dim3& g, const dim3& b, hipStream_t s, const PA<double>& p) {
+  hipLaunchKernelGGL((k_adj_row_f64<true>), g, b, 0, s, p);
+}
+template <>
+void launch_row<double, false>(const dim3& g, const dim3& b, hipStream_t s, const PA<double>& p) {
+  hipLaunchKernelGGL((k_adj_row_f64<false>), g, b, 0, s, p);
+}
+template <>
+void launch_row<float, true>(const dim3& g, const dim3& b, hipStream_t s, const PA<float>& p) {
+  hipLaunchKernelGGL((k_adj_row_f32<true>), g, b, 0, s, p);
+}
+template <>
+void launch_row<float, false>(const dim3& g, const dim3& b, hipStream_t s, const PA<float>& p) {
+  hipLaunchKernelGGL((k_adj_row_f32<false>), g, b, 0, s, p);
 }
 
 template <typename T>
-hipError_t adj_stage_t(const AdjInst* inst, const int* tile_inst, int ntiles, int nc,
-                       int64_t total, const T* P, const T* lam, const T* extra, T* lamW, T* out,
-                       double c_id, double c_L_over_dt, double c_extra, const double* dt_dev,
-                       double dt_host, double gamma, bool lim, hipStream_t s) {
+hipError_t adj_stage_t(const AdjInst* inst, const int* tile_inst, int ntiles, int nc, const T* P,
+                       const T* lam, const T* extra, T* out, double c_id, double c_L_over_dt,
+                       double c_extra, const double* dt_dev, double dt_host, double gamma,
+                       bool lim, hipStream_t s) {
   PA<T> p;
   p.P = P;
   p.lam = lam;
   p.extra = extra;
-  p.lamW = lamW;
-  p.out = lim ? lamW : out;
+  p.out = out;
   p.inst = inst;
   p.tile_inst = tile_inst;
   p.dt_dev = dt_dev;
@@ -585,15 +675,11 @@ hipError_t adj_stage_t(const AdjInst* inst, const int* tile_inst, int ntiles, in
   p.nc = nc;
   p.ntiles = ntiles;
   p.gamma = (T)gamma;
-  p.limiter = lim;
+  const dim3 grid((ntiles + 3) / 4), block(256);
   if (lim)
-    hipLaunchKernelGGL((k_adj_lt<T, true>), dim3(ntiles), dim3(256), 0, s, p);
+    launch_row<T, true>(grid, block, s, p);
   else
-    hipLaunchKernelGGL((k_adj_lt<T, false>), dim3(ntiles), dim3(256), 0, s, p);
-  if (!lim) return hipGetLastError();
-  p.out = out;
-  hipLaunchKernelGGL((k_adj_pit<T>), dim3(ntiles), dim3(256), 0, s, p);
-  (void)total;
+    launch_row<T, false>(grid, block, s, p);
   return hipGetLastError();
 }
 
@@ -601,33 +687,35 @@ hipError_t adj_stage_t(const AdjInst* inst, const int* tile_inst, int ntiles, in
 
 // One adjoint step of a set of 2D Euler Cartesian instances (a single mesh is
 // one instance).  inst/tile_inst are device tables; V1 is the stage-1 output
-// of the forward step from U.  lam_np1 -> lam_n.  ws1, ws2: state-sized
-// workspaces.
+// of the forward step from U.  lam_np1 -> lam_n.  ws: one state-sized
+// workspace (lam_V1).
 hipError_t launch_adjoint2d(const void* inst, const int* tile_inst, int ntiles, int nc,
                             int64_t total, bool f64, bool lim, double gamma, const void* U,
                             const void* V1, const double* dt_dev, double dt_host,
                             const void* lam_np1, void* lam_n, void* ws1, void* ws2,
                             hipStream_t s) {
   const AdjInst* in = static_cast<const AdjInst*>(inst);
+  (void)total;
+  (void)ws1;
   hipError_t e;
   // stage 2: ws2 = lam_V1 = Pi_V1^T [lam'/2 + (dt/2) L^T lam']
   // stage 1: lam_n = Pi_U^T [lam_V1 + dt L^T lam_V1 + lam'/2]
   if (f64) {
     using T = double;
-    e = adj_stage_t<T>(in, tile_inst, ntiles, nc, total, (const T*)V1, (const T*)lam_np1, nullptr,
-                       (T*)ws1, (T*)ws2, 0.5, 0.5, 0.0, dt_dev, dt_host, gamma, lim, s);
+    e = adj_stage_t<T>(in, tile_inst, ntiles, nc, (const T*)V1, (const T*)lam_np1, nullptr,
+                       (T*)ws2, 0.5, 0.5, 0.0, dt_dev, dt_host, gamma, lim, s);
     if (e == hipSuccess)
-      e = adj_stage_t<T>(in, tile_inst, ntiles, nc, total, (const T*)U, (const T*)ws2,
-                         (const T*)lam_np1, (T*)ws1, (T*)lam_n, 1.0, 1.0, 0.5, dt_dev, dt_host,
-                         gamma, lim, s);
+      e = adj_stage_t<T>(in, tile_inst, ntiles, nc, (const T*)U, (const T*)ws2,
+                         (const T*)lam_np1, (T*)lam_n, 1.0, 1.0, 0.5, dt_dev, dt_host, gamma,
+                         lim, s);
   } else {
     using T = float;
-    e = adj_stage_t<T>(in, tile_inst, ntiles, nc, total, (const T*)V1, (const T*)lam_np1, nullptr,
-                       (T*)ws1, (T*)ws2, 0.5, 0.5, 0.0, dt_dev, dt_host, gamma, lim, s);
+    e = adj_stage_t<T>(in, tile_inst, ntiles, nc, (const T*)V1, (const T*)lam_np1, nullptr,
+                       (T*)ws2, 0.5, 0.5, 0.0, dt_dev, dt_host, gamma, lim, s);
     if (e == hipSuccess)
-      e = adj_stage_t<T>(in, tile_inst, ntiles, nc, total, (const T*)U, (const T*)ws2,
-                         (const T*)lam_np1, (T*)ws1, (T*)lam_n, 1.0, 1.0, 0.5, dt_dev, dt_host,
-                         gamma, lim, s);
+      e = adj_stage_t<T>(in, tile_inst, ntiles, nc, (const T*)U, (const T*)ws2,
+                         (const T*)lam_np1, (T*)lam_n, 1.0, 1.0, 0.5, dt_dev, dt_host, gamma,
+                         lim, s);
   }
   return e;
 }

@@ -95,19 +95,27 @@ static dg_status batch_upload(dg_mesh* m) {
   return DG_OK;
 }
 
-// Adjoint tables (15 x 16-cell tiles) of one or more 2D Cartesian instances.
+// Adjoint tables (58-column strips of kAdjRows rows) of one or more 2D Cartesian instances.
 static dg_status adjoint_tables(dg_mesh* m, const BatchDesc& d, bool batched) {
   std::vector<AdjInst> ai(d.ninst);
   std::vector<int> ti;
   int tile0 = 0;
+  // rows per wave: about kAdjWaves waves over the whole set, within
+  // [kAdjRowsMin, kAdjRowsMax] (each wave marches 4 rows beyond its own)
+  int64_t strips = 0;
+  for (int i = 0; i < d.ninst; ++i)
+    strips += (int64_t)((d.nx[i] + kAdjCols - 1) / kAdjCols) * d.ny[i];
+  const int rows = (int)std::min<int64_t>(
+      kAdjRowsMax, std::max<int64_t>(kAdjRowsMin, (strips + kAdjWaves - 1) / kAdjWaves));
   for (int i = 0; i < d.ninst; ++i) {
     AdjInst a{};
     a.nx = d.nx[i];
     a.ny = d.ny[i];
     a.off = (int)d.off[i];
     a.tx0 = tile0;
-    a.tiles_x = (a.nx + kAdjTileX - 1) / kAdjTileX;
-    a.tiles_y = (a.ny + kAdjTileY - 1) / kAdjTileY;
+    a.rows = std::min(rows, a.ny);
+    a.tiles_x = (a.nx + kAdjCols - 1) / kAdjCols;
+    a.tiles_y = (a.ny + a.rows - 1) / a.rows;
     a.hx = d.hx[i];
     a.hy = d.hy[i];
     ai[i] = a;

@@ -42,14 +42,17 @@ struct FaceList2D {
 };
 struct FLDev;
 
-// One 2D Cartesian instance of the adjoint kernels: a mesh of nx x ny cells
+// One 2D Cartesian instance of the adjoint kernel: a mesh of nx x ny cells
 // starting at cell `off` of the global state arrays, whose adjoint tiles
-// (kAdjTileX x kAdjTileY cells) start at tile `tx0` of the tile list.
-constexpr int kAdjTileX = 15;
-constexpr int kAdjTileY = 16;
+// (kAdjCols columns x `rows` rows, one wave each) start at tile `tx0` of the
+// tile list.
+constexpr int kAdjCols = 58;
+constexpr int kAdjRowsMin = 16;
+constexpr int kAdjRowsMax = 64;
+constexpr int kAdjWaves = 2048;
 struct AdjInst {
   int nx, ny, off, tx0;
-  int tiles_x, tiles_y, pad0, pad1;
+  int tiles_x, tiles_y, rows, pad;
   double hx, hy;
 };
 
