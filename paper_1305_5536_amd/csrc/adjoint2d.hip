@@ -241,12 +241,13 @@ __device__ __forceinline__ void flux_xy_vjp(const T* u, T gamma, const T* a, con
 }
 
 // ------------------------------------------------------------ row kernel --
-// Limiter branch data of one row (per lane): alpha and dm per variable, the
+// Limiter branch data of one row (per lane): alpha per variable, the
 // arg-max / arg-min codes (6 bits per variable) and the active / D-from-max /
-// dm-from-x flags (3 bits per variable).
+// dm-from-x flags (3 bits per variable).  dm is recomputed from the gradient
+// and the axis flag when needed.
 template <typename T>
 struct LimRow {
-  T alpha[4], dm[4];
+  T alpha[4];
   unsigned code, flag;
 };
 
@@ -334,7 +335,6 @@ __device__ __forceinline__ void adj_row_body(const PA<T>& p) {
     for (int v = 0; v < 4; ++v) {
       g1[2 * v] = g1[2 * v + 1] = T(0);
       lr1.alpha[v] = T(1);
-      lr1.dm[v] = T(0);
       pr3.lhi[v] = pr3.llo[v] = T(0);
       own3[v] = T(0);
     }
@@ -398,13 +398,11 @@ __device__ __forceinline__ void adj_row_body(const PA<T>& p) {
         T nb[5] = {m1[v], lane_up(m1[v]), lane_down(m1[v]), m2[v], m0[v]};
         LimInfo<T> li = lim_info(nb, g1[2 * v], g1[2 * v + 1], hx2, hy2);
         lr1.alpha[v] = li.alpha;
-        lr1.dm[v] = li.dm;
         lr1.code |= (unsigned)(li.amax | (li.amin << 3)) << (6 * v);
         lr1.flag |= (unsigned)((li.active ? 1 : 0) | (li.dplus ? 2 : 0) | (li.xaxis ? 4 : 0))
                     << (3 * v);
       } else {
         lr1.alpha[v] = T(1);
-        lr1.dm[v] = T(0);
       }
     }
 
@@ -557,7 +555,8 @@ __device__ __forceinline__ void adj_row_body(const PA<T>& p) {
           T om = acc2[3 * v], ogx = al * lgx, ogy = al * lgy;
           if (fl & 1u) {
             const T la = gx * lgx + gy * lgy;
-            const T idm = rcp(lr2.dm[v]);
+            const T dm = (fl & 4u) ? fabs(gx) * hx2 : fabs(gy) * hy2;
+            const T idm = rcp(dm);
             const T lD = la * idm;
             const T ldm = -la * al * idm;
             if (fl & 2u) {
@@ -584,39 +583,32 @@ __device__ __forceinline__ void adj_row_body(const PA<T>& p) {
     // S4: row j-3's mean adjoints (self, -x, +x, -y = row j-4, +y = row j-2)
     if (LIM) {
       const int r3 = j - 3;
-      PitRow<T> pl, pr;
-      pl.code = lane_up_u(pr3.code);
-      pr.code = lane_down_u(pr3.code);
+      const bool wr = own && r3 >= y0 && r3 < y1;
+      const unsigned o = roff(r3);
+      const unsigned cla = lane_up_u(pr3.code), cra = lane_down_u(pr3.code);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        pl.lhi[v] = lane_up(pr3.lhi[v]);
-        pl.llo[v] = lane_up(pr3.llo[v]);
-        pr.lhi[v] = lane_down(pr3.lhi[v]);
-        pr.llo[v] = lane_down(pr3.llo[v]);
-      }
-      if (own && r3 >= y0 && r3 < y1) {
-        const unsigned o = roff(r3);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int sh = 6 * v;
-          T om = own3[v];
-          // the code a neighbour uses for this cell: self 0, from -x it is +x (2),
-          // from +x it is -x (1), from -y (row below) +y (4), from +y -y (3)
-          const unsigned cs = (pr3.code >> sh) & 63u, cl = (pl.code >> sh) & 63u,
-                         cr = (pr.code >> sh) & 63u, cd = (pr4.code >> sh) & 63u,
-                         cu = (pr2.code >> sh) & 63u;
-          if ((cs & 7u) == 0u) om += pr3.lhi[v];
-          if ((cs >> 3) == 0u) om += pr3.llo[v];
-          if ((cl & 7u) == 2u) om += pl.lhi[v];
-          if ((cl >> 3) == 2u) om += pl.llo[v];
-          if ((cr & 7u) == 1u) om += pr.lhi[v];
-          if ((cr >> 3) == 1u) om += pr.llo[v];
-          if ((cd & 7u) == 4u) om += pr4.lhi[v];
-          if ((cd >> 3) == 4u) om += pr4.llo[v];
-          if ((cu & 7u) == 3u) om += pr2.lhi[v];
-          if ((cu >> 3) == 3u) om += pr2.llo[v];
-          st(O, nc, 3 * v, o, om);
-        }
+        // lane shifts run on every lane; only the owning lanes use them
+        const T lhl = lane_up(pr3.lhi[v]), lll = lane_up(pr3.llo[v]);
+        const T lhr = lane_down(pr3.lhi[v]), llr = lane_down(pr3.llo[v]);
+        const int sh = 6 * v;
+        T om = own3[v];
+        // the code a neighbour uses for this cell: self 0, from -x it is +x (2),
+        // from +x it is -x (1), from -y (row below) +y (4), from +y -y (3)
+        const unsigned cs = (pr3.code >> sh) & 63u, cl = (cla >> sh) & 63u,
+                       cr = (cra >> sh) & 63u, cd = (pr4.code >> sh) & 63u,
+                       cu = (pr2.code >> sh) & 63u;
+        if ((cs & 7u) == 0u) om += pr3.lhi[v];
+        if ((cs >> 3) == 0u) om += pr3.llo[v];
+        if ((cl & 7u) == 2u) om += lhl;
+        if ((cl >> 3) == 2u) om += lll;
+        if ((cr & 7u) == 1u) om += lhr;
+        if ((cr >> 3) == 1u) om += llr;
+        if ((cd & 7u) == 4u) om += pr4.lhi[v];
+        if ((cd >> 3) == 4u) om += pr4.llo[v];
+        if ((cu & 7u) == 3u) om += pr2.lhi[v];
+        if ((cu >> 3) == 3u) om += pr2.llo[v];
+        if (wr) st(O, nc, 3 * v, o, om);
       }
       pr4 = pr3;
       pr3 = pr2;
@@ -631,8 +623,11 @@ __global__ __launch_bounds__(256) void k_adj_row_f64(PA<double> p) {
   adj_row_body<double, LIM>(p);
 }
 
+// FP32: two waves per SIMD, at the price of a few values spilled (16 bytes per
+// lane), measured faster than one wave per SIMD without spills.
 template <bool LIM>
-__global__ __launch_bounds__(256) void k_adj_row_f32(PA<float> p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_row_f32(
+    PA<float> p) {
   adj_row_body<float, LIM>(p);
 }
 

@@ -1,0 +1,156 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times
+(library-default tiling, device step sizes, fused CFL minima, batched graph).
+
+* C2 2048^2 and C4 (10^6 Voronoi cells): two FP64 steps on the oracle's own
+  step schedule, every cell compared (the oracle finishes a step in about a
+  second on the host's cores); the FP32 error is stated.
+* C3 256^3 MHD: one FP64 step against the oracle, every cell.
+* C5 (256 instances, N in {64..512}): the full batch in its bench launch shape;
+  four sampled instances (the first, the largest and two others) carry the
+  seeded recipe and are compared with the oracle; the others hold a uniform
+  state (instances are independent).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G53 = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def errs_hydro(A, B, nvar, dim, h, ncoef):
+    """err_k = max(|d mean_k|, h |d grad_k|) / max|mean_k| per hydro variable
+    (each scale floored at the density scale: momenta that vanish)."""
+    A = A.reshape(ncoef, -1)
+    B = B.reshape(ncoef, -1)
+    out = []
+    rho_scale = np.abs(B[0]).max()
+    for v in range(nvar):
+        k = v * (1 + dim)
+        scale = max(np.abs(B[k]).max(), rho_scale)
+        d = np.abs(A[k] - B[k]).max()
+        for c in range(1, 1 + dim):
+            d = max(d, h * np.abs(A[k + c] - B[k + c]).max())
+        out.append(d / scale)
+    return np.array(out)
+
+
+def _run_gpu(s, U0, dts):
+    """The bench's step: stage 1, stage 2 (with the fused CFL reduction), on
+    device step sizes."""
+    torch = __import__("torch")
+    U = s.to_device(U0)
+    V1, Un = s.empty(), s.empty()
+    nxt = torch.empty(s.ninst, dtype=torch.float64, device=s.device)
+    for dt in dts:
+        d = torch.tensor(dt, dtype=torch.float64, device=s.device).reshape(-1)
+        s.stage1(U, d, V1)
+        s.stage2(U, V1, d, Un, cfl=0.3, dt_next=nxt)
+        U, Un = Un, U
+    s.check()
+    return U
+
+
+def test_c2_full_size(oracle, torch_cuda):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    n = 2048
+    U0 = W.c2_state(n)
+    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    ref, dts = oracle.run(om, U0, 2, G53, 0.3, True)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), precision=prec, gamma=G53)
+        got = _run_gpu(s, U0, dts).double().cpu().numpy()
+        e = errs_hydro(got, ref, 4, 2, 1.0 / n, 12)
+        print(f"C2 2048^2 {prec}, 2 steps, per-field error: {e}")
+        assert e.max() < tol, (prec, e)
+        s.close()
+
+
+def test_c4_full_size(oracle, torch_cuda):
+    from paper_1305_5536_amd.solver import Solver
+    from workloads.voronoi import c4_state, periodic_voronoi
+    m = periodic_voronoi(1000000, seed=1004)
+    U0 = c4_state(m)
+    om = oracle.Mesh.facelist(m)
+    ref, dts = oracle.run(om, U0, 2, G53, 0.3, True)
+    h = math.sqrt(m["cell_volume"].min())
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(m, precision=prec, gamma=G53)
+        got = _run_gpu(s, U0, dts).double().cpu().numpy()
+        e = errs_hydro(got, ref, 4, 2, h, 12)
+        print(f"C4 10^6 cells {prec}, 2 steps, per-field error: {e}")
+        assert e.max() < tol, (prec, e)
+        s.close()
+
+
+def test_c3_full_size(oracle, torch_cuda):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    n = 256
+    U0 = W.c3_state(n)
+    om = oracle.Mesh.cartesian((n,) * 3, (0.0,) * 3, (1.0,) * 3)
+    dt = oracle.cfl_dt(om, U0, G53, 0.3, mhd=True)
+    ref = oracle.step(om, U0, dt, G53, True, mhd=True)
+    s = Solver(cartesian((n,) * 3, (0.0,) * 3, (1.0,) * 3), physics="mhd", gamma=G53)
+    got = _run_gpu(s, U0, [dt]).cpu().numpy()
+    e = errs_hydro(got, ref, 5, 3, 1.0 / n, 31)
+    A, B = got.reshape(31, -1), ref.reshape(31, -1)
+    eb = max(np.abs(A[20:23] - B[20:23]).max(), np.abs(A[23:] - B[23:]).max() / n) / \
+        np.abs(B[20:23]).max()
+    print(f"C3 256^3 fp64, 1 step, per-field error: {e}, B: {eb:.3e}")
+    assert e.max() < 1e-12 and eb < 1e-12, (e, eb)
+
+
+def test_c5_full_batch_sampled(oracle, torch_cuda):
+    from paper_1305_5536_amd import autotune
+    from paper_1305_5536_amd.solver import Solver, batch
+    sizes = W.batched_instances(256)
+    big = int(np.argmax(sizes))
+    sample = sorted({0, big, 17, 200})
+    uni = {}
+    states = []
+    for i, N in enumerate(sizes):
+        if i in sample:
+            states.append(W.batched_state(N, 2005 + i))
+        else:
+            if N not in uni:
+                U = np.zeros((12, N * N))
+                U[0] = 1.0
+                U[9] = 1.0 / (G53 - 1.0)
+                uni[N] = U.reshape(-1)
+            states.append(uni[N])
+    shapes = [(N, N) for N in sizes]
+    refs, dts = {}, {}
+    for i in sample:
+        om = oracle.Mesh.cartesian(shapes[i], (0.0, 0.0), (1.0, 1.0))
+        refs[i], dts[i] = oracle.run(om, states[i], 2, G53, 0.3, True)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(batch(shapes), precision=prec, gamma=G53)
+        U0 = s.pack(states)
+        autotune.autotune_batch(s, U0, shapes, use_cache=False)
+        # the oracle's schedule for the sampled instances, any valid dt elsewhere
+        dth = s.cfl_dt(U0, 0.3).cpu().numpy()
+        sched = np.tile(dth, (2, 1))
+        for i in sample:
+            sched[:, i] = dts[i]
+        torch = torch_cuda
+        out, _ = s.run(U0, 2, dt_hist=torch.tensor(sched.reshape(-1), device=s.device,
+                                                    dtype=torch.float64), graph=True)
+        s.check()
+        got = s.unpack(out)
+        for i in sample:
+            e = errs_hydro(got[i], refs[i], 4, 2, 1.0 / sizes[i], 12)
+            print(f"C5 instance {i} (N={sizes[i]}) {prec}, 2 steps: {e}")
+            assert e.max() < tol, (prec, i, e)
+        s.close()
