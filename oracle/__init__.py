@@ -63,6 +63,13 @@ def lib():
         L.or_step_jvp.restype = ctypes.c_int
         L.or_step_jvp.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   _dp, _dp, ctypes.c_double, _dp, _dp]
+        L.or_step_mh.restype = ctypes.c_int
+        L.or_step_mh.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp,
+                                 ctypes.c_double, _dp]
+        L.or_rhs_mh.restype = ctypes.c_int
+        L.or_rhs_mh.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_double, _dp]
+        L.or_predict_prim.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_double,
+                                      _dp, _dp]
         L.or_rhs_jvp.restype = ctypes.c_int
         L.or_rhs_jvp.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
                                  _dp]
@@ -226,9 +233,42 @@ def cfl_dt(mesh: Mesh, U, gamma: float, cfl: float, mhd: bool = False) -> float:
     return lib().or_cfl_dt(mesh._h, int(mhd), gamma, _p(U), cfl)
 
 
+def step_mh(mesh: Mesh, U, dt: float, gamma: float, limiter: bool) -> np.ndarray:
+    """One MUSCL-Hancock step (Euler): Ua = Pi(U), U' = Ua + dt L_MH(Ua; dt/2)."""
+    U = _state(mesh, U, False)
+    out = np.empty_like(U)
+    if lib().or_step_mh(mesh._h, int(limiter), gamma, _p(U), dt, _p(out)):
+        raise NonPhysical("non-physical state in the MUSCL-Hancock step")
+    return out
+
+
+def rhs_mh(mesh: Mesh, U, half_dt: float, gamma: float) -> np.ndarray:
+    """The MUSCL-Hancock operator: surface and volume terms of the half-step
+    primitive prediction (no limiter)."""
+    U = _state(mesh, U, False)
+    out = np.empty_like(U)
+    rc = lib().or_rhs_mh(mesh._h, gamma, _p(U), half_dt, _p(out))
+    if rc:
+        raise NonPhysical("non-physical state in the MUSCL-Hancock operator")
+    return out
+
+
+def predict_prim(mean, grad, gamma: float, half_dt: float):
+    """(primitive centroid values advanced by half_dt, primitive gradients
+    [nvar x 3]) of one cell from its conserved mean and gradients."""
+    mean = _f64(mean)
+    dim = len(mean) - 2
+    grad = _f64(grad).reshape(dim + 2, dim)
+    prim = np.empty(dim + 2)
+    gprim = np.empty((dim + 2) * 3)
+    lib().or_predict_prim(dim, gamma, _p(mean), _p(grad), half_dt, _p(prim), _p(gprim))
+    return prim, gprim.reshape(dim + 2, 3)[:, :dim]
+
+
 def run(mesh: Mesh, U, nsteps: int, gamma: float, cfl: float, limiter: bool,
-        mhd: bool = False, t_end: float | None = None):
-    """Advance nsteps (or until t_end) with the CFL step; returns (U, dt list)."""
+        mhd: bool = False, t_end: float | None = None, integrator: str = "rk2"):
+    """Advance nsteps (or until t_end) with the CFL step; returns (U, dt list).
+    integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock, Euler only)."""
     U = _f64(U).copy()
     dts = []
     t = 0.0
@@ -238,7 +278,10 @@ def run(mesh: Mesh, U, nsteps: int, gamma: float, cfl: float, limiter: bool,
             if t >= t_end * (1 - 1e-14):
                 break
             dt = min(dt, t_end - t)
-        U = step(mesh, U, dt, gamma, limiter, mhd)
+        if integrator == "mh":
+            U = step_mh(mesh, U, dt, gamma, limiter)
+        else:
+            U = step(mesh, U, dt, gamma, limiter, mhd)
         dts.append(dt)
         t += dt
     return U, dts

@@ -620,6 +620,86 @@ template <class T> bool physical(const Phys& P, const T* u) {
   return finite(p) && p > T(0);
 }
 
+// ------------------------------------------------ MUSCL-Hancock prediction --
+// Sec. 2.4: the cell's conserved mean and gradients are turned into primitive
+// values (rho, v, p) and primitive gradients at the centroid (chain rule, as
+// in the paper's example for d(v_x)/dy); the primitive state is advanced half
+// a step with its time derivative from the quasi-linear Euler equations,
+//   rho_t = -(v . grad rho + rho div v)
+//   v_t   = -(v . grad) v - grad p / rho
+//   p_t   = -(gamma p div v + v . grad p),
+// evaluated with the centroid values and gradients, and extrapolated
+// linearly to the point r (a face Gauss point or a volume point), then turned
+// back into conserved variables for the Riemann solver and the volume flux.
+// Euler only.
+template <class T> struct Prim {
+  T w[5];        // rho, v (dim components), p at the centroid, advanced by half_dt
+  T gw[5][3];    // primitive gradients
+};
+
+template <class T> void predict_prim(const Phys& P, const Poly<T>& q, double half_dt, Prim<T>& out) {
+  const int dim = P.dim;
+  const T rho = q.m[0];
+  T v[3] = {T(0), T(0), T(0)};
+  for (int d = 0; d < dim; ++d) v[d] = q.m[1 + d] / rho;
+  T v2 = T(0);
+  for (int d = 0; d < dim; ++d) v2 += v[d] * v[d];
+  const T E = q.m[1 + dim];
+  const T gm1 = T(P.gamma - 1.0);
+  const T p = gm1 * (E - T(0.5) * rho * v2);
+  // primitive gradients at the centroid
+  T grho[3], gv[3][3], gp[3];
+  for (int d = 0; d < dim; ++d) {
+    grho[d] = q.g[0][d];
+    for (int i = 0; i < dim; ++i) gv[i][d] = (q.g[1 + i][d] - v[i] * grho[d]) / rho;
+    // E = p/(gamma-1) + rho |v|^2 / 2
+    T s = q.g[1 + dim][d] - T(0.5) * v2 * grho[d];
+    for (int i = 0; i < dim; ++i) s -= rho * v[i] * gv[i][d];
+    gp[d] = gm1 * s;
+  }
+  T div = T(0);
+  for (int d = 0; d < dim; ++d) div += gv[d][d];
+  T vgrho = T(0), vgp = T(0);
+  for (int d = 0; d < dim; ++d) {
+    vgrho += v[d] * grho[d];
+    vgp += v[d] * gp[d];
+  }
+  const T rho_t = -(vgrho + rho * div);
+  const T p_t = -(T(P.gamma) * p * div + vgp);
+  const T h = T(half_dt);
+  out.w[0] = rho + h * rho_t;
+  for (int i = 0; i < dim; ++i) {
+    T adv = T(0);
+    for (int d = 0; d < dim; ++d) adv += v[d] * gv[i][d];
+    const T vt = -(adv + gp[i] / rho);
+    out.w[1 + i] = v[i] + h * vt;
+  }
+  out.w[1 + dim] = p + h * p_t;
+  for (int d = 0; d < dim; ++d) {
+    out.gw[0][d] = grho[d];
+    for (int i = 0; i < dim; ++i) out.gw[1 + i][d] = gv[i][d];
+    out.gw[1 + dim][d] = gp[d];
+  }
+}
+
+// Conserved state of the predicted primitive polynomial at offset r.
+template <class T> void eval_prim(const Phys& P, const Prim<T>& pr, const double* r, T* u) {
+  const int dim = P.dim;
+  T w[5];
+  for (int k = 0; k < dim + 2; ++k) {
+    T s = pr.w[k];
+    for (int d = 0; d < dim; ++d) s += pr.gw[k][d] * T(r[d]);
+    w[k] = s;
+  }
+  T v2 = T(0);
+  u[0] = w[0];
+  for (int d = 0; d < dim; ++d) {
+    u[1 + d] = w[0] * w[1 + d];
+    v2 += w[1 + d] * w[1 + d];
+  }
+  u[1 + dim] = w[1 + dim] / T(P.gamma - 1.0) + T(0.5) * w[0] * v2;
+}
+
 // Solve the small symmetric system A x = b (Gaussian elimination with
 // partial pivoting), n <= 8.
 template <class T> void solve_small(int n, const double* Ain, const T* b, T* x) {
@@ -676,8 +756,11 @@ struct Ctx {
 // Semi-discrete right-hand side L(U) for one cell (Sec. 2.2): surface terms
 // over the cell's faces (Gauss points in order), then the volume term, then
 // the inverse mass matrices.  Returns false on a non-physical state.
+// half_dt < 0: the semi-discrete operator L(U) of the cell polynomials.
+// half_dt >= 0: the MUSCL-Hancock operator, the same surface and volume terms
+// with every state taken from the half-step primitive prediction (Sec. 2.4).
 template <class T>
-bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e) {
+bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.0) {
   const Mesh& M = *C.mesh;
   const Phys& P = C.P;
   const int dim = P.dim, nv = P.nv(), nh = P.nhyd();
@@ -702,6 +785,11 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e) {
     Poly<T> qL, qR;
     load_poly(P, U, nc, fg.L, qL);
     load_poly(P, U, nc, fg.R, qR);
+    Prim<T> pL, pR;
+    if (half_dt >= 0) {
+      predict_prim(P, qL, half_dt, pL);
+      predict_prim(P, qR, half_dt, pR);
+    }
     for (int p = 0; p < fg.ng; ++p) {
       double rL[3], rR[3];
       for (int d = 0; d < 3; ++d) {
@@ -710,8 +798,13 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e) {
         if (d >= dim) rL[d] = rR[d] = 0.0;
       }
       T uL[8], uR[8], F[8];
-      eval_poly(P, qL, rL, uL);
-      eval_poly(P, qR, rR, uR);
+      if (half_dt >= 0) {
+        eval_prim(P, pL, rL, uL);
+        eval_prim(P, pR, rR, uR);
+      } else {
+        eval_poly(P, qL, rL, uL);
+        eval_poly(P, qR, rR, uR);
+      }
       if (P.mhd) {
         // One normal field for the Riemann problem: the average of the two
         // extrapolated normal components (Sec. 2.6).
@@ -747,9 +840,14 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e) {
   }
   // Volume term: int F . grad(test) dOmega, with grad(x_d) = e_d for the
   // Taylor basis and the constant derivatives of V4..V11 for B.
+  Prim<T> pe;
+  if (half_dt >= 0) predict_prim(P, qe, half_dt, pe);
   for (int q = 0; q < cg.nq; ++q) {
     T u[8];
-    eval_poly(P, qe, cg.rq[q], u);
+    if (half_dt >= 0)
+      eval_prim(P, pe, cg.rq[q], u);
+    else
+      eval_poly(P, qe, cg.rq[q], u);
     if (!physical(P, u)) ok = false;
     T Fd[3][8];
     for (int d = 0; d < dim; ++d) {
@@ -859,12 +957,12 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
   store_poly(P, Ul, nc, e, q);
 }
 
-template <class T> int rhs_all(const Ctx& C, const T* U, T* dUdt) {
+template <class T> int rhs_all(const Ctx& C, const T* U, T* dUdt, double half_dt = -1.0) {
   int64_t nc = C.mesh->nc;
   int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (int64_t e = 0; e < nc; ++e)
-    if (!rhs_cell(C, U, dUdt, e)) bad |= 1;
+    if (!rhs_cell(C, U, dUdt, e, half_dt)) bad |= 1;
   return bad;
 }
 
@@ -896,6 +994,22 @@ template <class T> int step_all(const Ctx& C, const T* U, double dt, T* Un) {
   bad |= rhs_all(C, Ub.data(), L2.data());
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < len; ++i) Un[i] = T(0.5) * Ua[i] + T(0.5) * (Ub[i] + T(dt) * L2[i]);
+  return bad;
+}
+
+// One MUSCL-Hancock step (Sec. 2.4), the limiter at the start of the step:
+//   Ua = Pi(U);  U_next = Ua + dt L_MH(Ua; dt/2),
+// L_MH the surface and volume terms of the half-step primitive prediction.
+template <class T> int step_mh_all(const Ctx& C, const T* U, double dt, T* Un) {
+  int64_t len = (int64_t)C.P.ncoef() * C.mesh->nc;
+  std::vector<T> Ua(len), L(len);
+  if (C.limiter)
+    limit_all(C, U, Ua.data());
+  else
+    std::copy(U, U + len, Ua.begin());
+  int bad = rhs_all(C, Ua.data(), L.data(), 0.5 * dt);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < len; ++i) Un[i] = Ua[i] + T(dt) * L[i];
   return bad;
 }
 
@@ -1035,6 +1149,37 @@ void or_limit(void* h, int mhd, const double* U, double* Ul) {
 int or_step(void* h, int mhd, int limiter, double gamma, const double* U, double dt, double* Un) {
   Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma}, limiter};
   return step_all(C, U, dt, Un) ? 5 : 0;
+}
+
+// MUSCL-Hancock step and operator (Euler only; 5 = non-physical, 4 = MHD).
+int or_step_mh(void* h, int limiter, double gamma, const double* U, double dt, double* Un) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma}, limiter};
+  return step_mh_all(C, U, dt, Un) ? 5 : 0;
+}
+
+int or_rhs_mh(void* h, double gamma, const double* U, double half_dt, double* L) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma}, 0};
+  if (!(half_dt >= 0)) return 1;
+  return rhs_all(C, U, L, half_dt) ? 5 : 0;
+}
+
+// The predicted primitive polynomial of one cell state (for unit pins):
+// prim[0..dim+1] the centroid values advanced by half_dt, gprim[k*3+d] the
+// primitive gradients.
+void or_predict_prim(int dim, double gamma, const double* mean, const double* grad,
+                     double half_dt, double* prim, double* gprim) {
+  Phys P{dim, 0, gamma};
+  Poly<double> q;
+  for (int v = 0; v < dim + 2; ++v) {
+    q.m[v] = mean[v];
+    for (int d = 0; d < 3; ++d) q.g[v][d] = d < dim ? grad[v * dim + d] : 0.0;
+  }
+  Prim<double> pr;
+  predict_prim(P, q, half_dt, pr);
+  for (int k = 0; k < dim + 2; ++k) {
+    prim[k] = pr.w[k];
+    for (int d = 0; d < 3; ++d) gprim[k * 3 + d] = d < dim ? pr.gw[k][d] : 0.0;
+  }
 }
 
 // Directional derivative of one step: Un = S(U), dUn = (dS/dU) dU.
