@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--no-fp32", dest="also_fp32", action="store_false")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=None)
+    p.add_argument("--integrator", choices=["rk2", "mh"], default="rk2",
+                   help="c1/c2: SSP-RK2 (default, two stage kernels per step) or the paper's "
+                        "MUSCL-Hancock step (one kernel per step)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 5 device copies of 1 GiB (the reference kernel that scales "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counts to bytes) and exit")
@@ -133,6 +136,37 @@ def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3):
     return {"wall_s": wall, "event_s": tev, "stage1_s": t1, "stage2_s": t2, "dt_last": final_dt}
 
 
+def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3):
+    """MUSCL-Hancock steps (one kernel each, with the fused CFL minima and the
+    dt reduction), HIP events around every launch pair."""
+    import torch
+
+    from paper_1305_5536_amd.solver import Solver
+    s = Solver(mesh, physics="euler", precision=precision, limiter=limiter, gamma=gamma)
+    U = s.to_device(U0)
+    Un = s.empty()
+    dt = s.cfl_dt(U, cfl)
+    for _ in range(warmup):
+        s.step_mh(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    s.check()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        s.step_mh(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        ev[k + 1].record(stream)
+        U, Un = Un, U
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.check()
+    tev = ev[0].elapsed_time(ev[-1]) * 1e-3
+    s.close()
+    return {"wall_s": wall, "event_s": tev, "step_s": tev / steps}
+
+
 def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label=""):
     import oracle
     om = oracle.Mesh.cartesian((n,) * dim, (0.0,) * dim, (1.0,) * dim)
@@ -152,12 +186,60 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_mh(a, U0, mesh, ncells, gamma, limiter, workload, oracle_mesh):
+    """The MUSCL-Hancock variant of a 2D Cartesian config: one kernel per step;
+    the metric counts cells x flux passes (one per step)."""
+    elem = 8 if a.precision == "fp64" else 4
+    r = run_gpu_mh(U0, mesh, gamma, a.precision, a.steps, a.warmup, limiter=limiter)
+    per_launch = 24 * elem * ncells  # reads U, writes U_next
+    achieved = per_launch / r["step_s"] / 1e9
+    out = {
+        "metric": METRIC, "value": ncells * a.steps / r["event_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": r["step_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": workload + ", MUSCL-Hancock integrator (one flux pass per step)",
+                   "cells": ncells, "flux_passes_per_step": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cart2d MUSCL-Hancock step (+ dt reduction)",
+                     "bytes_per_launch": per_launch, "avg_launch_s": r["step_s"]},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu_mh(U0, mesh, gamma, "fp32", a.steps, a.warmup, limiter=limiter)
+        out["fp32"] = {"value": ncells * a.steps / r32["event_s"],
+                       "ms_per_step": r32["step_s"] * 1e3,
+                       "GBs": 24 * 4 * ncells / r32["step_s"] / 1e9}
+    if not a.no_cpu:
+        import oracle
+        log("timing the CPU oracle (MUSCL-Hancock)")
+        om = oracle.Mesh.cartesian(*oracle_mesh)
+        dt = oracle.cfl_dt(om, U0, gamma, 0.3)
+        t1 = time.perf_counter()
+        Uc = U0
+        for _ in range(a.cpu_steps):
+            Uc = oracle.step_mh(om, Uc, dt, gamma, limiter)
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": ncells * a.cpu_steps / el, "unit": "cell-updates/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{a.cpu_steps} MUSCL-Hancock steps of the same state, "
+                                         f"FP64, {el:.1f} s"}
+    return out
+
+
 def bench_c2(a):
     import workloads as W
     from paper_1305_5536_amd.solver import cartesian
     n = a.n
     log(f"generating the {n}x{n} shear-layer state")
     U0 = W.c2_state(n)
+    if a.integrator == "mh":
+        return bench_mh(a, U0, cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), n * n, 5.0 / 3.0, True,
+                        f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, P1 Taylor "
+                        "DG, HLL, limiter on, CFL 0.3",
+                        ((n, n), (0.0, 0.0), (1.0, 1.0)))
     log("timing the GPU steps")
     elem = 8 if a.precision == "fp64" else 4
     mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
@@ -250,6 +332,11 @@ def bench_c1(a):
     n = a.n
     U0 = W.c1_state(n)
     mesh = cartesian((n, n), (0.0, 0.0), (10.0, 10.0))
+    if a.integrator == "mh":
+        return bench_mh(a, U0, mesh, n * n, 1.4, False,
+                        f"2D Euler isentropic vortex, periodic Cartesian {n}x{n} on [0,10]^2, "
+                        "gamma 1.4, HLL, no limiter, CFL 0.3",
+                        ((n, n), (0.0, 0.0), (10.0, 10.0)))
     from paper_1305_5536_amd.solver import Solver
     log("timing the GPU steps")
     s = Solver(mesh, physics="euler", precision=a.precision, limiter=False, gamma=1.4)

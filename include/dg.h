@@ -175,6 +175,22 @@ dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next,
 dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,
                         void* stream);
 
+/* One MUSCL-Hancock step, the paper's own integrator (Sec. 2.4):
+ *   Ua = Pi(U);  U_next = Ua + dt L_MH(Ua; dt/2),
+ * where L_MH has the surface and volume terms of dg_rhs (eqn:GalerkUpdate)
+ * but takes every face Gauss-point and volume-point state from the cell's
+ * half-step prediction: primitive values (rho, v, p) and gradients at the
+ * centroid from the conserved mean and gradients (chain rule), advanced by
+ * dt/2 with the quasi-linear Euler time derivatives, extrapolated linearly
+ * and converted back to conserved variables.  One kernel per step (half the
+ * flux passes of the SSP-RK2 step).  Step size: *dt_dev (one per instance on
+ * a batch) when dt_dev is not NULL, else dt.  When dt_next_dev is not NULL,
+ * also writes the CFL step of U_next (as dg_stage2).  U_next must not alias
+ * U.  Built for 2D Euler on Cartesian meshes and batches (DG_EUNSUPPORTED
+ * otherwise). */
+dg_status dg_step_mh(dg_mesh_t mesh, const void* U, void* U_next, double dt, const double* dt_dev,
+                     double cfl, double* dt_next_dev, void* stream);
+
 /* Discrete adjoint of dg_step (vector-Jacobian product), dt frozen:
  *   lam_n = (d step(U, dt) / d U)^T lam_np1
  * through both stages, both limiter applications (the branch the forward step
@@ -190,8 +206,10 @@ dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const doubl
 dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double dt,
                           const double* dt_dev, const void* lam_np1, void* lam_n, void* stream);
 
-/* Flag of dg_run: capture the launch sequence into a hipGraph. */
+/* Flags of dg_run: capture the launch sequence into a hipGraph; step with
+ * dg_step_mh (MUSCL-Hancock, one kernel per step) instead of SSP-RK2. */
 #define DG_RUN_GRAPH 1
+#define DG_RUN_MUSCL_HANCOCK 2
 
 /* nsteps SSP-RK2 steps (the dg_stage1/dg_stage2 pair of each step) from U_in
  * to U_out, with per-step (per-instance) step sizes in the device array
@@ -204,7 +222,7 @@ dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double 
  *   state-sized DEVICE buffers; ckpt[j] receives the state after step
  *   (j + 1) ckpt_every (written by that step's stage 2, no extra copy).
  * v1_keep: NULL, or a HOST array of nsteps DEVICE buffers that receive each
- *   step's stage-1 output (the V1 of dg_adjoint_step).
+ *   step's stage-1 output (the V1 of dg_adjoint_step); SSP-RK2 only.
  * U_in is not modified (unless it is U_out); U_out may equal U_in only when
  * nsteps >= 2; U_out, the checkpoints and v1_keep buffers must be distinct.
  * Intermediate states ping-pong through two state-sized workspaces of the

@@ -17,6 +17,7 @@ DG_FP64, DG_FP32 = 0, 1
 DG_FLUX_HLL, DG_FLUX_HLLD = 0, 1
 DG_LIMITER_NONE, DG_LIMITER_MINMOD = 0, 1
 DG_RUN_GRAPH = 1
+DG_RUN_MUSCL_HANCOCK = 2
 
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ENOMEM", 3: "DG_EHIP", 4: "DG_EUNSUPPORTED",
                 5: "DG_ENONPHYSICAL"}
@@ -77,6 +78,9 @@ SYMBOLS = [
     ("dg_adjoint_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_step_mh", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_run", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),

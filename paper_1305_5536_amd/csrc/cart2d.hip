@@ -18,6 +18,12 @@
 // left; the y-face between the window rows is solved by the lane of that
 // column.
 //
+// MUSCL-Hancock mode (Sec. 2.4): the same faces and volume points, with every
+// state taken from the cell's half-step primitive prediction (centroid
+// primitive values and gradients from the limited conserved coefficients,
+// advanced dt/2 with the quasi-linear Euler time derivatives, extrapolated
+// linearly, converted back to conserved variables); one pass per step.
+//
 // Per-cell algebra (weights and the inverse mass matrix folded together).
 // With S = F(g0) + F(g1) and D = F(g1) - F(g0) for the two Gauss points of a
 // face (g0 at the lower tangential offset), and sum_q F_d(q) the volume
@@ -48,7 +54,7 @@ struct P2 {
   double* dt_next;
   double cfl;
   int nx, ny, rows, tiles_x, ntiles, nc;
-  T gamma;
+  T gamma, igm1;              // gamma, 1/(gamma - 1)
   T cmx, cmy, cgx, cgy, ccr;  // 1/(2hx), 1/(2hy), 3/hx^2, 3/hy^2, sqrt3/(hx hy)
   T hx2, hy2, qx, qy;         // hx/2, hy/2, hx/(2 sqrt3), hy/(2 sqrt3)
   double ihx, ihy;            // 1/hx, 1/hy
@@ -171,9 +177,50 @@ __device__ __forceinline__ void flux_xy(const T* u, T gamma, T* Fx, T* Fy, bool&
   Fy[3] = (u[3] + p) * vy;
 }
 
+// Half-step primitive prediction of a limited cell: the returned Cell holds
+// primitive values (rho, v_x, v_y, p) at the centroid advanced by h = dt/2 in
+// m and the primitive gradients in gx, gy.
+template <typename T>
+__device__ __forceinline__ Cell<T> predict(const Cell<T>& c, T gamma, T h) {
+  const T gm1 = gamma - T(1);
+  const T rho = c.m[0], ir = rcp(rho);
+  const T vx = c.m[1] * ir, vy = c.m[2] * ir;
+  const T v2 = vx * vx + vy * vy;
+  const T p = gm1 * (c.m[3] - T(0.5) * rho * v2);
+  Cell<T> w;
+  w.gx[0] = c.gx[0];
+  w.gy[0] = c.gy[0];
+  w.gx[1] = (c.gx[1] - vx * c.gx[0]) * ir;
+  w.gy[1] = (c.gy[1] - vx * c.gy[0]) * ir;
+  w.gx[2] = (c.gx[2] - vy * c.gx[0]) * ir;
+  w.gy[2] = (c.gy[2] - vy * c.gy[0]) * ir;
+  // E = p/(gamma-1) + rho |v|^2/2
+  w.gx[3] = gm1 * (c.gx[3] - T(0.5) * v2 * c.gx[0] - rho * (vx * w.gx[1] + vy * w.gx[2]));
+  w.gy[3] = gm1 * (c.gy[3] - T(0.5) * v2 * c.gy[0] - rho * (vx * w.gy[1] + vy * w.gy[2]));
+  const T div = w.gx[1] + w.gy[2];
+  const T rho_t = -(vx * w.gx[0] + vy * w.gy[0] + rho * div);
+  const T vx_t = -(vx * w.gx[1] + vy * w.gy[1] + w.gx[3] * ir);
+  const T vy_t = -(vx * w.gx[2] + vy * w.gy[2] + w.gy[3] * ir);
+  const T p_t = -(gamma * p * div + vx * w.gx[3] + vy * w.gy[3]);
+  w.m[0] = fma(h, rho_t, rho);
+  w.m[1] = fma(h, vx_t, vx);
+  w.m[2] = fma(h, vy_t, vy);
+  w.m[3] = fma(h, p_t, p);
+  return w;
+}
+
+// Conserved variables of a primitive state (in place).
+template <typename T>
+__device__ __forceinline__ void to_cons(T* u, T igm1) {
+  const T rho = u[0], vx = u[1], vy = u[2];
+  u[1] = rho * vx;
+  u[2] = rho * vy;
+  u[3] = fma(u[3], igm1, T(0.5) * rho * (vx * vx + vy * vy));
+}
+
 // x-face between the left neighbour L (lane - 1) and this cell R.  Returns
 // S = F(g0) + F(g1), D = F(g1) - F(g0) per variable (g0 at y offset -qy).
-template <typename T>
+template <typename T, bool PRIM = false>
 __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
   T bl[4], br[4], tl[4], tr[4];
@@ -190,11 +237,19 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
     uL[v] = bl[v] - tl[v];
     uR[v] = br[v] - tr[v];
   }
+  if (PRIM) {
+    to_cons(uL, p.igm1);
+    to_cons(uR, p.igm1);
+  }
   hll<T, 0>(uL, uR, p.gamma, F0, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     uL[v] = bl[v] + tl[v];
     uR[v] = br[v] + tr[v];
+  }
+  if (PRIM) {
+    to_cons(uL, p.igm1);
+    to_cons(uR, p.igm1);
   }
   hll<T, 0>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
@@ -205,7 +260,7 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
 }
 
 // y-face between the lower cell L (previous row) and the upper cell R.
-template <typename T>
+template <typename T, bool PRIM = false>
 __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
   T bl[4], br[4], tl[4], tr[4];
@@ -222,11 +277,19 @@ __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const 
     uL[v] = bl[v] - tl[v];
     uR[v] = br[v] - tr[v];
   }
+  if (PRIM) {
+    to_cons(uL, p.igm1);
+    to_cons(uR, p.igm1);
+  }
   hll<T, 1>(uL, uR, p.gamma, F0, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     uL[v] = bl[v] + tl[v];
     uR[v] = br[v] + tr[v];
+  }
+  if (PRIM) {
+    to_cons(uL, p.igm1);
+    to_cons(uR, p.igm1);
   }
   hll<T, 1>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
@@ -237,7 +300,7 @@ __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const 
 }
 
 // Volume term: sums of F_x and F_y over the 2x2 Gauss points.
-template <typename T>
+template <typename T, bool PRIM = false>
 __device__ __forceinline__ void volume(const Cell<T>& c, const P2<T>& p, T* sx, T* sy,
                                        bool& bad) {
 #pragma unroll
@@ -249,6 +312,7 @@ __device__ __forceinline__ void volume(const Cell<T>& c, const P2<T>& p, T* sx, 
     T u[4], Fx[4], Fy[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) u[v] = fma(c.gx[v], ox, fma(c.gy[v], oy, c.m[v]));
+    if (PRIM) to_cons(u, p.igm1);
     flux_xy(u, p.gamma, Fx, Fy, bad);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -318,7 +382,10 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
   T ySm[4], yDm[4];
   // the step size is first needed when row y0 is finalised
   T dt = T(0);
-  if (MODE == kStage1 || MODE == kStage2) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
+  if (MODE == kStage1 || MODE == kStage2 || MODE == kMH)
+    dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
+  // MUSCL-Hancock: predicted primitive cells of the window rows j-1 and j
+  Cell<T> prevP, curP;
 
   for (int j = y0 - 1; j <= y1; ++j) {
     Cell<T> nx2;
@@ -329,12 +396,18 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
     r2 = next(r2);
 
     if (LIM || MODE == kLimit) limit_cell(cur, prev.m, nx1.m, p);
+    if (MODE == kMH) curP = predict(cur, p.gamma, T(0.5) * dt);
 
     if (MODE == kLimit) {
       if (own && j >= y0 && j < y1) store_cell(p.out, nc, wrap(j) * nx + col, cur);
     } else {
       T Sy[4], Dy[4];
-      if (j >= y0) yface(prev, cur, p, Sy, Dy, bad);
+      if (j >= y0) {
+        if (MODE == kMH)
+          yface<T, true>(prevP, curP, p, Sy, Dy, bad);
+        else
+          yface(prev, cur, p, Sy, Dy, bad);
+      }
       if (j >= y0 + 1) {
         // Finalise row f = j - 1 (held in prev).
         Cell<T> u0nn;
@@ -345,16 +418,17 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
             load_means(p.u0, nc, ru * nx + col, u0nn.m);
           ru = next(ru);
         }
+        const Cell<T>& ev = MODE == kMH ? prevP : prev;  // the row's evaluated polynomial
         Cell<T> left;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          left.m[v] = lane_up(prev.m[v]);
-          left.gx[v] = lane_up(prev.gx[v]);
-          left.gy[v] = lane_up(prev.gy[v]);
+          left.m[v] = lane_up(ev.m[v]);
+          left.gx[v] = lane_up(ev.gx[v]);
+          left.gy[v] = lane_up(ev.gy[v]);
         }
         T Sm[4], Dm[4], sx[4], sy[4];
-        xface(left, prev, p, Sm, Dm, bad);
-        volume(prev, p, sx, sy, bad);
+        xface<T, MODE == kMH>(left, ev, p, Sm, Dm, bad);
+        volume<T, MODE == kMH>(ev, p, sx, sy, bad);
         Cell<T> o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -389,7 +463,7 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
         }
         if (own) {
           store_cell(p.out, nc, wrap(j - 1) * nx + col, o);
-          if (MODE == kStage2 && p.dt_next) dtmin = fmin(dtmin, cell_dt(o.m, p));
+          if ((MODE == kStage2 || MODE == kMH) && p.dt_next) dtmin = fmin(dtmin, cell_dt(o.m, p));
         }
       }
       if (j >= y0) {
@@ -403,9 +477,10 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
     prev = cur;
     cur = nx1;
     nx1 = nx2;
+    if (MODE == kMH) prevP = curP;
   }
   if (bad && own) atomicOr(p.status, 1);
-  if (MODE == kStage2 && p.dt_next) {
+  if ((MODE == kStage2 || MODE == kMH) && p.dt_next) {
     // per-wave CFL minimum; a one-workgroup kernel reduces them afterwards
     dtmin = wave_min(dtmin);
     if (lane == 0) p.dtpart[wave] = dtmin;
@@ -578,6 +653,7 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
   p.nc = (int)m->ncells;
   const double hx = m->c2.hx, hy = m->c2.hy, s3 = 1.7320508075688772;
   p.gamma = (T)m->cfg.gamma;
+  p.igm1 = (T)(1.0 / (m->cfg.gamma - 1.0));
   p.cmx = (T)(0.5 / hx);
   p.cmy = (T)(0.5 / hy);
   p.cgx = (T)(3.0 / (hx * hx));
@@ -599,7 +675,7 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
   P2<T> p = make_params<T>(m, in, u0, out, dt_dev, dt_host);
   const int nblocks = (p.ntiles + 3) / 4;
   const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
-  if (mode == kStage2) {
+  if (mode == kStage2 || mode == kMH) {
     p.dt_next = dt_next;
     p.cfl = cfl;
   }
@@ -621,6 +697,15 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
         hipLaunchKernelGGL((k_cart2d<T, kStage2, true>), dim3(nblocks), dim3(256), 0, s, p);
       else
         hipLaunchKernelGGL((k_cart2d<T, kStage2, false>), dim3(nblocks), dim3(256), 0, s, p);
+      if (dt_next)
+        hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
+                           dt_next);
+      break;
+    case kMH:
+      if (lim)
+        hipLaunchKernelGGL((k_cart2d<T, kMH, true>), dim3(nblocks), dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_cart2d<T, kMH, false>), dim3(nblocks), dim3(256), 0, s, p);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);
@@ -657,6 +742,7 @@ PB<T> make_batch_params(const dg_mesh* m, const void* in, const void* u0, void* 
   b.base.dt_next = nullptr;
   b.base.nc = (int)m->ncells;
   b.base.gamma = (T)m->cfg.gamma;
+  b.base.igm1 = (T)(1.0 / (m->cfg.gamma - 1.0));
   b.inst = static_cast<const BInst<T>*>(m->bt.inst);
   b.tile_inst = m->bt.tile_inst;
   b.ntiles = m->bt.ntiles;
@@ -675,7 +761,7 @@ hipError_t launch_batch_t(const dg_mesh* m, int mode, const void* in, const void
   const int nblocks = (waves + wpb - 1) / wpb;
   const dim3 grid(nblocks), block(64 * wpb);
   const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
-  if (mode == kStage2) {
+  if (mode == kStage2 || mode == kMH) {
     b.base.dt_next = dt_next;
     b.base.cfl = cfl;
   }
@@ -697,6 +783,15 @@ hipError_t launch_batch_t(const dg_mesh* m, int mode, const void* in, const void
         hipLaunchKernelGGL((k_cart2d_batch<T, kStage2, true>), grid, block, 0, s, b);
       else
         hipLaunchKernelGGL((k_cart2d_batch<T, kStage2, false>), grid, block, 0, s, b);
+      if (dt_next)
+        hipLaunchKernelGGL(k_min_finalize_batch, dim3(m->bt.ninst), dim3(256), 0, s, m->dtpart,
+                           m->bt.inst_tile0, cfl, dt_next);
+      break;
+    case kMH:
+      if (lim)
+        hipLaunchKernelGGL((k_cart2d_batch<T, kMH, true>), grid, block, 0, s, b);
+      else
+        hipLaunchKernelGGL((k_cart2d_batch<T, kMH, false>), grid, block, 0, s, b);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize_batch, dim3(m->bt.ninst), dim3(256), 0, s, m->dtpart,
                            m->bt.inst_tile0, cfl, dt_next);

@@ -493,6 +493,24 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
   return DG_OK;
 }
 
+static bool mh_supported(const dg_mesh* m) {
+  return m->cfg.physics == DG_EULER && ((m->kind == 0 && m->dim == 2) || m->kind == 2);
+}
+
+dg_status dg_step_mh(dg_mesh_t m, const void* U, void* Un, double dt, const double* dt_dev,
+                     double cfl, double* dt_next_dev, void* stream) {
+  if (!m || !U || !Un) return einval("dg_step_mh: NULL argument");
+  m->ws_a_fresh = false;
+  if (!mh_supported(m)) {
+    set_error("dg_step_mh: built for 2D Euler Cartesian meshes and batches");
+    return DG_EUNSUPPORTED;
+  }
+  if (U == Un) return einval("dg_step_mh: U_next must not alias U");
+  if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_step_mh: dt must be finite and >= 0");
+  if (dt_next_dev && !(cfl > 0 && std::isfinite(cfl))) return einval("dg_step_mh: cfl must be > 0");
+  return dispatch(m, kMH, U, nullptr, Un, dt_dev, dt, (hipStream_t)stream, cfl, dt_next_dev);
+}
+
 dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double cfl,
                  double* dt_hist, int ckpt_every, void* const* ckpt, void* const* v1_keep,
                  int flags, void* stream) {
@@ -502,7 +520,13 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
   if (ckpt_every < 0 || (ckpt_every > 0 && nsteps > ckpt_every && !ckpt))
     return einval("dg_run: checkpoints need ckpt_every >= 0 and a ckpt array");
   if (nsteps == 1 && U_out == U_in) return einval("dg_run: U_out may equal U_in only for >= 2 steps");
-  if (flags & ~DG_RUN_GRAPH) return einval("dg_run: unknown flag");
+  if (flags & ~(DG_RUN_GRAPH | DG_RUN_MUSCL_HANCOCK)) return einval("dg_run: unknown flag");
+  const bool mh = (flags & DG_RUN_MUSCL_HANCOCK) != 0;
+  if (mh && !mh_supported(m)) {
+    set_error("dg_run: MUSCL-Hancock is built for 2D Euler Cartesian meshes and batches");
+    return DG_EUNSUPPORTED;
+  }
+  if (mh && v1_keep) return einval("dg_run: v1_keep needs the SSP-RK2 integrator");
   m->ws_a_fresh = false;
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)m->ncoef * m->ncells * m->elem;
@@ -529,6 +553,13 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
       else
         out = cur == m->tmp ? m->run_ws : m->tmp;
       const double* dtn = dt_hist + (int64_t)n * nd;
+      if (mh) {
+        dg_status st = dispatch(m, kMH, cur, nullptr, out, dtn, 0.0, q, cfl,
+                                cfl > 0 ? dt_hist + (int64_t)(n + 1) * nd : nullptr);
+        if (st != DG_OK) return st;
+        cur = out;
+        continue;
+      }
       dg_status st = dispatch(m, kStage1, cur, nullptr, V1, dtn, 0.0, q);
       if (st != DG_OK) return st;
       m->ws_a_fresh = true;

@@ -17,7 +17,8 @@ enum StageMode : int {
   kRhs = 0,     // out = L(in)
   kStage1 = 1,  // out = Pi(in) + dt L(Pi(in))
   kStage2 = 2,  // out = Pi(u0)/2 + (Pi(in) + dt L(Pi(in)))/2
-  kLimit = 3    // out = Pi(in)
+  kLimit = 3,   // out = Pi(in)
+  kMH = 4       // out = Pi(in) + dt L_MH(Pi(in); dt/2): one MUSCL-Hancock step
 };
 
 // Geometry and launch shape of a periodic 2D Cartesian mesh.

@@ -191,6 +191,22 @@ class Solver:
                                   _stream()), "dg_stage2")
         return out
 
+    def step_mh(self, U: torch.Tensor, dt, out: torch.Tensor | None = None, cfl: float = 0.0,
+                dt_next: torch.Tensor | None = None) -> torch.Tensor:
+        """One MUSCL-Hancock step (one kernel); dt a float or a device float64
+        tensor (one value per instance); optionally dt_next = CFL step of U'."""
+        self._check_state(U)
+        out = self.empty() if out is None else out
+        self._check_state(out, "out")
+        h, d = self._dt_args(dt)
+        nxt = None
+        if dt_next is not None:
+            self._check_dt(dt_next)
+            nxt = _ptr(dt_next)
+        C.check(C.lib().dg_step_mh(self._h, _ptr(U), _ptr(out), h, d, float(cfl), nxt,
+                                   _stream()), "dg_step_mh")
+        return out
+
     def adjoint_step(self, U: torch.Tensor, dt, lam_next: torch.Tensor,
                      V1: torch.Tensor | None = None, out: torch.Tensor | None = None):
         """lam_n = (d step(U, dt)/dU)^T lam_next (dt frozen; a float, or a device
@@ -207,10 +223,14 @@ class Solver:
 
     def run(self, U: torch.Tensor, nsteps: int, cfl: float = 0.0,
             dt_hist: torch.Tensor | None = None, out: torch.Tensor | None = None,
-            ckpt_every: int = 0, ckpts=None, v1_keep=None, graph: bool = True):
+            ckpt_every: int = 0, ckpts=None, v1_keep=None, graph: bool = True,
+            integrator: str = "rk2"):
         """nsteps steps from U (dg_run).  cfl > 0: adaptive step sizes, written
         to dt_hist ((nsteps + 1) x ninst); cfl = 0: dt_hist (nsteps x ninst) is
-        read.  Returns (U_out, dt_hist)."""
+        read.  integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock).  Returns
+        (U_out, dt_hist)."""
+        if integrator not in ("rk2", "mh"):
+            raise ValueError("integrator must be 'rk2' or 'mh'")
         self._check_state(U)
         out = self.empty() if out is None else out
         self._check_state(out, "out")
@@ -238,7 +258,9 @@ class Solver:
             v1 = (ctypes.c_void_p * nsteps)(*[_ptr(c) for c in v1_keep[:nsteps]])
         C.check(C.lib().dg_run(self._h, _ptr(U), _ptr(out), int(nsteps), float(cfl),
                                _ptr(dt_hist), int(ckpt_every), ck, v1,
-                               C.DG_RUN_GRAPH if graph else 0, _stream()), "dg_run")
+                               (C.DG_RUN_GRAPH if graph else 0) |
+                               (C.DG_RUN_MUSCL_HANCOCK if integrator == "mh" else 0),
+                               _stream()), "dg_run")
         return out, dt_hist
 
     def cfl_dt(self, U: torch.Tensor, cfl: float, out: torch.Tensor | None = None) -> torch.Tensor:

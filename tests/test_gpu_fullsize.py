@@ -1,9 +1,10 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
 (library-default tiling, device step sizes, fused CFL minima, batched graph).
 
-* C2 2048^2 and C4 (10^6 Voronoi cells): two FP64 steps on the oracle's own
-  step schedule, every cell compared (the oracle finishes a step in about a
-  second on the host's cores); the FP32 error is stated.
+* C2 2048^2 (SSP-RK2 and MUSCL-Hancock) and C4 (10^6 Voronoi cells): two
+  FP64 steps on the oracle's own step schedule, every cell compared (the
+  oracle finishes a step in about a second on the host's cores); the FP32
+  error is stated.
 * C3 256^3 MHD: one FP64 step against the oracle, every cell.
 * C5 (256 instances, N in {64..512}): the full batch in its bench launch shape;
   four sampled instances (the first, the largest and two others) carry the
@@ -74,6 +75,31 @@ def test_c2_full_size(oracle, torch_cuda):
         got = _run_gpu(s, U0, dts).double().cpu().numpy()
         e = errs_hydro(got, ref, 4, 2, 1.0 / n, 12)
         print(f"C2 2048^2 {prec}, 2 steps, per-field error: {e}")
+        assert e.max() < tol, (prec, e)
+        s.close()
+
+
+def test_c2_full_size_muscl_hancock(oracle, torch_cuda):
+    """The C2 recipe with the MUSCL-Hancock step (one kernel per step, fused
+    CFL minima), two steps on the oracle's schedule, every cell."""
+    torch = torch_cuda
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    n = 2048
+    U0 = W.c2_state(n)
+    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    ref, dts = oracle.run(om, U0, 2, G53, 0.3, True, integrator="mh")
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), precision=prec, gamma=G53)
+        U = s.to_device(U0)
+        V = s.empty()
+        nxt = torch.empty(1, dtype=torch.float64, device=s.device)
+        for dt in dts:
+            d = torch.tensor([dt], dtype=torch.float64, device=s.device)
+            s.step_mh(U, d, out=V, cfl=0.3, dt_next=nxt)
+            U, V = V, U
+        s.check()
+        e = errs_hydro(U.double().cpu().numpy(), ref, 4, 2, 1.0 / n, 12)
+        print(f"C2 2048^2 MUSCL-Hancock {prec}, 2 steps, per-field error: {e}")
         assert e.max() < tol, (prec, e)
         s.close()
 
