@@ -82,6 +82,7 @@ def lib():
         L.or_cell_geometry.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp,
                                        ctypes.POINTER(ctypes.c_int), _dp, _dp]
         L.or_gram_B.argtypes = [_dp, _dp]
+        L.or_gram_B2.argtypes = [_dp, _dp]
         L.or_eval_B.argtypes = [_dp, _dp, _dp, _dp]
         L.or_divB.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.or_num_threads.restype = ctypes.c_int
@@ -312,6 +313,14 @@ def hlld(uL, uR, n, gamma: float) -> np.ndarray:
     out = np.zeros(8)
     lib().or_hlld(gamma, _p(uL), _p(uR), _p(n3), _p(out))
     return out
+
+
+def gram_B2(M) -> np.ndarray:
+    """5x5 Gram matrix of the 2D B basis from the 2x2 second-moment matrix."""
+    M = _f64(M).reshape(4)
+    G = np.empty(25)
+    lib().or_gram_B2(_p(M), _p(G))
+    return G.reshape(5, 5)
 
 
 def gram_B(M) -> np.ndarray:

@@ -309,12 +309,15 @@ struct Mesh {
 // p_total = p_gas + B^2/2, E = p_gas/(gamma-1) + rho v^2/2 + B^2/2.
 struct Phys {
   int dim;      // spatial dimension of the mesh
-  int mhd;      // 0 Euler, 1 ideal MHD (3D only)
+  int mhd;      // 0 Euler, 1 ideal MHD (2D or 3D; velocity and B have 3 components)
   double gamma;
   int nv() const { return mhd ? 8 : dim + 2; }
   int nvel() const { return mhd ? 3 : dim; }
   int nhyd() const { return mhd ? 5 : dim + 2; }  // Taylor-basis variables
-  int ncoef() const { return mhd ? 5 * (1 + dim) + 3 + 8 : (dim + 2) * (1 + dim); }
+  // non-constant B basis functions: V4..V11 in 3D; in 2D V3..V5 for (B_x, B_y)
+  // plus the two Taylor functions x, y of B_z
+  int nfun() const { return dim == 3 ? 8 : 5; }
+  int ncoef() const { return mhd ? 5 * (1 + dim) + 3 + nfun() : (dim + 2) * (1 + dim); }
 };
 
 // The locally divergence-free magnetic basis of Sec. 2.2 (3D), functions
@@ -335,6 +338,24 @@ struct LBInit {
     LB[7][0][0] = 1; LB[7][2][2] = -1;  // V11
   }
 } lbinit;
+
+// The 2D magnetic basis (Sec. 2.2): V3 = (y, 0), V4 = (0, x), V5 = (x, -y) for
+// (B_x, B_y), with coefficients alpha_1 = dB_x/dy, alpha_2 = dB_y/dx,
+// alpha_3 = dB_x/dx = -dB_y/dy, and B_z in the Taylor basis (x, y).
+double LB2[8][3][3];
+struct LB2Init {
+  LB2Init() {
+    std::memset(LB2, 0, sizeof(LB2));
+    LB2[0][0][1] = 1;                     // V3: B_x = y
+    LB2[1][1][0] = 1;                     // V4: B_y = x
+    LB2[2][0][0] = 1; LB2[2][1][1] = -1;  // V5: B_x = x, B_y = -y
+    LB2[3][2][0] = 1;                     // B_z = x
+    LB2[4][2][1] = 1;                     // B_z = y
+  }
+} lb2init;
+
+// The B basis table of the mesh dimension.
+inline const double (*basis(const Phys& P))[3][3] { return P.dim == 3 ? LB : LB2; }
 
 template <class T> struct State {
   T u[8];
@@ -564,7 +585,7 @@ void load_poly(const Phys& P, const T* U, int64_t nc, int64_t e, Poly<T>& q) {
   if (P.mhd) {
     int base = nh * (1 + dim);
     for (int c = 0; c < 3; ++c) q.m[5 + c] = U[(int64_t)(base + c) * nc + e];
-    for (int j = 0; j < 8; ++j) q.a[j] = U[(int64_t)(base + 3 + j) * nc + e];
+    for (int j = 0; j < P.nfun(); ++j) q.a[j] = U[(int64_t)(base + 3 + j) * nc + e];
   }
 }
 
@@ -578,16 +599,17 @@ void store_poly(const Phys& P, T* U, int64_t nc, int64_t e, const Poly<T>& q) {
   if (P.mhd) {
     int base = nh * (1 + dim);
     for (int c = 0; c < 3; ++c) U[(int64_t)(base + c) * nc + e] = q.m[5 + c];
-    for (int j = 0; j < 8; ++j) U[(int64_t)(base + 3 + j) * nc + e] = q.a[j];
+    for (int j = 0; j < P.nfun(); ++j) U[(int64_t)(base + 3 + j) * nc + e] = q.a[j];
   }
 }
 
 // Gradient of B component c (from the divergence-free coefficients).
-template <class T> void grad_B(const Poly<T>& q, int c, T* gB) {
+template <class T> void grad_B(const Phys& P, const Poly<T>& q, int c, T* gB) {
+  const auto LBp = basis(P);
   for (int d = 0; d < 3; ++d) {
     T s = T(0);
-    for (int j = 0; j < 8; ++j)
-      if (LB[j][c][d] != 0.0) s += T(LB[j][c][d]) * q.a[j];
+    for (int j = 0; j < P.nfun(); ++j)
+      if (LBp[j][c][d] != 0.0) s += T(LBp[j][c][d]) * q.a[j];
     gB[d] = s;
   }
 }
@@ -602,11 +624,12 @@ template <class T> void eval_poly(const Phys& P, const Poly<T>& q, const double*
     u[v] = s;
   }
   if (P.mhd) {
+    const auto LBp = basis(P);
     for (int c = 0; c < 3; ++c) {
       T s = q.m[5 + c];
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < P.nfun(); ++j)
         for (int d = 0; d < 3; ++d)
-          if (LB[j][c][d] != 0.0) s += q.a[j] * T(LB[j][c][d] * r[d]);
+          if (LBp[j][c][d] != 0.0) s += q.a[j] * T(LBp[j][c][d] * r[d]);
       u[5 + c] = s;
     }
   }
@@ -734,15 +757,18 @@ template <class T> void solve_small(int n, const double* Ain, const T* b, T* x) 
 }
 
 // Gram matrix of the B basis, G_ij = int V_i . V_j dOmega, from the cell's
-// second-moment matrix M (Sec. 2.2: the 8x8 mass matrix M_B).
-void gram_B(const double M[3][3], double* G) {
-  for (int i = 0; i < 8; ++i)
-    for (int j = 0; j < 8; ++j) {
+// second-moment matrix M (Sec. 2.2: the mass matrix M_B, 8x8 in 3D; in 2D the
+// printed 3x3 matrix of alpha_1..alpha_3 plus the B_z block M).
+void gram_B(const Phys& P, const double M[3][3], double* G) {
+  const auto LBp = basis(P);
+  const int nf = P.nfun();
+  for (int i = 0; i < nf; ++i)
+    for (int j = 0; j < nf; ++j) {
       double s = 0;
       for (int c = 0; c < 3; ++c)
         for (int d = 0; d < 3; ++d)
-          for (int e = 0; e < 3; ++e) s += LB[i][c][d] * LB[j][c][e] * M[d][e];
-      G[i * 8 + j] = s;
+          for (int e = 0; e < 3; ++e) s += LBp[i][c][d] * LBp[j][c][e] * M[d][e];
+      G[i * nf + j] = s;
     }
 }
 
@@ -826,16 +852,18 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.
       for (int k = 0; k < nv; ++k) rmean[k] += sg * F[k];
       for (int v = 0; v < nh; ++v)
         for (int d = 0; d < dim; ++d) rgrad[v][d] += sg * F[v] * T(r[d]);
-      if (P.mhd)
-        for (int j = 0; j < 8; ++j) {
+      if (P.mhd) {
+        const auto LBp = basis(P);
+        for (int j = 0; j < P.nfun(); ++j) {
           T s = T(0);
           for (int c = 0; c < 3; ++c) {
             double vj = 0;
-            for (int d = 0; d < 3; ++d) vj += LB[j][c][d] * r[d];
+            for (int d = 0; d < 3; ++d) vj += LBp[j][c][d] * r[d];
             if (vj != 0.0) s += F[5 + c] * T(vj);
           }
           ra[j] += sg * s;
         }
+      }
     }
   }
   // Volume term: int F . grad(test) dOmega, with grad(x_d) = e_d for the
@@ -858,14 +886,16 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.
     T w = T(cg.wq[q]);
     for (int v = 0; v < nh; ++v)
       for (int d = 0; d < dim; ++d) rgrad[v][d] += w * Fd[d][v];
-    if (P.mhd)
-      for (int j = 0; j < 8; ++j) {
+    if (P.mhd) {
+      const auto LBp = basis(P);
+      for (int j = 0; j < P.nfun(); ++j) {
         T s = T(0);
         for (int c = 0; c < 3; ++c)
-          for (int d = 0; d < 3; ++d)
-            if (LB[j][c][d] != 0.0) s += T(LB[j][c][d]) * Fd[d][5 + c];
+          for (int d = 0; d < dim; ++d)
+            if (LBp[j][c][d] != 0.0) s += T(LBp[j][c][d]) * Fd[d][5 + c];
         ra[j] += w * s;
       }
+    }
   }
   // Inverse mass matrices: means divide by V; gradients solve M g = res
   // (Sec. 2.2, "Derivative information is obtained by matrix inversion").
@@ -881,8 +911,8 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.
   }
   if (P.mhd) {
     double G[64];
-    gram_B(cg.M, G);
-    solve_small(8, G, ra, out.a);
+    gram_B(P, cg.M, G);
+    solve_small(P.nfun(), G, ra, out.a);
   }
   store_poly(P, dUdt, nc, e, out);
   return ok;
@@ -949,10 +979,10 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
     T aB = T(1);
     for (int c = 0; c < 3; ++c) {
       T gB[3];
-      grad_B(q, c, gB);
+      grad_B(P, q, c, gB);
       aB = dmin(aB, alpha_of(5 + c, gB));
     }
-    for (int j = 0; j < 8; ++j) q.a[j] = aB * q.a[j];
+    for (int j = 0; j < P.nfun(); ++j) q.a[j] = aB * q.a[j];
   }
   store_poly(P, Ul, nc, e, q);
 }
@@ -1253,7 +1283,14 @@ void or_gram_B(const double* M, double* G) {
   double m[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) m[i][j] = M[3 * i + j];
-  gram_B(m, G);
+  gram_B(Phys{3, 1, 1.4}, m, G);
+}
+
+// Gram matrix of the 2D B basis (V3, V4, V5, then the B_z Taylor functions)
+// from the 2x2 second-moment matrix M (row-major); G is 5x5.
+void or_gram_B2(const double* M, double* G) {
+  double m[3][3] = {{M[0], M[1], 0.0}, {M[2], M[3], 0.0}, {0.0, 0.0, 0.0}};
+  gram_B(Phys{2, 1, 1.4}, m, G);
 }
 
 // Evaluate the B polynomial (Bbar, a4..a11) at offset r.

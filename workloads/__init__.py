@@ -16,13 +16,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from .cartesian import (acoustic_state, alfven_state, batched_instances, batched_state,
-                        c1_state, c2_state,
+from .cartesian import (acoustic_state, alfven2d_state, alfven_state, batched_instances,
+                        batched_state, c1_state, c2_state, orszag_tang_state, rotor_state,
                         c3_state, cartesian_centres, gresho_state, project_cartesian,
                         random_p1_state, vortex_cell_means, vortex_fields)
 
 __all__ = [
-    "acoustic_state", "alfven_state", "batched_instances", "batched_state", "c1_state", "c2_state", "c3_state",
+    "acoustic_state", "alfven2d_state", "alfven_state", "batched_instances", "batched_state",
+    "orszag_tang_state", "rotor_state", "c1_state", "c2_state", "c3_state",
     "cartesian_centres", "gresho_state", "project_cartesian", "random_p1_state",
     "vortex_cell_means", "vortex_fields",
 ]

@@ -39,6 +39,14 @@ def _vb(r):
     ]
 
 
+# The 2D magnetic functions of Sec. 2.2 (V3, V4, V5 for (B_x, B_y)) and the
+# Taylor functions x, y of B_z; used only to project initial fields.
+def _vb2(r):
+    x, y = r
+    zero = 0.0 * x
+    return [(y, zero, zero), (zero, x, zero), (x, -y, zero), (zero, zero, x), (zero, zero, y)]
+
+
 def project_cartesian(fields, n, lo, hi, nq=None, mhd=False):
     """P1 projection of ``fields(*X) -> list of conserved arrays`` on every cell.
 
@@ -53,8 +61,10 @@ def project_cartesian(fields, n, lo, hi, nq=None, mhd=False):
     means = None
     first = None
     second = np.zeros(dim)
-    bproj = np.zeros((8, nc)) if mhd else None
-    gram = np.zeros((8, 8)) if mhd else None
+    nb = 8 if dim == 3 else 5
+    bfun = _vb if dim == 3 else _vb2
+    bproj = np.zeros((nb, nc)) if mhd else None
+    gram = np.zeros((nb, nb)) if mhd else None
     for idx in np.ndindex(*([nq] * dim)):
         r = [xs[idx[d]] * h[d] for d in range(dim)]
         w = float(np.prod([ws[i] for i in idx]))
@@ -70,12 +80,12 @@ def project_cartesian(fields, n, lo, hi, nq=None, mhd=False):
         for d in range(dim):
             second[d] += w * r[d] ** 2
         if mhd:
-            basis = _vb(r)
-            for j in range(8):
+            basis = bfun(r)
+            for j in range(nb):
                 bproj[j] += w * sum(vals[5 + c] * basis[j][c] for c in range(3))
-                for i in range(8):
+                for i in range(nb):
                     gram[i, j] += w * sum(basis[i][c] * basis[j][c] for c in range(3))
-    ncoef = nh * (1 + dim) + (11 if mhd else 0)
+    ncoef = nh * (1 + dim) + ((3 + nb) if mhd else 0)
     U = np.zeros((ncoef, nc))
     for v in range(nh):
         U[v * (1 + dim)] = means[v]
@@ -84,7 +94,7 @@ def project_cartesian(fields, n, lo, hi, nq=None, mhd=False):
     if mhd:
         base = nh * (1 + dim)
         U[base:base + 3] = means[5:8]
-        U[base + 3:base + 11] = np.linalg.solve(gram, bproj)
+        U[base + 3:base + 3 + nb] = np.linalg.solve(gram, bproj)
     return U.reshape(-1)
 
 
@@ -217,9 +227,9 @@ def random_p1_state(n, lo, hi, gamma, seed, amp=0.1, nmodes=4, kmax=3, mhd=False
         for c in range(3):
             k, a, ph = sa[c]
             for m in range(len(a)):
-                th = sum(2 * math.pi * k[m][d] * (X[d] - lo[d]) / L[d] for d in range(3)) + ph[m]
+                th = sum(2 * math.pi * k[m][d] * (X[d] - lo[d]) / L[d] for d in range(dim)) + ph[m]
                 g = [2 * math.pi * k[m][d] / L[d] * a[m] * np.cos(th) / len(a) * bamp
-                     for d in range(3)]
+                     for d in range(dim)] + [0.0 * X[0]] * (3 - dim)
                 # (curl A)_i = eps_ijk d_j A_k with A = e_c * sin(...)
                 B[(c + 1) % 3] = B[(c + 1) % 3] + g[(c + 2) % 3]
                 B[(c + 2) % 3] = B[(c + 2) % 3] - g[(c + 1) % 3]
@@ -399,6 +409,67 @@ def alfven_state(n, plane=(0, 1), t=0.0, amp=0.1, p0=0.1, gamma=5.0 / 3.0):
     hi = [1.0, 1.0, 1.0]
     hi[third] = 1.0 / n
     return project_cartesian(f, tuple(shape), (0.0, 0.0, 0.0), tuple(hi), mhd=True), tuple(shape), tuple(hi)
+
+
+# ------------------------------------------------------------------- 2D MHD
+def alfven2d_state(n, t=0.0, amp=0.1, p0=0.1, gamma=5.0 / 3.0):
+    """Travelling circularly polarised Alfven wave on the unit square, an exact
+    nonlinear solution of ideal MHD: rho = 1, p = p0, B_par = 1 along k = (1, 1),
+    B_perp of magnitude ``amp`` rotating between the in-plane normal and z,
+    v_perp = -B_perp (wavelength 1/sqrt 2, Alfven speed 1)."""
+    kvec = np.array([1.0, 1.0])
+    kn = np.linalg.norm(kvec)
+    khat = np.array([1.0, 1.0, 0.0]) / kn
+    e1 = np.array([-1.0, 1.0, 0.0]) / math.sqrt(2)
+    e2 = np.array([0.0, 0.0, 1.0])
+
+    def f(X, Y):
+        ph = 2 * math.pi * (kvec[0] * X + kvec[1] * Y - kn * t)
+        b1 = amp * np.sin(ph)
+        b2 = amp * np.cos(ph)
+        B = [khat[c] + b1 * e1[c] + b2 * e2[c] for c in range(3)]
+        vel = [-(b1 * e1[c] + b2 * e2[c]) for c in range(3)]
+        return _mhd_conserved(1.0 + 0.0 * X, vel, p0 + 0.0 * X, B, gamma)
+
+    return project_cartesian(f, (n, n), (0.0, 0.0), (1.0, 1.0), mhd=True)
+
+
+def orszag_tang_state(n, gamma=5.0 / 3.0, nq=None):
+    """The paper's Orszag-Tang setup (Sec. 3.9) on the unit square: rho =
+    gamma^2/(4 pi), p = gamma/(4 pi), v = (-sin 2 pi y, sin 2 pi x), and B =
+    (-sin 2 pi y, sin 4 pi x) in the units of the cited setup, i.e. divided by
+    sqrt(4 pi) in the units used here (magnetic pressure B^2/2)."""
+    s4 = math.sqrt(4 * math.pi)
+
+    def f(X, Y):
+        rho = gamma ** 2 / (4 * math.pi) + 0.0 * X
+        p = gamma / (4 * math.pi) + 0.0 * X
+        vel = [-np.sin(2 * math.pi * Y), np.sin(2 * math.pi * X), 0.0 * X]
+        B = [-np.sin(2 * math.pi * Y) / s4, np.sin(4 * math.pi * X) / s4, 0.0 * X]
+        return _mhd_conserved(rho, vel, p, B, gamma)
+
+    return project_cartesian(f, (n, n), (0.0, 0.0), (1.0, 1.0), nq=nq, mhd=True)
+
+
+def rotor_state(n, gamma=5.0 / 3.0, nq=None):
+    """The paper's magnetic rotor (Sec. 3.8) on the unit square: a dense
+    rotating disc (rho = 10 for r <= 0.1, tapered to 1 at r = 0.115), p = 0.5,
+    B_x = 2.5/sqrt(4 pi), B_y = 0, the ambient fluid at rest."""
+    r0, r1 = 0.1, 0.115
+
+    def f(X, Y):
+        dx, dy = X - 0.5, Y - 0.5
+        r = np.sqrt(dx * dx + dy * dy)
+        fr = (r1 - r) / (r1 - r0)
+        inner, taper = r <= r0, (r > r0) & (r <= r1)
+        rho = np.where(inner, 10.0, np.where(taper, 1.0 + 9.0 * fr, 1.0))
+        rs = np.where(r > 0, r, 1.0)
+        vx = np.where(inner, -dy / r0, np.where(taper, -fr * dy / rs, 0.0))
+        vy = np.where(inner, dx / r0, np.where(taper, fr * dx / rs, 0.0))
+        B = [2.5 / math.sqrt(4 * math.pi) + 0.0 * X, 0.0 * X, 0.0 * X]
+        return _mhd_conserved(rho, [vx, vy, 0.0 * X], 0.5 + 0.0 * X, B, gamma)
+
+    return project_cartesian(f, (n, n), (0.0, 0.0), (1.0, 1.0), nq=nq, mhd=True)
 
 
 # ------------------------------------------------------------------ batched C5
