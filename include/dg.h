@@ -19,7 +19,12 @@
  * k = v*(1+dim) + c, c = 0 the cell mean, c = 1..dim the gradient along x, y(,
  * z) about the cell centroid (the Taylor basis of Sec. 2.2).  Ideal MHD (3D)
  * appends the three B means and the coefficients a4..a11 of the locally
- * divergence-free functions V4..V11 of Sec. 2.2 (31 arrays in all).
+ * divergence-free functions V4..V11 of Sec. 2.2 (31 arrays in all).  Ideal
+ * MHD in 2D carries three momenta (rho v_z too) as Taylor variables
+ * (k = 3v + c, v = 0..4), then the means of Bx, By, Bz (15..17), the
+ * coefficients a1, a2, a3 of the 2D divergence-free functions (x-y field)
+ * V3 = (y, 0), V4 = (0, x), V5 = (x, -y) (18..20) and the x and y gradients of
+ * Bz (21, 22): 23 arrays in all.
  * Cartesian cells are numbered x fastest: cell = (k*ny + j)*nx + i.
  * Element type is double (DG_FP64) or float (DG_FP32), per dg_config.
  *
@@ -73,7 +78,7 @@ typedef enum { DG_FLUX_HLL = 0, DG_FLUX_HLLD = 1 } dg_flux;
 typedef enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1 } dg_limiter;
 
 /* Physics and numerics of a mesh.  Euler needs DG_FLUX_HLL; MHD needs
- * DG_FLUX_HLLD and a 3D Cartesian mesh.  gamma is the adiabatic index of
+ * DG_FLUX_HLLD and a 2D or 3D Cartesian mesh (kind 0).  gamma is the adiabatic index of
  * p_gas = (gamma - 1) rho u (Sec. 2.1). */
 typedef struct {
   int physics;    /* dg_physics */
@@ -130,7 +135,8 @@ void dg_mesh_destroy(dg_mesh_t mesh);
 /* Number of state elements (ncoef * ncells), or -1 for a NULL handle. */
 int64_t dg_state_len(dg_mesh_t mesh);
 
-/* Number of coefficient arrays per cell (12 for 2D Euler, 31 for 3D MHD). */
+/* Number of coefficient arrays per cell (12 for 2D Euler, 23 for 2D MHD, 31
+ * for 3D MHD). */
 int dg_ncoef(dg_mesh_t mesh);
 
 /* dUdt = L(U): the semi-discrete DG right-hand side (Sec. 2.2) without the
@@ -161,10 +167,10 @@ dg_status dg_step(dg_mesh_t mesh, const void* U, void* U_next, double dt, void* 
  * (the formula of dg_cfl_dt), from per-wave minima taken inside the stage
  * kernel plus one single-workgroup reduction; it may equal dt_dev.
  * V1 must not alias U; U_next must alias neither U nor V1.
- * On 3D MHD meshes the limiter runs as its own pass: dg_stage1 keeps Pi(U) in
- * the handle's workspace, and a dg_stage2 that immediately follows it on the
- * same handle with the same U pointer reuses that copy (U must not be
- * modified in between); any other dg_stage2 limits U again. */
+ * On MHD and face-list meshes the limiter runs as its own pass: dg_stage1
+ * keeps Pi(U) in the handle's workspace, and a dg_stage2 that immediately
+ * follows it on the same handle with the same U pointer reuses that copy (U
+ * must not be modified in between); any other dg_stage2 limits U again. */
 dg_status dg_stage1(dg_mesh_t mesh, const void* U, void* V1, double dt, const double* dt_dev,
                     void* stream);
 dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next, double dt,

@@ -42,6 +42,11 @@ hipError_t launch_facelist_cfl(const dg_mesh* m, const void* U, double cfl, doub
 hipError_t launch_cart3d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                          const double* dt_dev, double dt_host, double cfl, double* dt_next,
                          hipStream_t s);
+hipError_t launch_mhd2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
+                        const double* dt_dev, double dt_host, double cfl, double* dt_next,
+                        hipStream_t s);
+hipError_t launch_mhd2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                            hipStream_t s);
 hipError_t launch_cart3d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
 
@@ -63,6 +68,12 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
+// Meshes whose limiter runs as a pass of its own into ws_a / ws_b (3D and 2D
+// MHD, face lists); the 2D Euler kernels limit inside the stage kernel.
+static bool limiter_pass(const dg_mesh* m) {
+  return m->dim == 3 || m->kind == 1 || m->cfg.physics == DG_MHD;
+}
+
 static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                           const double* dt_dev, double dt_host, hipStream_t s,
                           double cfl = 0.0, double* dt_next = nullptr) {
@@ -71,6 +82,8 @@ static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void
     e = launch_facelist(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else if (m->kind == 2)
     e = launch_cart2d_batch(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+  else if (m->dim == 2 && m->cfg.physics == DG_MHD)
+    e = launch_mhd2d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else if (m->dim == 2)
     e = launch_cart2d(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else
@@ -176,8 +189,8 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
       set_error("dg_mesh_create: MHD supports the HLLD flux only");
       return DG_EUNSUPPORTED;
     }
-    if (d->dim != 3 || d->kind != 0) {
-      set_error("dg_mesh_create: MHD is built for 3D Cartesian meshes only");
+    if (d->kind != 0) {
+      set_error("dg_mesh_create: MHD is built for 2D and 3D Cartesian meshes only");
       return DG_EUNSUPPORTED;
     }
   } else {
@@ -230,13 +243,19 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   (void)hipGetDevice(&m->device);
   int64_t nwaves = 0;
   if (d->kind == 0 && d->dim == 2) {
-    m->ncoef = 12;
+    const bool mhd = cfg->physics == DG_MHD;
+    m->ncoef = mhd ? 23 : 12;
     m->ncells = d->n[0] * d->n[1];
+    if (m->ncells * m->ncoef >= ((int64_t)1 << 31)) {
+      delete m;
+      return einval("dg_mesh_create: mesh too large for 32-bit indexing");
+    }
     m->c2.nx = (int)d->n[0];
     m->c2.ny = (int)d->n[1];
     m->c2.hx = (d->hi[0] - d->lo[0]) / d->n[0];
     m->c2.hy = (d->hi[1] - d->lo[1]) / d->n[1];
-    m->c2.tiles_x = (int)((d->n[0] + 59) / 60);
+    // Euler tiles hold 60 interior columns, MHD tiles 62
+    m->c2.tiles_x = (int)(mhd ? (d->n[0] + 61) / 62 : (d->n[0] + 59) / 60);
     m->c2.rows_per_tile = default_rows(m->c2.tiles_x, d->n[1]);
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
@@ -318,7 +337,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   }
   const size_t bytes = (size_t)m->ncoef * (size_t)m->ncells * m->elem;
   hipError_t e = hipMalloc(&m->v1, bytes);
-  const bool separate_limiter = m->dim == 3 || m->kind == 1;
+  const bool separate_limiter = limiter_pass(m);
   if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_a, bytes);
   if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_b, bytes);
   if (e == hipSuccess) e = hipMalloc(&m->status, sizeof(int));
@@ -394,7 +413,7 @@ static dg_status step_impl(dg_mesh_t m, const void* U, void* Un, const double* d
   }
   dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, dt_dev, dt_host, s);
   if (st != DG_OK) return st;
-  // 3D keeps Pi(U) of stage 1 in its workspace for the stage-2 combination
+  // a separate limiter pass keeps Pi(U) of stage 1 for the stage-2 combination
   m->ws_a_fresh = true;
   m->ws_a_src = U;
   st = dispatch(m, kStage2, m->v1, U, target, dt_dev, dt_host, s);
@@ -420,9 +439,9 @@ dg_status dg_stage1(dg_mesh_t m, const void* U, void* V1, double dt, const doubl
   if (U == V1) return einval("dg_stage1: U and V1 must not alias");
   if (!dt_dev && (!std::isfinite(dt) || dt < 0)) return einval("dg_stage1: dt must be finite and >= 0");
   dg_status st = dispatch(m, kStage1, U, nullptr, V1, dt_dev, dt, (hipStream_t)stream);
-  // 3D keeps Pi(U) in its workspace; an immediately following dg_stage2 on
+  // a separate limiter pass keeps Pi(U); an immediately following dg_stage2 on
   // the same U reuses it
-  m->ws_a_fresh = st == DG_OK && (m->dim == 3 || m->kind == 1);
+  m->ws_a_fresh = st == DG_OK && limiter_pass(m);
   m->ws_a_src = U;
   return st;
 }
@@ -454,6 +473,8 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
     e = launch_facelist_cfl(m, U, cfl, dt_dev, s);
   else if (m->kind == 2)
     e = launch_cart2d_batch_cfl(m, U, cfl, dt_dev, s);
+  else if (m->dim == 2 && m->cfg.physics == DG_MHD)
+    e = launch_mhd2d_cfl(m, U, cfl, dt_dev, s);
   else if (m->dim == 2)
     e = launch_cart2d_cfl(m, U, cfl, dt_dev, s);
   else

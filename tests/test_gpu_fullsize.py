@@ -6,6 +6,8 @@
   oracle finishes a step in about a second on the host's cores); the FP32
   error is stated.
 * C3 256^3 MHD: one FP64 step against the oracle, every cell.
+* 2D MHD Orszag-Tang at the paper's 512^2: two FP64 steps (limiter on, fused
+  CFL minima, device step sizes) against the oracle, every cell.
 * C5 (256 instances, N in {64..512}): the full batch in its bench launch shape;
   four sampled instances (the first, the largest and two others) carry the
   seeded recipe and are compared with the oracle; the others hold a uniform
@@ -136,6 +138,25 @@ def test_c3_full_size(oracle, torch_cuda):
         np.abs(B[20:23]).max()
     print(f"C3 256^3 fp64, 1 step, per-field error: {e}, B: {eb:.3e}")
     assert e.max() < 1e-12 and eb < 1e-12, (e, eb)
+
+
+def test_orszag_tang_512_full_size(oracle, torch_cuda):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    n = 512
+    U0 = W.orszag_tang_state(n)
+    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    ref, dts = oracle.run(om, U0, 2, G53, 0.3, True, mhd=True)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), physics="mhd", precision=prec,
+                   gamma=G53)
+        got = _run_gpu(s, U0, dts).double().cpu().numpy()
+        e = errs_hydro(got, ref, 5, 2, 1.0 / n, 23)
+        A, B = got.reshape(23, -1), ref.reshape(23, -1)
+        eb = max(np.abs(A[15:18] - B[15:18]).max(), np.abs(A[18:] - B[18:]).max() / n) / \
+            np.abs(B[15:18]).max()
+        print(f"Orszag-Tang 512^2 {prec}, 2 steps, per-field error: {e}, B: {eb:.3e}")
+        assert e.max() < tol and eb < tol, (prec, e, eb)
+        s.close()
 
 
 def test_c5_full_batch_sampled(oracle, torch_cuda):

@@ -438,8 +438,10 @@ def orszag_tang_state(n, gamma=5.0 / 3.0, nq=None):
     """The paper's Orszag-Tang setup (Sec. 3.9) on the unit square: rho =
     gamma^2/(4 pi), p = gamma/(4 pi), v = (-sin 2 pi y, sin 2 pi x), and B =
     (-sin 2 pi y, sin 4 pi x) in the units of the cited setup, i.e. divided by
-    sqrt(4 pi) in the units used here (magnetic pressure B^2/2)."""
+    sqrt(4 pi) in the units used here (magnetic pressure B^2/2).  ``n`` is the
+    cell count per side or a pair (nx, ny)."""
     s4 = math.sqrt(4 * math.pi)
+    shape = (n, n) if np.isscalar(n) else tuple(n)
 
     def f(X, Y):
         rho = gamma ** 2 / (4 * math.pi) + 0.0 * X
@@ -448,7 +450,7 @@ def orszag_tang_state(n, gamma=5.0 / 3.0, nq=None):
         B = [-np.sin(2 * math.pi * Y) / s4, np.sin(4 * math.pi * X) / s4, 0.0 * X]
         return _mhd_conserved(rho, vel, p, B, gamma)
 
-    return project_cartesian(f, (n, n), (0.0, 0.0), (1.0, 1.0), nq=nq, mhd=True)
+    return project_cartesian(f, shape, (0.0, 0.0), (1.0, 1.0), nq=nq, mhd=True)
 
 
 def rotor_state(n, gamma=5.0 / 3.0, nq=None):
