@@ -38,6 +38,13 @@ STAGE_VALUES = {1: 24, 2: 36}
 # Gauss points of 3 faces, 8 volume points, accumulation, inverse mass matrix
 # and the RK combination; counted from the kernel's formulation).
 MHD_FLOPS_PER_CELL_STAGE = 8700
+# The same count for one 2D MHD cell-stage (4 HLLD solves at the two Gauss
+# points of the -x and +y faces a cell owns, 4 volume points, traces,
+# accumulation and the stage combination).
+MHD2D_FLOPS_PER_CELL_STAGE = 3000
+# Algorithmic bytes of one 2D MHD cell-stage: 69 of the 23-coefficient values
+# (stage 1 reads U, writes V1 and Pi(U); stage 2 reads V1 and Pi(U), writes U').
+MHD2D_BYTES_PER_CELL_STAGE = {"fp64": 69 * 8, "fp32": 69 * 4}
 # Algorithmic bytes of one 2D Euler cell-stage on a face list: the state (24
 # values per stage on average: 2.5 coefficient sets of 12 per step / 2 stages
 # rounded as in the Cartesian case, 240 B in FP64) plus the static geometry a
@@ -50,10 +57,11 @@ FACELIST_BYTES_PER_CELL_STAGE = {"fp64": 464, "fp32": 232}
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5"], default="c2",
+    p.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5", "ot"], default="c2",
                    help="c2: 2D Euler shear layer 2048^2 (default); c1: isentropic vortex "
                         "64^2; c3: 3D MHD 256^3; c4: static Voronoi mesh of 1M cells; c5: "
-                        "256 batched instances N^2, N in {64..512}, with the adjoint")
+                        "256 batched instances N^2, N in {64..512}, with the adjoint; ot: 2D "
+                        "MHD Orszag-Tang vortex 512^2")
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--n", type=int, default=None, help="cells per side")
@@ -72,7 +80,8 @@ def parse():
     # (cells per side or cells, timed steps, warm-up steps, oracle steps of the
     # CPU baseline sized to about 10-30 s of host work)
     dflt = {"c1": (64, 100, 10, 8000), "c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 12),
-            "c4": (1000000, 100, 5, 50), "c5": (256, 200, 20, 800)}[a.config]
+            "c4": (1000000, 100, 5, 50), "c5": (256, 200, 20, 800),
+            "ot": (512, 1000, 20, 16)}[a.config]
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
@@ -323,6 +332,51 @@ def bench_c3(a):
         ns = 96
         out["cpu_baseline"] = cpu_baseline(W.c3_state(ns), ns, a.cpu_steps, dim=3, mhd=True,
                                            label="the same MHD-turbulence recipe")
+    return out
+
+
+def bench_ot(a):
+    import workloads as W
+    from paper_1305_5536_amd.solver import cartesian
+    n = a.n
+    U0 = W.orszag_tang_state(n)
+    mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    r = run_gpu(U0, mesh, "mhd", 5.0 / 3.0, a.precision, a.steps, a.warmup)
+    ncells = n * n
+    value = ncells * 2 * a.steps / r["event_s"]
+    peak = FP64_VALU_PEAK_TFLOPS if a.precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+    # dominant kernel: stage 2 (k_mhd2d<T, 2, true>; the event bracket also
+    # holds the 4-us one-workgroup dt reduction)
+    achieved = MHD2D_FLOPS_PER_CELL_STAGE * ncells / r["stage2_s"] / 1e12
+    traffic = pmc_traffic("k_mhd2d_ot_512.md", "k_mhd2d<double, 2, true>", f"{n}x{n}",
+                          "paper_1305_5536_amd/csrc/mhd2d.hip") if a.precision == "fp64" else None
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"2D ideal MHD Orszag-Tang vortex, periodic Cartesian {n}^2, "
+                               "gamma 5/3, P1 Taylor + 2D divergence-free B basis, HLLD, "
+                               "limiter on, SSP-RK2",
+                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "stage 2 (k_mhd2d, limit on read, + dt reduction)",
+                     "flops_per_launch": MHD2D_FLOPS_PER_CELL_STAGE * ncells,
+                     "algorithmic_bytes_per_launch": MHD2D_BYTES_PER_CELL_STAGE[a.precision] * ncells,
+                     "avg_launch_s": r["stage2_s"]},
+        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3},
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu(U0, mesh, "mhd", 5.0 / 3.0, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "stage2_TFLOPs": MHD2D_FLOPS_PER_CELL_STAGE * ncells / r32["stage2_s"] / 1e12}
+    if not a.no_cpu:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, dim=2, mhd=True,
+                                           label="the Orszag-Tang setup")
     return out
 
 
@@ -664,7 +718,7 @@ def main():
         copy_calibration()
         return
     out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-           "c5": bench_c5}[a.config](a)
+           "c5": bench_c5, "ot": bench_ot}[a.config](a)
     print(json.dumps(out))
 
 

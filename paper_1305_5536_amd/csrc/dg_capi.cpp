@@ -68,8 +68,19 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
-// Meshes whose limiter runs as a pass of its own into ws_a / ws_b (3D and 2D
-// MHD, face lists); the 2D Euler kernels limit inside the stage kernel.
+// Rows per wave of the 2D MHD stage kernel: about 8192 waves over the mesh,
+// 2 to 16 rows (each wave solves one extra y-face row; measured on 512^2 and
+// 2048^2 meshes).
+static int default_rows_mhd2d(int64_t ntiles_x, int64_t nrows) {
+  int64_t rows = (ntiles_x * nrows + 8191) / 8192;
+  rows = std::max<int64_t>(2, std::min<int64_t>(16, rows));
+  return (int)std::min<int64_t>(rows, nrows);
+}
+
+// Meshes that keep Pi(U) of stage 1 in ws_a for stage 2 (3D MHD and face
+// lists limit in passes of their own into ws_a / ws_b; 2D MHD limits on read
+// and its stage 1 writes Pi(U) to ws_a); the 2D Euler kernels limit inside
+// the stage kernel and recompute Pi(U^n) in stage 2.
 static bool limiter_pass(const dg_mesh* m) {
   return m->dim == 3 || m->kind == 1 || m->cfg.physics == DG_MHD;
 }
@@ -254,9 +265,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.ny = (int)d->n[1];
     m->c2.hx = (d->hi[0] - d->lo[0]) / d->n[0];
     m->c2.hy = (d->hi[1] - d->lo[1]) / d->n[1];
-    // Euler tiles hold 60 interior columns, MHD tiles 62
-    m->c2.tiles_x = (int)(mhd ? (d->n[0] + 61) / 62 : (d->n[0] + 59) / 60);
-    m->c2.rows_per_tile = default_rows(m->c2.tiles_x, d->n[1]);
+    m->c2.tiles_x = (int)((d->n[0] + 59) / 60);  // 60 interior columns per wave
+    m->c2.rows_per_tile =
+        mhd ? default_rows_mhd2d(m->c2.tiles_x, d->n[1]) : default_rows(m->c2.tiles_x, d->n[1]);
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
     if (cfg->physics == DG_EULER) {
@@ -339,7 +350,8 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   hipError_t e = hipMalloc(&m->v1, bytes);
   const bool separate_limiter = limiter_pass(m);
   if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_a, bytes);
-  if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_b, bytes);
+  // (2D MHD limits on read: its stage kernels need only ws_a, for Pi(U^n))
+  if (e == hipSuccess && (m->dim == 3 || m->kind == 1)) e = hipMalloc(&m->ws_b, bytes);
   if (e == hipSuccess) e = hipMalloc(&m->status, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
@@ -691,7 +703,9 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
   }
   if (m->kind != 0) return DG_OK;
   if (m->dim == 2) {
-    int r = rows ? std::min(rows, m->c2.ny) : default_rows(m->c2.tiles_x, m->c2.ny);
+    int r = rows ? std::min(rows, m->c2.ny)
+                 : (m->cfg.physics == DG_MHD ? default_rows_mhd2d(m->c2.tiles_x, m->c2.ny)
+                                             : default_rows(m->c2.tiles_x, m->c2.ny));
     m->c2.rows_per_tile = r;
     m->c2.tiles_y = (m->c2.ny + r - 1) / r;
   } else {

@@ -17,15 +17,23 @@
 // Sec. 2.5 with one alpha for Bx, By and Bz.
 //
 // Kernels.
-//   k_lim2m : Pi(U) -> out, one thread per cell (memory bound).
-//   k_mhd2d : L(Ulim) combined into an SSP-RK2 stage.  One wave owns up to
-//             62 x-columns (lanes 0 and 63 are halo columns) and marches up a
-//             range of rows.  x-faces: each lane solves its -x face and hands
-//             the sums to its left neighbour through DPP.  y-faces: solved once
-//             per row pair, the lower row's share carried to the next row in
-//             registers; a tile's first -y face is solved by both tiles that
-//             share it, with the same operands, so every face flux is
-//             bit-identical on its two sides (exact conservation).
+//   k_mhd2d : one SSP-RK2 stage (or L alone), limiting its input on read.  One
+//             wave owns up to 60 x-columns (lanes 0, 1 and 62, 63 are halo
+//             columns: a limited cell needs its x-neighbours' means, an owned
+//             cell its x-neighbours limited) and marches up a range of rows.
+//             The current limited row sits in wave-private LDS (each lane only
+//             touches its own slot), the row above is loaded and limited while
+//             the current row's x-faces and volume term are computed (its
+//             y-neighbours' means are the current row and one row further up).
+//             x-faces: each lane solves its -x face per Gauss point and hands
+//             the flux to its left neighbour through DPP.  y-faces: solved once
+//             per row pair, the lower row's sums carried to the next row; a
+//             tile's first -y face is solved by both tiles that share it with
+//             the same operands and arithmetic, so every face flux is
+//             bit-identical on its two sides.  Stage 1 also writes Pi(U^n) of
+//             its cells, which stage 2 reads for its combination.
+//   k_lim2m : Pi(U) -> out, one thread per cell (dg_limit, and Pi(U^n) for a
+//             stage 2 not preceded by the stage 1 of the same U).
 //   k_cfl2m : per-wave minima of the CFL bound (fast magnetosonic speeds).
 // The stage kernel is VALU-bound: four HLLD solves per cell and stage.
 //
@@ -54,6 +62,7 @@ struct P2M {
   const T* __restrict__ in;  // limited state (stage kernel) or raw state (limiter, CFL)
   const T* __restrict__ ua;  // stage 2: Pi(U^n)
   T* __restrict__ out;
+  T* __restrict__ lim_out;   // stage 1 with the limiter: Pi(in) of the owned cells (or NULL)
   const double* dt_dev;
   double dt_host;
   int* status;
@@ -130,6 +139,44 @@ __device__ __forceinline__ T alpha_of(T phi, T hi, T lo, T gx, T gy, const P2M<T
   const T D = fmin(hi - phi, phi - lo);
   const T dm = fmax(fabs(gx) * p.half[0], fabs(gy) * p.half[1]);
   return (dm > D) ? D * rcp(dm) : T(1);
+}
+
+// The limiter of Sec. 2.5 applied to a cell held by this lane, inside a row
+// held by the wave: the x-neighbours' means come from lanes -1 and +1 by DPP
+// (the end lanes get wrong values; they are halo lanes whose results are not
+// used), the y-neighbours' means are mS and mN (order rho, mx, my, mz, E, Bx,
+// By, Bz).
+template <typename T>
+__device__ __forceinline__ void limit_in_row(Q2<T>& q, const T* mS, const T* mN,
+                                             const P2M<T>& p) {
+  T hi[8], lo[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const T own = k < 5 ? q.m[k] : q.b[k - 5];
+    const T l = lane_up(own), r = lane_down(own);
+    hi[k] = fmax(fmax(fmax(own, l), fmax(r, mS[k])), mN[k]);
+    lo[k] = fmin(fmin(fmin(own, l), fmin(r, mS[k])), mN[k]);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T a = alpha_of(q.m[v], hi[v], lo[v], q.g[v][0], q.g[v][1], p);
+    q.g[v][0] *= a;
+    q.g[v][1] *= a;
+  }
+  T aB = T(1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    aB = fmin(aB, alpha_of(q.b[c], hi[5 + c], lo[5 + c], dB(q.a, c, 0), dB(q.a, c, 1), p));
+#pragma unroll
+  for (int jj = 0; jj < 5; ++jj) q.a[jj] *= aB;
+}
+
+template <typename T>
+__device__ __forceinline__ void means_of(const Q2<T>& q, T* m) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) m[v] = q.m[v];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m[5 + c] = q.b[c];
 }
 
 // ------------------------------------------------------------- limiter --
@@ -326,27 +373,69 @@ __device__ __forceinline__ void finish(const Acc<T>& a, const P2M<T>& p, Q2<T>& 
   d.a[4] = a.P[2][1] * p.imu[1];
 }
 
-template <typename T>
-__device__ __forceinline__ void lane_up_q(const Q2<T>& q, Q2<T>& o) {
+// Accumulate one Gauss point of a face of axis D (tangential sign s) into a
+// cell's residual, as add_face does for the sums of a face.
+template <typename T, int D>
+__device__ __forceinline__ void add_point(Acc<T>& a, const T* F, T s, T sigma, const P2M<T>& p) {
+  constexpr int t = 1 - D;
+  const T cm = sigma * p.c2h[D], ct = s * sigma * p.cs, cp = s * sigma * p.pt[D];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k != 5 + D) a.m[k] = fma(cm, F[k], a.m[k]);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    o.m[v] = lane_up(q.m[v]);
-    o.g[v][0] = lane_up(q.g[v][0]);
-    o.g[v][1] = lane_up(q.g[v][1]);
+    a.g[v][D] = fma(-p.c3[D], F[v], a.g[v][D]);
+    a.g[v][t] = fma(ct, F[v], a.g[v][t]);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) o.b[c] = lane_up(q.b[c]);
+  for (int c = 0; c < 3; ++c) {
+    if (c == D) continue;
+    a.P[c][D] = fma(T(-0.25), F[5 + c], a.P[c][D]);
+    a.P[c][t] = fma(cp, F[5 + c], a.P[c][t]);
+  }
+}
+
+// Wave-private LDS copy of the current row's polynomials (one slot per lane),
+// which keeps 23 values per lane out of the register file while the Riemann
+// solves run.  Each lane touches only its own slot; the compiler barriers stop
+// the compiler from forwarding the stores to the loads (which would put the
+// row back into registers).
+template <typename T>
+struct Row {
+  T v[23][64];
+};
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+template <typename T>
+__device__ __forceinline__ void lds_put(Row<T>& r, int lane, const Q2<T>& q) {
+  compiler_fence();
 #pragma unroll
-  for (int j = 0; j < 5; ++j) o.a[j] = lane_up(q.a[j]);
+  for (int v = 0; v < 5; ++v) {
+    r.v[3 * v][lane] = q.m[v];
+    r.v[3 * v + 1][lane] = q.g[v][0];
+    r.v[3 * v + 2][lane] = q.g[v][1];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r.v[15 + c][lane] = q.b[c];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) r.v[18 + j][lane] = q.a[j];
+  compiler_fence();
 }
 
 template <typename T>
-__device__ __forceinline__ void lane_down_sums(Sums<T>& f) {
+__device__ __forceinline__ void lds_get(const Row<T>& r, int lane, Q2<T>& q) {
+  compiler_fence();
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    f.S[k] = lane_down(f.S[k]);
-    f.T1[k] = lane_down(f.T1[k]);
+  for (int v = 0; v < 5; ++v) {
+    q.m[v] = r.v[3 * v][lane];
+    q.g[v][0] = r.v[3 * v + 1][lane];
+    q.g[v][1] = r.v[3 * v + 2][lane];
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) q.b[c] = r.v[15 + c][lane];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) q.a[j] = r.v[18 + j][lane];
 }
 
 // CFL bound of a cell from its means: 1 / sum_d (|v_d| + c_f,d)/h_d over the
@@ -370,69 +459,176 @@ __device__ __forceinline__ double cell_dt(const T* m, const P2M<T>& p) {
   return 1.0 / s;
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(64) void k_mhd2d(P2M<T> p) {
+// State at a point of a face of axis D: normal offset hn, tangential offset ht
+// from the cell centroid.
+template <typename T, int D>
+__device__ __forceinline__ void point(const Q2<T>& q, T hn, T ht, T* u) {
+  constexpr int t = 1 - D;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = fma(q.g[v][t], ht, fma(q.g[v][D], hn, q.m[v]));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[5 + c] = fma(dB(q.a, c, t), ht, fma(dB(q.a, c, D), hn, q.b[c]));
+}
+
+// HLLD flux at the Gauss point of tangential sign s of the y-face between the
+// cells lo (below) and hi (above).
+template <typename T>
+__device__ __forceinline__ void yface_point(const Q2<T>& lo, const Q2<T>& hi, T s,
+                                            const P2M<T>& p, T* F, bool& bad) {
+  T uL[8], uR[8];
+  point<T, 1>(lo, p.half[1], s * p.q[0], uL);
+  point<T, 1>(hi, -p.half[1], s * p.q[0], uR);
+  // one normal field for the Riemann problem: the average of both sides
+  const T bn = T(0.5) * (uL[6] + uR[6]);
+  uL[6] = bn;
+  uR[6] = bn;
+  hlld_axis<T, 1>(uL, uR, p.gamma, p.eps, F, bad);
+}
+
+// Sums of a y-face from its two Gauss-point fluxes (s = -1, then +1).
+template <typename T>
+__device__ __forceinline__ void ysums(const T* Fm, const T* Fp, Sums<T>& f) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f.S[k] = Fm[k] + Fp[k];
+    f.T1[k] = Fp[k] - Fm[k];
+  }
+}
+
+// Occupancy target (measured): one wave per SIMD in FP64, where the stage
+// kernels then keep everything in registers (capping them at 256 for two waves
+// spills and runs slower), three in FP32 (168 registers, no spills).
+template <typename T>
+struct Waves {
+  static constexpr int n = sizeof(T) == 8 ? 1 : 3;
+};
+
+template <typename T, int MODE, bool LIM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Waves<T>::n, Waves<T>::n)))
+void k_mhd2d(P2M<T> p) {
+  __shared__ Row<T> row;  // the current (limited) row; each lane reads only its own slot
   const int lane = threadIdx.x;
   const int wave = xcd_remap(blockIdx.x, gridDim.x);
   if (wave >= p.ntiles) return;
   const int tx = wave % p.tiles_x, ty = wave / p.tiles_x;
   const int nx = p.nx, ny = p.ny, nc = p.nc;
-  const int colu = tx * p.width + lane - 1;
-  const bool own = lane >= 1 && lane <= p.width && colu < nx;
+  // lanes 0, 1 and 62, 63 are halo columns: a limited cell needs the means of
+  // its x-neighbours, and an owned cell needs its x-neighbours limited
+  const int colu = tx * p.width + lane - 2;
+  const bool own = lane >= 2 && lane < 2 + p.width && colu < nx;
   int col = colu % nx;
   if (col < 0) col += nx;
   const int y0 = ty * p.rows;
   const int y1 = min(y0 + p.rows, ny);
-  auto yw = [ny](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+  auto yw = [ny](int y) {
+    y %= ny;
+    return y < 0 ? y + ny : y;
+  };
   bool bad = false;
   double dtmin = 1e300;
 
-  Q2<T> cur;
   Sums<T> carry;  // sums of the current row's -y face
   {
-    Q2<T> prv;
+    Q2<T> prv, cur;
     load_q(p.in, nc, yw(y0 - 1) * nx + col, prv);
     load_q(p.in, nc, y0 * nx + col, cur);
-    face<T, 1>(prv, cur, p, carry, bad);
+    if (LIM) {
+      T mA[8], mB[8], mP[8], mC[8];
+      load_means(p.in, nc, yw(y0 - 2) * nx + col, mA);
+      load_means(p.in, nc, yw(y0 + 1) * nx + col, mB);
+      means_of(prv, mP);
+      means_of(cur, mC);
+      limit_in_row(prv, mA, mC, p);
+      limit_in_row(cur, mP, mB, p);
+    }
+    T Fm[8], Fp[8];
+    yface_point(prv, cur, T(-1), p, Fm, bad);
+    yface_point(prv, cur, T(1), p, Fp, bad);
+    ysums(Fm, Fp, carry);
+    lds_put(row, lane, cur);
   }
   T dt = T(0);
   if (MODE != kRhs) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
 
   for (int y = y0; y < y1; ++y) {
-    Q2<T> nb;  // the row above, in flight while the x-faces are solved
-    load_q(p.in, nc, yw(y + 1) * nx + col, nb);
     Acc<T> acc;
     zero(acc);
     add_face<T, 1>(acc, carry, T(1), p);
-    {
-      // x-faces: this lane solves its -x face (left neighbour by DPP); the +x
-      // face comes from lane + 1
-      Q2<T> l;
-      lane_up_q(cur, l);
-      Sums<T> fx;
-      face<T, 0>(l, cur, p, fx, bad);
-      add_face<T, 0>(acc, fx, T(1), p);
-      lane_down_sums(fx);
-      add_face<T, 0>(acc, fx, T(-1), p);
+    // x-faces: this lane solves its -x face at each Gauss point; the left
+    // cell's +x point value comes from lane - 1 and the flux goes back to it
+    // by DPP.  The row polynomial is re-read from LDS per point, so no face
+    // trace stays live across a Riemann solve.
+#pragma unroll 1
+    for (int g = 0; g < 2; ++g) {
+      const T s = g ? T(1) : T(-1);
+      Q2<T> c;
+      lds_get(row, lane, c);
+      T uL[8], uR[8], F[8];
+      point<T, 0>(c, p.half[0], s * p.q[1], uL);
+      point<T, 0>(c, -p.half[0], s * p.q[1], uR);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) uL[k] = lane_up(uL[k]);
+      const T bn = T(0.5) * (uL[5] + uR[5]);
+      uL[5] = bn;
+      uR[5] = bn;
+      hlld_axis<T, 0>(uL, uR, p.gamma, p.eps, F, bad);
+      add_point<T, 0>(acc, F, s, T(1), p);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) F[k] = lane_down(F[k]);
+      add_point<T, 0>(acc, F, s, T(-1), p);
     }
-    add_volume(acc, cur, p, bad);
-    face<T, 1>(cur, nb, p, carry, bad);
-    add_face<T, 1>(acc, carry, T(-1), p);
+    // the row above (limited on read: its y-neighbours are this row and the
+    // row above it); the loads are in flight during the volume term
+    Q2<T> nb;
+    load_q(p.in, nc, yw(y + 1) * nx + col, nb);
+    T mN2[8];
+    if (LIM) load_means(p.in, nc, yw(y + 2) * nx + col, mN2);
+    {
+      Q2<T> c;
+      lds_get(row, lane, c);
+      add_volume(acc, c, p, bad);
+    }
+    if (LIM) {
+      Q2<T> c;
+      lds_get(row, lane, c);
+      T mC[8];
+      means_of(c, mC);
+      limit_in_row(nb, mC, mN2, p);
+    }
+    {
+      T Fm[8], Fp[8];
+      {
+        Q2<T> c;
+        lds_get(row, lane, c);
+        yface_point(c, nb, T(-1), p, Fm, bad);
+      }
+      add_point<T, 1>(acc, Fm, T(-1), T(-1), p);
+      {
+        Q2<T> c;
+        lds_get(row, lane, c);
+        yface_point(c, nb, T(1), p, Fp, bad);
+      }
+      add_point<T, 1>(acc, Fp, T(1), T(-1), p);
+      ysums(Fm, Fp, carry);
+    }
     Q2<T> d;
     finish(acc, p, d);
+    const int e = y * nx + col;
     if (MODE != kRhs) {
+      Q2<T> c;
+      lds_get(row, lane, c);
+      if (MODE == kStage1 && LIM && p.lim_out && own) store_q(p.lim_out, nc, e, c);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        d.m[v] = fma(dt, d.m[v], cur.m[v]);
-        d.g[v][0] = fma(dt, d.g[v][0], cur.g[v][0]);
-        d.g[v][1] = fma(dt, d.g[v][1], cur.g[v][1]);
+        d.m[v] = fma(dt, d.m[v], c.m[v]);
+        d.g[v][0] = fma(dt, d.g[v][0], c.g[v][0]);
+        d.g[v][1] = fma(dt, d.g[v][1], c.g[v][1]);
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d.b[c] = fma(dt, d.b[c], cur.b[c]);
+      for (int cc = 0; cc < 3; ++cc) d.b[cc] = fma(dt, d.b[cc], c.b[cc]);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) d.a[j] = fma(dt, d.a[j], cur.a[j]);
+      for (int j = 0; j < 5; ++j) d.a[j] = fma(dt, d.a[j], c.a[j]);
     }
-    const int e = y * nx + col;
     if (MODE == kStage2) {
       Q2<T> ua;
       load_q(p.ua, nc, e, ua);
@@ -454,7 +650,7 @@ __global__ __launch_bounds__(64) void k_mhd2d(P2M<T> p) {
         dtmin = fmin(dtmin, cell_dt(mm, p));
       }
     }
-    cur = nb;
+    lds_put(row, lane, nb);
   }
   // every face is the -x or -y face of a cell owned by some wave, so the
   // owners' flags cover all quadrature points
@@ -485,6 +681,7 @@ P2M<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.in = static_cast<const T*>(in);
   p.ua = static_cast<const T*>(ua);
   p.out = static_cast<T*>(out);
+  p.lim_out = nullptr;
   p.dt_dev = dt_dev;
   p.dt_host = dt_host;
   p.status = m->status;
@@ -525,25 +722,28 @@ hipError_t lim_t(const dg_mesh* m, const void* in, void* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Stage kernel launch.  lim: limit `in` on read; lim_out: stage 1 also
+// writes Pi(in) there.
 template <typename T>
-hipError_t rhs_t(const dg_mesh* m, int mode, const void* in, const void* ua, void* out,
-                 const double* dt_dev, double dt_host, bool want_dt, hipStream_t s) {
+hipError_t rhs_t(const dg_mesh* m, int mode, bool lim, const void* in, const void* ua, void* out,
+                 void* lim_out, const double* dt_dev, double dt_host, bool want_dt, hipStream_t s) {
   P2M<T> p = make_params<T>(m, in, ua, out, dt_dev, dt_host);
   if (want_dt) p.dtpart = m->dtpart;
+  p.lim_out = static_cast<T*>(lim_out);
   const unsigned nb = (unsigned)p.ntiles;
-  switch (mode) {
-    case kRhs:
-      hipLaunchKernelGGL((k_mhd2d<T, kRhs>), dim3(nb), dim3(64), 0, s, p);
-      break;
-    case kStage1:
-      hipLaunchKernelGGL((k_mhd2d<T, kStage1>), dim3(nb), dim3(64), 0, s, p);
-      break;
-    case kStage2:
-      hipLaunchKernelGGL((k_mhd2d<T, kStage2>), dim3(nb), dim3(64), 0, s, p);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  const dim3 g(nb), b(64);
+  if (mode == kRhs && !lim)
+    hipLaunchKernelGGL((k_mhd2d<T, kRhs, false>), g, b, 0, s, p);
+  else if (mode == kStage1 && !lim)
+    hipLaunchKernelGGL((k_mhd2d<T, kStage1, false>), g, b, 0, s, p);
+  else if (mode == kStage1)
+    hipLaunchKernelGGL((k_mhd2d<T, kStage1, true>), g, b, 0, s, p);
+  else if (mode == kStage2 && !lim)
+    hipLaunchKernelGGL((k_mhd2d<T, kStage2, false>), g, b, 0, s, p);
+  else if (mode == kStage2)
+    hipLaunchKernelGGL((k_mhd2d<T, kStage2, true>), g, b, 0, s, p);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -560,9 +760,9 @@ hipError_t cfl_t(const dg_mesh* m, const void* U, hipStream_t s) {
 
 hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt, hipStream_t s);
 
-// Stage dispatch for 2D MHD.  The limiter runs as its own pass into the
-// workspace (ws_a holds Pi(U) of stage 1 for the stage-2 combination, ws_b
-// holds Pi(V1)).
+// Stage dispatch for 2D MHD.  The stage kernels limit their input on read;
+// stage 1 also writes Pi(U) to ws_a, which a stage 2 on the same U reuses as
+// its Pi(U^n) (any other stage 2 limits U^n into ws_a with a separate pass).
 hipError_t launch_mhd2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                         const double* dt_dev, double dt_host, double cfl, double* dt_next,
                         hipStream_t s) {
@@ -571,36 +771,26 @@ hipError_t launch_mhd2d(const dg_mesh* m, int mode, const void* in, const void* 
   auto limit = [&](const void* a, void* b) {
     return f64 ? lim_t<double>(m, a, b, s) : lim_t<float>(m, a, b, s);
   };
-  auto rhs = [&](int md, const void* a, const void* ua, void* o, bool want_dt) {
-    return f64 ? rhs_t<double>(m, md, a, ua, o, dt_dev, dt_host, want_dt, s)
-               : rhs_t<float>(m, md, a, ua, o, dt_dev, dt_host, want_dt, s);
+  auto rhs = [&](int md, bool l, const void* a, const void* ua, void* o, void* lo, bool want_dt) {
+    return f64 ? rhs_t<double>(m, md, l, a, ua, o, lo, dt_dev, dt_host, want_dt, s)
+               : rhs_t<float>(m, md, l, a, ua, o, lo, dt_dev, dt_host, want_dt, s);
   };
   hipError_t e = hipSuccess;
   switch (mode) {
     case kLimit:
       return limit(in, out);
     case kRhs:
-      return rhs(kRhs, in, nullptr, out, false);
-    case kStage1: {
-      const void* a = in;
-      if (lim) {
-        e = limit(in, m->ws_a);
-        a = m->ws_a;
-      }
-      if (e == hipSuccess) e = rhs(kStage1, a, nullptr, out, false);
-      return e;
-    }
+      return rhs(kRhs, false, in, nullptr, out, nullptr, false);
+    case kStage1:
+      return rhs(kStage1, lim, in, nullptr, out, lim ? m->ws_a : nullptr, false);
     case kStage2: {
       // in = V1, u0 = U^n
       const void* ua = u0;
-      const void* b = in;
       if (lim) {
         if (!(m->ws_a_fresh && m->ws_a_src == u0)) e = limit(u0, m->ws_a);
         ua = m->ws_a;
-        if (e == hipSuccess) e = limit(in, m->ws_b);
-        b = m->ws_b;
       }
-      if (e == hipSuccess) e = rhs(kStage2, b, ua, out, dt_next != nullptr);
+      if (e == hipSuccess) e = rhs(kStage2, lim, in, ua, out, nullptr, dt_next != nullptr);
       if (e == hipSuccess && dt_next)
         e = launch_min_finalize(m->dtpart, m->c2.tiles_x * m->c2.tiles_y, cfl, dt_next, s);
       return e;
