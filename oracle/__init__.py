@@ -55,19 +55,21 @@ def lib():
         L.or_ncoef.restype = ctypes.c_int
         L.or_ncoef.argtypes = [ctypes.c_int, ctypes.c_int]
         L.or_rhs.restype = ctypes.c_int
-        L.or_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.or_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
+                             _dp]
         L.or_limit.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
         L.or_step.restype = ctypes.c_int
-        L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
-                              ctypes.c_double, _dp]
+        L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.or_step_jvp.restype = ctypes.c_int
         L.or_step_jvp.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   _dp, _dp, ctypes.c_double, _dp, _dp]
         L.or_step_mh.restype = ctypes.c_int
-        L.or_step_mh.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp,
-                                 ctypes.c_double, _dp]
+        L.or_step_mh.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 _dp, ctypes.c_double, _dp]
         L.or_rhs_mh.restype = ctypes.c_int
-        L.or_rhs_mh.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, ctypes.c_double, _dp]
+        L.or_rhs_mh.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp,
+                                ctypes.c_double, _dp]
         L.or_predict_prim.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_double,
                                       _dp, _dp]
         L.or_rhs_jvp.restype = ctypes.c_int
@@ -79,6 +81,9 @@ def lib():
         L.or_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
         L.or_hll.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
         L.or_hlld.argtypes = [ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.or_exact_riemann.restype = ctypes.c_int
+        L.or_exact_riemann.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
+                                       _dp]
         L.or_cell_geometry.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp,
                                        ctypes.POINTER(ctypes.c_int), _dp, _dp]
         L.or_gram_B.argtypes = [_dp, _dp]
@@ -176,11 +181,16 @@ def _state(mesh: Mesh, U, mhd: bool) -> np.ndarray:
     return U
 
 
-def rhs(mesh: Mesh, U, gamma: float, mhd: bool = False, check: bool = True) -> np.ndarray:
-    """Semi-discrete DG right-hand side L(U), coefficient-major layout."""
+_RIEMANN = {"hll": 0, "exact": 1}
+
+
+def rhs(mesh: Mesh, U, gamma: float, mhd: bool = False, check: bool = True,
+        flux: str = "hll") -> np.ndarray:
+    """Semi-discrete DG right-hand side L(U), coefficient-major layout.
+    flux: the Euler face flux, "hll" or "exact" (MHD always uses HLLD)."""
     U = _state(mesh, U, mhd)
     out = np.empty_like(U)
-    rc = lib().or_rhs(mesh._h, int(mhd), gamma, _p(U), _p(out))
+    rc = lib().or_rhs(mesh._h, int(mhd), _RIEMANN[flux], gamma, _p(U), _p(out))
     if rc and check:
         raise NonPhysical("non-physical state in L(U)")
     return out
@@ -195,11 +205,12 @@ def limit(mesh: Mesh, U, mhd: bool = False) -> np.ndarray:
 
 
 def step(mesh: Mesh, U, dt: float, gamma: float, limiter: bool, mhd: bool = False,
-         check: bool = True) -> np.ndarray:
+         check: bool = True, flux: str = "hll") -> np.ndarray:
     """One SSP-RK2 step with the limiter at the start of each stage."""
     U = _state(mesh, U, mhd)
     out = np.empty_like(U)
-    rc = lib().or_step(mesh._h, int(mhd), int(limiter), gamma, _p(U), dt, _p(out))
+    rc = lib().or_step(mesh._h, int(mhd), _RIEMANN[flux], int(limiter), gamma, _p(U), dt,
+                       _p(out))
     if rc and check:
         raise NonPhysical("non-physical state in step")
     return out
@@ -234,21 +245,22 @@ def cfl_dt(mesh: Mesh, U, gamma: float, cfl: float, mhd: bool = False) -> float:
     return lib().or_cfl_dt(mesh._h, int(mhd), gamma, _p(U), cfl)
 
 
-def step_mh(mesh: Mesh, U, dt: float, gamma: float, limiter: bool) -> np.ndarray:
+def step_mh(mesh: Mesh, U, dt: float, gamma: float, limiter: bool,
+            flux: str = "hll") -> np.ndarray:
     """One MUSCL-Hancock step (Euler): Ua = Pi(U), U' = Ua + dt L_MH(Ua; dt/2)."""
     U = _state(mesh, U, False)
     out = np.empty_like(U)
-    if lib().or_step_mh(mesh._h, int(limiter), gamma, _p(U), dt, _p(out)):
+    if lib().or_step_mh(mesh._h, _RIEMANN[flux], int(limiter), gamma, _p(U), dt, _p(out)):
         raise NonPhysical("non-physical state in the MUSCL-Hancock step")
     return out
 
 
-def rhs_mh(mesh: Mesh, U, half_dt: float, gamma: float) -> np.ndarray:
+def rhs_mh(mesh: Mesh, U, half_dt: float, gamma: float, flux: str = "hll") -> np.ndarray:
     """The MUSCL-Hancock operator: surface and volume terms of the half-step
     primitive prediction (no limiter)."""
     U = _state(mesh, U, False)
     out = np.empty_like(U)
-    rc = lib().or_rhs_mh(mesh._h, gamma, _p(U), half_dt, _p(out))
+    rc = lib().or_rhs_mh(mesh._h, _RIEMANN[flux], gamma, _p(U), half_dt, _p(out))
     if rc:
         raise NonPhysical("non-physical state in the MUSCL-Hancock operator")
     return out
@@ -267,9 +279,11 @@ def predict_prim(mean, grad, gamma: float, half_dt: float):
 
 
 def run(mesh: Mesh, U, nsteps: int, gamma: float, cfl: float, limiter: bool,
-        mhd: bool = False, t_end: float | None = None, integrator: str = "rk2"):
+        mhd: bool = False, t_end: float | None = None, integrator: str = "rk2",
+        flux: str = "hll"):
     """Advance nsteps (or until t_end) with the CFL step; returns (U, dt list).
-    integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock, Euler only)."""
+    integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock, Euler only); flux: the
+    Euler face flux ("hll" or "exact")."""
     U = _f64(U).copy()
     dts = []
     t = 0.0
@@ -280,9 +294,9 @@ def run(mesh: Mesh, U, nsteps: int, gamma: float, cfl: float, limiter: bool,
                 break
             dt = min(dt, t_end - t)
         if integrator == "mh":
-            U = step_mh(mesh, U, dt, gamma, limiter)
+            U = step_mh(mesh, U, dt, gamma, limiter, flux=flux)
         else:
-            U = step(mesh, U, dt, gamma, limiter, mhd)
+            U = step(mesh, U, dt, gamma, limiter, mhd, flux=flux)
         dts.append(dt)
         t += dt
     return U, dts
@@ -313,6 +327,21 @@ def hlld(uL, uR, n, gamma: float) -> np.ndarray:
     out = np.zeros(8)
     lib().or_hlld(gamma, _p(uL), _p(uR), _p(n3), _p(out))
     return out
+
+
+def exact_riemann(uL, uR, n, gamma: float):
+    """Exact Euler Riemann solver along the unit normal n: (flux, (p*, u*),
+    (rho, u_n, p) on the face).  Raises NonPhysical on vacuum generation."""
+    uL = _f64(uL)
+    uR = _f64(uR)
+    n3 = _f64(list(n) + [0.0] * (3 - len(n)))
+    out = np.zeros(8)
+    star = np.zeros(2)
+    face = np.zeros(3)
+    if lib().or_exact_riemann(len(n), gamma, _p(uL), _p(uR), _p(n3), _p(out), _p(star),
+                              _p(face)):
+        raise NonPhysical("vacuum generation in the Riemann problem")
+    return out[:len(uL)], star, face
 
 
 def gram_B2(M) -> np.ndarray:

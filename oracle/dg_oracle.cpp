@@ -79,6 +79,11 @@ inline Dual dabs(Dual a) { return a.v < 0 ? -a : a; }
 template <class T> inline T dmin(T a, T b) { return (b < a) ? b : a; }
 template <class T> inline T dmax(T a, T b) { return (b > a) ? b : a; }
 template <class T> inline bool finite(T a) { return std::isfinite(val(a)); }
+inline double dpow(double a, double e) { return std::pow(a, e); }
+inline Dual dpow(Dual a, double e) {
+  double p = std::pow(a.v, e);
+  return {p, e * p / a.v * a.d};
+}
 
 // ------------------------------------------------------------------- mesh --
 // A face f joins cells L and R; its unit normal n points from L to R.
@@ -311,6 +316,7 @@ struct Phys {
   int dim;      // spatial dimension of the mesh
   int mhd;      // 0 Euler, 1 ideal MHD (2D or 3D; velocity and B have 3 components)
   double gamma;
+  int riemann = 0;  // Euler face flux: 0 HLL (Davis speeds), 1 exact Riemann solver
   int nv() const { return mhd ? 8 : dim + 2; }
   int nvel() const { return mhd ? 3 : dim; }
   int nhyd() const { return mhd ? 5 : dim + 2; }  // Taylor-basis variables
@@ -561,6 +567,115 @@ void hlld(const Phys& P, const T* uL, const T* uR, const double* n, T* F) {
   uss[4] = Ess;
   T Ss = a == 0 ? SsL : SsR;
   for (int k = 0; k < 8; ++k) F[k] = Z.F[k] + Ss * (uss[k] - Z.u[k]);
+}
+
+// Exact Riemann solver for the Euler equations, the Euler flux the paper uses
+// (Sec. 2.3), posed along the face normal n.  In the face frame the two outer
+// waves are each a shock or a rarefaction; across a wave on side K the
+// velocity changes by f_K(p), with f_K from the Rankine-Hugoniot conditions
+// when p > p_K and from the isentropic relation with the Riemann invariant
+// u +- 2c/(gamma-1) when p <= p_K.  The star pressure p* solves
+// f_L(p) + f_R(p) + u_R - u_L = 0 (Newton's method started from the value
+// that is exact when both waves are rarefactions); u* = (u_L + u_R)/2 +
+// (f_R(p*) - f_L(p*))/2.  The state on the face (x/t = 0) follows from the
+// position of the waves, and the tangential velocity is the one upwind of the
+// contact.  F is the physical flux of that state.  Returns false on vacuum
+// generation (u_R - u_L >= 2 (c_L + c_R)/(gamma - 1)).
+template <class T> void wave_relation(T p, T rK, T pK, T cK, double g, T& f, T& df) {
+  if (p > pK) {
+    T A = T(2.0 / (g + 1.0)) / rK;
+    T B = T((g - 1.0) / (g + 1.0)) * pK;
+    T s = dsqrt(A / (p + B));
+    f = (p - pK) * s;
+    df = s * (T(1) - (p - pK) / (T(2) * (p + B)));
+  } else {
+    T r = dpow(p / pK, (g - 1.0) / (2.0 * g));
+    f = T(2.0 / (g - 1.0)) * cK * (r - T(1));
+    df = r * pK / (p * rK * cK);
+  }
+}
+
+template <class T>
+bool exact_riemann(const Phys& P, const T* uL, const T* uR, const double* n, T* F,
+                   T* star = nullptr, T* face_state = nullptr) {
+  const int nvel = P.nvel();
+  const double g = P.gamma;
+  T r[2], un[2], vt[2][3], p[2], c[2];
+  for (int a = 0; a < 2; ++a) {
+    const T* u = a == 0 ? uL : uR;
+    r[a] = u[0];
+    un[a] = T(0);
+    for (int d = 0; d < nvel; ++d) un[a] += u[1 + d] / u[0] * T(n[d]);
+    for (int d = 0; d < 3; ++d) vt[a][d] = d < nvel ? u[1 + d] / u[0] - un[a] * T(n[d]) : T(0);
+    p[a] = pressure(P, u);
+    c[a] = dsqrt(T(g) * p[a] / r[a]);
+  }
+  const T du = un[1] - un[0];
+  if (!(T(2.0 / (g - 1.0)) * (c[0] + c[1]) > du)) return false;
+  const double z = (g - 1.0) / (2.0 * g);
+  T ps = dpow((c[0] + c[1] - T(0.5 * (g - 1.0)) * du) /
+                  (c[0] / dpow(p[0], z) + c[1] / dpow(p[1], z)),
+              1.0 / z);
+  T fL, dfL, fR, dfR;
+  for (int it = 0; it < 100; ++it) {
+    wave_relation(ps, r[0], p[0], c[0], g, fL, dfL);
+    wave_relation(ps, r[1], p[1], c[1], g, fR, dfR);
+    T pn = ps - (fL + fR + du) / (dfL + dfR);
+    if (!(pn > T(0))) pn = T(0.5) * ps;
+    const bool done = dabs(pn - ps) <= T(1e-15) * (pn + ps);
+    ps = pn;
+    if (done) break;
+  }
+  wave_relation(ps, r[0], p[0], c[0], g, fL, dfL);
+  wave_relation(ps, r[1], p[1], c[1], g, fR, dfR);
+  const T us = T(0.5) * (un[0] + un[1]) + T(0.5) * (fR - fL);
+  if (star) {
+    star[0] = ps;
+    star[1] = us;
+  }
+  // sample the self-similar solution on the face, x/t = 0
+  const double G1 = (g + 1.0) / (2.0 * g), G2 = (g - 1.0) / (2.0 * g), G6 = (g - 1.0) / (g + 1.0);
+  const int a = us >= T(0) ? 0 : 1;    // side of the contact the face is on
+  const T sg = a == 0 ? T(1) : T(-1);  // mirror the right side onto the left
+  const T ua = sg * un[a], ra = r[a], pa = p[a], ca = c[a], usa = sg * us;
+  T rho, u, pr;
+  if (ps > pa) {
+    const T S = ua - ca * dsqrt(T(G1) * ps / pa + T(G2));  // shock speed
+    if (S >= T(0)) {
+      rho = ra; u = ua; pr = pa;
+    } else {
+      rho = ra * (ps / pa + T(G6)) / (T(G6) * ps / pa + T(1)); u = usa; pr = ps;
+    }
+  } else {
+    const T head = ua - ca;
+    const T tail = usa - ca * dpow(ps / pa, z);
+    if (head >= T(0)) {
+      rho = ra; u = ua; pr = pa;
+    } else if (tail < T(0)) {
+      rho = ra * dpow(ps / pa, 1.0 / g); u = usa; pr = ps;
+    } else {  // inside the rarefaction fan: u = c there
+      const T cf = T(2.0 / (g + 1.0)) * (ca + T(0.5 * (g - 1.0)) * ua);
+      u = cf;
+      rho = ra * dpow(cf / ca, 2.0 / (g - 1.0));
+      pr = pa * dpow(cf / ca, 2.0 * g / (g - 1.0));
+    }
+  }
+  u = sg * u;
+  if (face_state) {
+    face_state[0] = rho;
+    face_state[1] = u;
+    face_state[2] = pr;
+  }
+  T v[3], v2 = u * u;
+  for (int d = 0; d < 3; ++d) {
+    v[d] = u * T(n[d]) + vt[a][d];
+    v2 += vt[a][d] * vt[a][d];
+  }
+  const T E = pr / T(g - 1.0) + T(0.5) * rho * v2;
+  F[0] = rho * u;
+  for (int d = 0; d < nvel; ++d) F[1 + d] = rho * v[d] * u + pr * T(n[d]);
+  F[1 + nvel] = (E + pr) * u;
+  return true;
 }
 
 // ------------------------------------------------------ cell polynomials --
@@ -845,7 +960,9 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.
       if (!physical(P, uL) || !physical(P, uR)) ok = false;
       if (P.mhd)
         hlld(P, uL, uR, fg.n, F);
-      else
+      else if (P.riemann == 1) {
+        if (!exact_riemann(P, uL, uR, fg.n, F)) ok = false;
+      } else
         hll(P, uL, uR, fg.n, F);
       const double* r = sides[m] == 0 ? rL : rR;
       T sg = sides[m] == 0 ? T(-fg.wg[p]) : T(fg.wg[p]);
@@ -1166,8 +1283,8 @@ int or_ncoef(int dim, int mhd) {
 }
 
 // L(U).  Returns 0, or 5 when a non-physical state was met.
-int or_rhs(void* h, int mhd, double gamma, const double* U, double* dUdt) {
-  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma}, 0};
+int or_rhs(void* h, int mhd, int riemann, double gamma, const double* U, double* dUdt) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma, riemann}, 0};
   return rhs_all(C, U, dUdt) ? 5 : 0;
 }
 
@@ -1176,19 +1293,21 @@ void or_limit(void* h, int mhd, const double* U, double* Ul) {
   limit_all(C, U, Ul);
 }
 
-int or_step(void* h, int mhd, int limiter, double gamma, const double* U, double dt, double* Un) {
-  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma}, limiter};
+int or_step(void* h, int mhd, int riemann, int limiter, double gamma, const double* U, double dt,
+            double* Un) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma, riemann}, limiter};
   return step_all(C, U, dt, Un) ? 5 : 0;
 }
 
 // MUSCL-Hancock step and operator (Euler only; 5 = non-physical, 4 = MHD).
-int or_step_mh(void* h, int limiter, double gamma, const double* U, double dt, double* Un) {
-  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma}, limiter};
+int or_step_mh(void* h, int riemann, int limiter, double gamma, const double* U, double dt,
+               double* Un) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma, riemann}, limiter};
   return step_mh_all(C, U, dt, Un) ? 5 : 0;
 }
 
-int or_rhs_mh(void* h, double gamma, const double* U, double half_dt, double* L) {
-  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma}, 0};
+int or_rhs_mh(void* h, int riemann, double gamma, const double* U, double half_dt, double* L) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma, riemann}, 0};
   if (!(half_dt >= 0)) return 1;
   return rhs_all(C, U, L, half_dt) ? 5 : 0;
 }
@@ -1259,6 +1378,14 @@ void or_hll(int dim, int mhd, double gamma, const double* uL, const double* uR, 
 void or_hlld(double gamma, const double* uL, const double* uR, const double* n, double* F) {
   Phys P{3, 1, gamma};
   hlld(P, uL, uR, n, F);
+}
+// Exact Euler Riemann solver on single states: flux F, star = (p*, u*) and
+// the primitive state (rho, u_n, p) on the face.  Returns 0, or 1 on vacuum
+// generation.
+int or_exact_riemann(int dim, double gamma, const double* uL, const double* uR, const double* n,
+                     double* F, double* star, double* face_state) {
+  Phys P{dim, 0, gamma, 1};
+  return exact_riemann(P, uL, uR, n, F, star, face_state) ? 0 : 1;
 }
 
 // Mesh geometry as the oracle sees it (for pins): volume, centroid, second
