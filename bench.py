@@ -73,6 +73,9 @@ def parse():
     p.add_argument("--integrator", choices=["rk2", "mh"], default="rk2",
                    help="c1/c2: SSP-RK2 (default, two stage kernels per step) or the paper's "
                         "MUSCL-Hancock step (one kernel per step)")
+    p.add_argument("--flux", choices=["hll", "exact"], default="hll",
+                   help="c2: the Euler face flux, HLL (default) or the exact Riemann solver "
+                        "(the paper's Euler flux)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 5 device copies of 1 GiB (the reference kernel that scales "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counts to bytes) and exit")
@@ -85,6 +88,8 @@ def parse():
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
+    if a.flux == "exact" and a.config == "c2" and not a.cpu_steps:
+        a.cpu_steps = 10  # the oracle's exact solver: ~1.3 s per 2048^2 step on 16 threads
     a.cpu_steps = a.cpu_steps or dflt[3]
     return a
 
@@ -109,11 +114,11 @@ def pmc_traffic(profile: str, kernel: str, shape: str, source: str):
     return traffic
 
 
-def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3):
+def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3, flux=None):
     import torch
 
     from paper_1305_5536_amd.solver import Solver
-    s = Solver(mesh, physics=physics, precision=precision, limiter=True, gamma=gamma)
+    s = Solver(mesh, physics=physics, precision=precision, limiter=True, gamma=gamma, flux=flux)
     U = s.to_device(U0)
     V1 = s.empty()
     Un = s.empty()
@@ -145,13 +150,14 @@ def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3):
     return {"wall_s": wall, "event_s": tev, "stage1_s": t1, "stage2_s": t2, "dt_last": final_dt}
 
 
-def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3):
+def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3, flux="hll"):
     """MUSCL-Hancock steps (one kernel each, with the fused CFL minima and the
     dt reduction), HIP events around every launch pair."""
     import torch
 
     from paper_1305_5536_amd.solver import Solver
-    s = Solver(mesh, physics="euler", precision=precision, limiter=limiter, gamma=gamma)
+    s = Solver(mesh, physics="euler", precision=precision, limiter=limiter, gamma=gamma,
+               flux=flux)
     U = s.to_device(U0)
     Un = s.empty()
     dt = s.cfl_dt(U, cfl)
@@ -176,14 +182,14 @@ def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3)
     return {"wall_s": wall, "event_s": tev, "step_s": tev / steps}
 
 
-def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label=""):
+def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label="", flux="hll"):
     import oracle
     om = oracle.Mesh.cartesian((n,) * dim, (0.0,) * dim, (1.0,) * dim)
     dt = oracle.cfl_dt(om, U0, gamma, 0.3, mhd=mhd)
     t0 = time.perf_counter()
     U = U0
     for _ in range(nsteps):
-        U = oracle.step(om, U, dt, gamma, True, mhd=mhd)
+        U = oracle.step(om, U, dt, gamma, True, mhd=mhd, flux=flux)
     el = time.perf_counter() - t0
     return {"value": n ** dim * 2 * nsteps / el, "unit": "cell-updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
@@ -199,7 +205,8 @@ def bench_mh(a, U0, mesh, ncells, gamma, limiter, workload, oracle_mesh):
     """The MUSCL-Hancock variant of a 2D Cartesian config: one kernel per step;
     the metric counts cells x flux passes (one per step)."""
     elem = 8 if a.precision == "fp64" else 4
-    r = run_gpu_mh(U0, mesh, gamma, a.precision, a.steps, a.warmup, limiter=limiter)
+    r = run_gpu_mh(U0, mesh, gamma, a.precision, a.steps, a.warmup, limiter=limiter,
+                   flux=a.flux)
     per_launch = 24 * elem * ncells  # reads U, writes U_next
     achieved = per_launch / r["step_s"] / 1e9
     out = {
@@ -217,7 +224,8 @@ def bench_mh(a, U0, mesh, ncells, gamma, limiter, workload, oracle_mesh):
         "wall_s": r["wall_s"],
     }
     if a.also_fp32 and a.precision == "fp64":
-        r32 = run_gpu_mh(U0, mesh, gamma, "fp32", a.steps, a.warmup, limiter=limiter)
+        r32 = run_gpu_mh(U0, mesh, gamma, "fp32", a.steps, a.warmup, limiter=limiter,
+                         flux=a.flux)
         out["fp32"] = {"value": ncells * a.steps / r32["event_s"],
                        "ms_per_step": r32["step_s"] * 1e3,
                        "GBs": 24 * 4 * ncells / r32["step_s"] / 1e9}
@@ -229,7 +237,7 @@ def bench_mh(a, U0, mesh, ncells, gamma, limiter, workload, oracle_mesh):
         t1 = time.perf_counter()
         Uc = U0
         for _ in range(a.cpu_steps):
-            Uc = oracle.step_mh(om, Uc, dt, gamma, limiter)
+            Uc = oracle.step_mh(om, Uc, dt, gamma, limiter, flux=a.flux)
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": ncells * a.cpu_steps / el, "unit": "cell-updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
@@ -244,15 +252,16 @@ def bench_c2(a):
     n = a.n
     log(f"generating the {n}x{n} shear-layer state")
     U0 = W.c2_state(n)
+    flux = "HLL" if a.flux == "hll" else "exact Riemann solver"
     if a.integrator == "mh":
         return bench_mh(a, U0, cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), n * n, 5.0 / 3.0, True,
                         f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, P1 Taylor "
-                        "DG, HLL, limiter on, CFL 0.3",
+                        f"DG, {flux}, limiter on, CFL 0.3",
                         ((n, n), (0.0, 0.0), (1.0, 1.0)))
     log("timing the GPU steps")
     elem = 8 if a.precision == "fp64" else 4
     mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
-    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup)
+    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup, flux=a.flux)
     ncells = n * n
     value = ncells * 2 * a.steps / r["event_s"]
     stage2_bytes = STAGE_VALUES[2] * elem * ncells
@@ -263,13 +272,14 @@ def bench_c2(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
-                               "P1 Taylor DG, HLL, limiter on, SSP-RK2 CFL 0.3",
+                               f"P1 Taylor DG, {flux}, limiter on, SSP-RK2 CFL 0.3",
                    "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, true>",
                                              "2048x2048", "paper_1305_5536_amd/csrc/cart2d.hip")
-                                 if n == 2048 and a.precision == "fp64" else None),
+                                 if n == 2048 and a.precision == "fp64" and a.flux == "hll"
+                                 else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
                      "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
         "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
@@ -277,14 +287,15 @@ def bench_c2(a):
         "wall_s": r["wall_s"],
     }
     if a.also_fp32 and a.precision == "fp64":
-        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup)
+        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup, flux=a.flux)
         out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
                        "ms_per_step": r32["event_s"] / a.steps * 1e3,
                        "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
                        "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / r32["stage1_s"] / 1e9}
     if not a.no_cpu:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state")
+        out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state",
+                                           flux=a.flux)
     return out
 
 

@@ -74,11 +74,14 @@ typedef enum {
 
 typedef enum { DG_EULER = 0, DG_MHD = 1 } dg_physics;
 typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
-typedef enum { DG_FLUX_HLL = 0, DG_FLUX_HLLD = 1 } dg_flux;
+typedef enum { DG_FLUX_HLL = 0, DG_FLUX_HLLD = 1, DG_FLUX_EXACT = 2 } dg_flux;
 typedef enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1 } dg_limiter;
 
-/* Physics and numerics of a mesh.  Euler needs DG_FLUX_HLL; MHD needs
- * DG_FLUX_HLLD and a 2D or 3D Cartesian mesh (kind 0).  gamma is the adiabatic index of
+/* Physics and numerics of a mesh.  Euler takes DG_FLUX_HLL (HLL with Davis
+ * wave speeds) on every mesh kind, or DG_FLUX_EXACT (the exact Riemann solver
+ * of the Euler equations, the paper's Euler flux, Sec. 2.3) on a single 2D
+ * Cartesian mesh (kind 0; not with dg_adjoint_step).  MHD needs DG_FLUX_HLLD
+ * and a 2D or 3D Cartesian mesh (kind 0).  gamma is the adiabatic index of
  * p_gas = (gamma - 1) rho u (Sec. 2.1). */
 typedef struct {
   int physics;    /* dg_physics */

@@ -98,7 +98,7 @@ __device__ __forceinline__ LimInfo<T> lim_info(const T* nb, T gx, T gy, T hx2, T
   r.xaxis = ax >= ay;
   r.dm = r.xaxis ? ax : ay;
   r.active = r.dm > r.D;
-  r.alpha = r.active ? r.D * rcp(r.dm) : T(1);
+  r.alpha = r.active ? div_small(r.D, r.dm) : T(1);
   return r;
 }
 
@@ -556,9 +556,8 @@ __device__ __forceinline__ void adj_row_body(const PA<T>& p) {
           if (fl & 1u) {
             const T la = gx * lgx + gy * lgy;
             const T dm = (fl & 4u) ? fabs(gx) * hx2 : fabs(gy) * hy2;
-            const T idm = rcp(dm);
-            const T lD = la * idm;
-            const T ldm = -la * al * idm;
+            const T lD = div_small(la, dm);
+            const T ldm = -div_small(la * al, dm);
             if (fl & 2u) {
               pr2.lhi[v] = lD;
               om -= lD;

@@ -35,6 +35,7 @@
 
 #include "dg_internal.h"
 #include "dg_math.h"
+#include "euler_exact.h"
 
 namespace dg {
 namespace {
@@ -123,7 +124,7 @@ __device__ __forceinline__ void limit_cell(Cell<T>& c, const T* mS, const T* mN,
     T lo = fmin(fmin(fmin(phi, mW), fmin(mE, mS[v])), mN[v]);
     T D = fmin(hi - phi, phi - lo);
     T dm = fmax(fabs(c.gx[v]) * p.hx2, fabs(c.gy[v]) * p.hy2);
-    T a = (dm > D) ? D * rcp(dm) : T(1);
+    T a = (dm > D) ? div_small(D, dm) : T(1);
     c.gx[v] *= a;
     c.gy[v] *= a;
   }
@@ -158,6 +159,15 @@ __device__ __forceinline__ void hll(const T* uL, const T* uR, T gamma, T* F, boo
   c = (left || right) ? T(0) : c;
 #pragma unroll
   for (int k = 0; k < 4; ++k) F[k] = fma(a, FL[k], fma(b, FR[k], c * (uR[k] - uL[k])));
+}
+
+// Face flux along axis AX: HLL (RS = 0) or the exact Riemann solver (RS = 1).
+template <typename T, int AX, int RS>
+__device__ __forceinline__ void riemann(const T* uL, const T* uR, T gamma, T* F, bool& bad) {
+  if (RS == 1)
+    exact_flux<T, AX>(uL, uR, gamma, F, bad);
+  else
+    hll<T, AX>(uL, uR, gamma, F, bad);
 }
 
 // Both Cartesian flux rows F_x, F_y at one state (volume term).
@@ -220,7 +230,7 @@ __device__ __forceinline__ void to_cons(T* u, T igm1) {
 
 // x-face between the left neighbour L (lane - 1) and this cell R.  Returns
 // S = F(g0) + F(g1), D = F(g1) - F(g0) per variable (g0 at y offset -qy).
-template <typename T, bool PRIM = false>
+template <typename T, bool PRIM = false, int RS = 0>
 __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
   T bl[4], br[4], tl[4], tr[4];
@@ -241,7 +251,7 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
     to_cons(uL, p.igm1);
     to_cons(uR, p.igm1);
   }
-  hll<T, 0>(uL, uR, p.gamma, F0, bad);
+  riemann<T, 0, RS>(uL, uR, p.gamma, F0, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     uL[v] = bl[v] + tl[v];
@@ -251,7 +261,7 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
     to_cons(uL, p.igm1);
     to_cons(uR, p.igm1);
   }
-  hll<T, 0>(uL, uR, p.gamma, F1, bad);
+  riemann<T, 0, RS>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     S[v] = F0[v] + F1[v];
@@ -260,7 +270,7 @@ __device__ __forceinline__ void xface(const Cell<T>& L, const Cell<T>& R, const 
 }
 
 // y-face between the lower cell L (previous row) and the upper cell R.
-template <typename T, bool PRIM = false>
+template <typename T, bool PRIM = false, int RS = 0>
 __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const P2<T>& p, T* S,
                                       T* D, bool& bad) {
   T bl[4], br[4], tl[4], tr[4];
@@ -281,7 +291,7 @@ __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const 
     to_cons(uL, p.igm1);
     to_cons(uR, p.igm1);
   }
-  hll<T, 1>(uL, uR, p.gamma, F0, bad);
+  riemann<T, 1, RS>(uL, uR, p.gamma, F0, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     uL[v] = bl[v] + tl[v];
@@ -291,7 +301,7 @@ __device__ __forceinline__ void yface(const Cell<T>& L, const Cell<T>& R, const 
     to_cons(uL, p.igm1);
     to_cons(uR, p.igm1);
   }
-  hll<T, 1>(uL, uR, p.gamma, F1, bad);
+  riemann<T, 1, RS>(uL, uR, p.gamma, F1, bad);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     S[v] = F0[v] + F1[v];
@@ -333,8 +343,9 @@ __device__ __forceinline__ double cell_dt(const T* m, const P2<T>& p) {
   return 1.0 / s;
 }
 
-// One wave's tile (tile index `wave` of the mesh described by p).
-template <typename T, int MODE, bool LIM>
+// One wave's tile (tile index `wave` of the mesh described by p).  RS selects
+// the face flux (0 HLL, 1 exact Riemann solver).
+template <typename T, int MODE, bool LIM, int RS = 0>
 __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) {
   const int tx = wave % p.tiles_x, ty = wave / p.tiles_x;
   const int colu = tx * kCols + lane - 2;
@@ -404,9 +415,9 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
       T Sy[4], Dy[4];
       if (j >= y0) {
         if (MODE == kMH)
-          yface<T, true>(prevP, curP, p, Sy, Dy, bad);
+          yface<T, true, RS>(prevP, curP, p, Sy, Dy, bad);
         else
-          yface(prev, cur, p, Sy, Dy, bad);
+          yface<T, false, RS>(prev, cur, p, Sy, Dy, bad);
       }
       if (j >= y0 + 1) {
         // Finalise row f = j - 1 (held in prev).
@@ -427,7 +438,7 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
           left.gy[v] = lane_up(ev.gy[v]);
         }
         T Sm[4], Dm[4], sx[4], sy[4];
-        xface<T, MODE == kMH>(left, ev, p, Sm, Dm, bad);
+        xface<T, MODE == kMH, RS>(left, ev, p, Sm, Dm, bad);
         volume<T, MODE == kMH>(ev, p, sx, sy, bad);
         Cell<T> o;
 #pragma unroll
@@ -487,12 +498,12 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
   }
 }
 
-template <typename T, int MODE, bool LIM>
+template <typename T, int MODE, bool LIM, int RS = 0>
 __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
   const int lane = threadIdx.x & (kLanes - 1);
   const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (wave >= p.ntiles) return;
-  cart2d_tile<T, MODE, LIM>(p, wave, lane);
+  cart2d_tile<T, MODE, LIM, RS>(p, wave, lane);
 }
 
 // ---------------------------------------------------------------- batches --
@@ -668,7 +679,7 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
   return p;
 }
 
-template <typename T>
+template <typename T, int RS>
 hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                     const double* dt_dev, double dt_host, double cfl, double* dt_next,
                     hipStream_t s) {
@@ -681,31 +692,31 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
   }
   switch (mode) {
     case kRhs:
-      hipLaunchKernelGGL((k_cart2d<T, kRhs, false>), dim3(nblocks), dim3(256), 0, s, p);
+      hipLaunchKernelGGL((k_cart2d<T, kRhs, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
       break;
     case kLimit:
       hipLaunchKernelGGL((k_cart2d<T, kLimit, true>), dim3(nblocks), dim3(256), 0, s, p);
       break;
     case kStage1:
       if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kStage1, true>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kStage1, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
       else
-        hipLaunchKernelGGL((k_cart2d<T, kStage1, false>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kStage1, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
       break;
     case kStage2:
       if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kStage2, true>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kStage2, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
       else
-        hipLaunchKernelGGL((k_cart2d<T, kStage2, false>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kStage2, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);
       break;
     case kMH:
       if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kMH, true>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kMH, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
       else
-        hipLaunchKernelGGL((k_cart2d<T, kMH, false>), dim3(nblocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((k_cart2d<T, kMH, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);
@@ -889,9 +900,12 @@ hipError_t launch_cart2d_batch_cfl(const dg_mesh* m, const void* U, double cfl, 
 hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                          const double* dt_dev, double dt_host, double cfl, double* dt_next,
                          hipStream_t s) {
+  const bool ex = m->cfg.flux == DG_FLUX_EXACT;
   if (m->cfg.precision == DG_FP64)
-    return launch_t<double>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
-  return launch_t<float>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+    return ex ? launch_t<double, 1>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s)
+              : launch_t<double, 0>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
+  return ex ? launch_t<float, 1>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s)
+            : launch_t<float, 0>(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
 }
 
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,

@@ -124,7 +124,7 @@ template <typename T>
 __device__ __forceinline__ T alpha_of(T phi, T hi, T lo, const T* g, const P3<T>& p) {
   T D = fmin(hi - phi, phi - lo);
   T dm = fmax(fmax(fabs(g[0]) * p.half[0], fabs(g[1]) * p.half[1]), fabs(g[2]) * p.half[2]);
-  return (dm > D) ? D * rcp(dm) : T(1);
+  return (dm > D) ? div_small(D, dm) : T(1);
 }
 
 // ------------------------------------------------------------- limiter --

@@ -191,8 +191,12 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma))
     return einval("dg_mesh_create: gamma must be finite and > 1");
   if (cfg->physics == DG_EULER) {
-    if (cfg->flux != DG_FLUX_HLL) {
-      set_error("dg_mesh_create: Euler supports the HLL flux only");
+    if (cfg->flux != DG_FLUX_HLL && cfg->flux != DG_FLUX_EXACT) {
+      set_error("dg_mesh_create: Euler takes the HLL or the exact Riemann flux");
+      return DG_EUNSUPPORTED;
+    }
+    if (cfg->flux == DG_FLUX_EXACT && (d->kind != 0 || d->dim != 2)) {
+      set_error("dg_mesh_create: the exact Riemann flux is built for 2D Cartesian meshes");
       return DG_EUNSUPPORTED;
     }
   } else if (cfg->physics == DG_MHD) {
@@ -499,8 +503,8 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
                           const double* dt_dev, const void* lam_np1, void* lam_n, void* stream) {
   if (!m || !U || !lam_np1 || !lam_n) return einval("dg_adjoint_step: NULL argument");
   m->ws_a_fresh = false;
-  if (!m->adj_inst) {
-    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes and batches");
+  if (!m->adj_inst || m->cfg.flux != DG_FLUX_HLL) {
+    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes and batches with HLL");
     return DG_EUNSUPPORTED;
   }
   if (!dt_dev && (!std::isfinite(dt) || dt < 0))

@@ -49,6 +49,19 @@ __device__ __forceinline__ float sqrt_pos(float x) {
   return fmaf(d, h, g);
 }
 
+// a / b for b > 0 that may be tiny, down to the denormal range (the limiter's
+// D / dm of a nearly flat cell): the reciprocal of such a b overflows, so both
+// operands are first scaled by a power of two (exactly).  For b above the
+// threshold this is a * rcp(b).
+__device__ __forceinline__ double div_small(double a, double b) {
+  const double s = b < 0x1p-900 ? 0x1p+1000 : 1.0;
+  return (a * s) * rcp(b * s);
+}
+__device__ __forceinline__ float div_small(float a, float b) {
+  const float s = b < 0x1p-100f ? 0x1p+100f : 1.0f;
+  return (a * s) * rcp(b * s);
+}
+
 // sqrt of a value that may be exactly zero.
 template <typename T>
 __device__ __forceinline__ T sqrt_nn(T x) {

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_fl_lim(PF<T> p) {
       const T d = q[3 * v + 1] * rx + q[3 * v + 2] * ry;
       // psi = (max - phi)/d for d > 0, (min - phi)/d for d < 0, 1 for d = 0
       const T num = d > T(0) ? hi[v] - q[3 * v] : lo[v] - q[3 * v];
-      const T psi = d != T(0) ? num * rcp(d) : T(1);
+      const T psi = d > T(0) ? div_small(num, d) : (d < T(0) ? div_small(-num, -d) : T(1));
       alpha[v] = fmin(alpha[v], psi);
     }
   }

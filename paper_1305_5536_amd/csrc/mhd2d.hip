@@ -138,7 +138,7 @@ template <typename T>
 __device__ __forceinline__ T alpha_of(T phi, T hi, T lo, T gx, T gy, const P2M<T>& p) {
   const T D = fmin(hi - phi, phi - lo);
   const T dm = fmax(fabs(gx) * p.half[0], fabs(gy) * p.half[1]);
-  return (dm > D) ? D * rcp(dm) : T(1);
+  return (dm > D) ? div_small(D, dm) : T(1);
 }
 
 // The limiter of Sec. 2.5 applied to a cell held by this lane, inside a row

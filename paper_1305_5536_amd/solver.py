@@ -33,7 +33,8 @@ class Solver:
     """
 
     def __init__(self, mesh: dict, physics: str = "euler", precision: str = "fp64",
-                 limiter: bool = True, gamma: float = 1.4, device: int | None = None):
+                 limiter: bool = True, gamma: float = 1.4, device: int | None = None,
+                 flux: str | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("the DG library needs a ROCm GPU; none is visible")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -42,9 +43,14 @@ class Solver:
         self.limiter = bool(limiter)
         self.gamma = float(gamma)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        # face flux: "hll" or "exact" for Euler (default "hll"), "hlld" for MHD
+        self.flux = flux or ("hlld" if physics == "mhd" else "hll")
+        fluxes = {"hll": C.DG_FLUX_HLL, "hlld": C.DG_FLUX_HLLD, "exact": C.DG_FLUX_EXACT}
+        if self.flux not in fluxes:
+            raise ValueError(f"unknown flux {self.flux!r}")
         cfg = C.dg_config(C.DG_MHD if physics == "mhd" else C.DG_EULER,
                           C.DG_FP64 if precision == "fp64" else C.DG_FP32,
-                          C.DG_FLUX_HLLD if physics == "mhd" else C.DG_FLUX_HLL,
+                          fluxes[self.flux],
                           C.DG_LIMITER_MINMOD if limiter else C.DG_LIMITER_NONE, self.gamma)
         d = C.dg_mesh_desc()
         self._keep = []

@@ -247,6 +247,31 @@ def test_stages_with_device_dt_and_fused_cfl(oracle, torch_cuda):
     assert dt.item() == dt_next.item()
 
 
+def test_limiter_with_denormal_slopes(oracle, torch_cuda):
+    """Nearly flat cells: slopes and mean differences in the denormal range.
+    The limiter's D/dm stays finite and equals the oracle's (IEEE division)."""
+    n, lo, hi = (16, 8), (0.0, 0.0), (1.0, 1.0)
+    U = np.zeros((12, 128))
+    U[0], U[9] = 1.0, 2.5
+    rng = np.random.default_rng(8)
+    for k in (1, 2, 4, 5, 7, 8, 10, 11):
+        U[k] = rng.choice([0.0, 3e-310, -2e-312, 1e-300, 5e-320], 128)
+    U[0] += rng.choice([0.0, 1e-16, 2.2e-16], 128)
+    # a strictly rising x-momentum of denormal size: D / dm is a ratio of two
+    # denormals (about 0.1)
+    U[3] = np.tile(np.arange(16), 8) * 1e-312
+    U[4] = 3e-310
+    U0 = U.reshape(-1)
+    s = _solver(n, lo, hi, G14)
+    got = s.limit(s.to_device(U0)).cpu().numpy()
+    ref = oracle.limit(oracle.Mesh.cartesian(n, lo, hi), U0)
+    assert np.all(np.isfinite(got))
+    # element-wise, with an absolute floor of a few thousand denormal ulps
+    assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref) + 1e-320)
+    assert np.all(np.isfinite(s.step(s.to_device(U0), 1e-3).cpu().numpy()))
+    s.check()
+
+
 def test_results_do_not_depend_on_tiling(torch_cuda):
     """Every cell and face uses the same arithmetic whatever the rows per wave:
     outputs are bitwise identical across tilings (including ragged tiles)."""

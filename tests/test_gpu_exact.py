@@ -1,0 +1,146 @@
+"""GPU 2D Euler with the exact Riemann solver (the paper's Euler flux, Sec. 2.3)
+against the oracle's exact solver, through the C ABI:
+
+* single RHS / step / MUSCL-Hancock calls on ragged meshes, limiter on and off;
+* 100 FP64 steps on the oracle's schedule at 1e-11 per field: the C2 shear
+  recipe at 128^2 and the paper's Sod tube (Sec. 3.2) along x and along y
+  (two interfaces on a periodic [-1, 1]); the FP32 error is stated;
+* the combinations that are not built (batches, face lists, the adjoint).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G14 = 1.4
+G53 = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(n, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=G53, limiter=True, precision="fp64"):
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    return Solver(cartesian(n, lo, hi), precision=precision, limiter=limiter, gamma=gamma,
+                  flux="exact")
+
+
+def field_errors(A, B, h, floor=None):
+    A = A.reshape(12, -1)
+    B = B.reshape(12, -1)
+    if floor is None:
+        floor = np.abs(B[0]).max()
+    out = []
+    for v in range(4):
+        k = 3 * v
+        d = max(np.abs(A[k] - B[k]).max(), h * np.abs(A[k + 1:k + 3] - B[k + 1:k + 3]).max())
+        out.append(d / max(np.abs(B[k]).max(), floor))
+    return np.array(out)
+
+
+def _state(n, seed, amp=0.3):
+    U = W.random_p1_state(n, (0.0, 0.0), (1.0, 1.0), G53, seed=seed, amp=amp).reshape(12, -1)
+    U = U.copy()
+    U[1::3] *= 2.0
+    U[2::3] *= 2.0
+    return U.reshape(-1)
+
+
+@pytest.mark.parametrize("n", [(100, 70), (61, 9), (1, 5), (3, 1), (130, 4), (64, 64)])
+def test_rhs_step_mh_match_oracle(oracle, torch_cuda, n):
+    U0 = _state(n, seed=90 + n[0] + 3 * n[1])
+    om = oracle.Mesh.cartesian(n, (0.0, 0.0), (1.0, 1.0))
+    h = min(1.0 / n[0], 1.0 / n[1])
+    s = _solver(n)
+    u = s.to_device(U0)
+    ref = oracle.rhs(om, U0, G53, flux="exact")
+    floor = np.abs(ref.reshape(12, -1)[0::3]).max()
+    e = field_errors(s.rhs(u).cpu().numpy(), ref, h, floor)
+    assert e.max() < 1e-12, ("rhs", e)
+    dt = oracle.cfl_dt(om, U0, G53, 0.3)
+    for limiter in (False, True):
+        sl = _solver(n, limiter=limiter)
+        ul = sl.to_device(U0)
+        ref = oracle.step(om, U0, dt, G53, limiter, flux="exact")
+        e = field_errors(sl.step(ul, dt).cpu().numpy(), ref, h)
+        assert e.max() < 1e-13, ("step", limiter, e)
+        ref = oracle.step_mh(om, U0, dt, G53, limiter, flux="exact")
+        e = field_errors(sl.step_mh(ul, dt).cpu().numpy(), ref, h)
+        assert e.max() < 1e-13, ("mh", limiter, e)
+        sl.check()
+
+
+def _run(s, U0, dts, mh=False):
+    U = s.to_device(U0)
+    V = s.empty()
+    for dt in dts:
+        if mh:
+            s.step_mh(U, dt, out=V)
+        else:
+            s.step(U, dt, out=V)
+        U, V = V, U
+    s.check()
+    return U.double().cpu().numpy()
+
+
+def test_shear_100_steps(oracle, torch_cuda):
+    """C2 recipe at 128^2 with the exact flux, limiter on."""
+    n = (128, 128)
+    U0 = W.c2_state(128)
+    om = oracle.Mesh.cartesian(n, (0.0, 0.0), (1.0, 1.0))
+    ref, dts = oracle.run(om, U0, 100, G53, 0.3, True, flux="exact")
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-3)):
+        e = field_errors(_run(_solver(n, precision=prec), U0, dts), ref, 1.0 / 128)
+        print(f"exact flux, shear 128^2 {prec}, 100 steps, per-field error: {e}")
+        assert e.max() < tol, (prec, e)
+
+
+def sod_state(n, axis):
+    """The paper's Sod tube (Sec. 3.2) on a periodic [-1, 1]: left state
+    (rho, p) = (1, 1) for |x| < 1/2, right state (0.25, 0.1795), at rest,
+    along x (axis 0, an n x 1 mesh) or y (axis 1, 1 x n)."""
+    h = 2.0 / n
+    x = -1.0 + h * (np.arange(n) + 0.5)
+    inside = np.abs(x) < 0.5
+    U = np.zeros((12, n))
+    U[0] = np.where(inside, 1.0, 0.25)
+    U[9] = np.where(inside, 1.0, 0.1795) / (G14 - 1.0)
+    shape = (n, 1) if axis == 0 else (1, n)
+    lo = (-1.0, 0.0) if axis == 0 else (0.0, -1.0)
+    hi = (1.0, h) if axis == 0 else (h, 1.0)
+    return U.reshape(-1), shape, lo, hi
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("mh", [False, True])
+def test_sod_100_steps(oracle, torch_cuda, axis, mh):
+    U0, shape, lo, hi = sod_state(256, axis)
+    om = oracle.Mesh.cartesian(shape, lo, hi)
+    ref, dts = oracle.run(om, U0, 100, G14, 0.3, True, flux="exact",
+                          integrator="mh" if mh else "rk2")
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4)):
+        s = _solver(shape, lo, hi, G14, precision=prec)
+        e = field_errors(_run(s, U0, dts, mh), ref, 2.0 / 256)
+        print(f"exact flux, Sod axis {axis} {'MH' if mh else 'RK2'} {prec}, 100 steps: {e}")
+        assert e.max() < tol, (prec, e)
+
+
+def test_unsupported_combinations(torch_cuda):
+    from paper_1305_5536_amd.capi import DGError
+    from paper_1305_5536_amd.solver import Solver, batch
+    from workloads.voronoi import periodic_voronoi
+    with pytest.raises(DGError):
+        Solver(batch([(8, 8), (4, 4)]), gamma=G53, flux="exact")
+    with pytest.raises(DGError):
+        Solver(periodic_voronoi(100, seed=1), gamma=G53, flux="exact")
+    s = _solver((8, 8))
+    U = s.to_device(_state((8, 8), seed=3))
+    with pytest.raises(DGError):
+        s.adjoint_step(U, 1e-3, s.to_device(np.ones(U.numel())))

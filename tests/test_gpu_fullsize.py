@@ -1,6 +1,7 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
 (library-default tiling, device step sizes, fused CFL minima, batched graph).
 
+* C2 2048^2 with the exact Riemann flux: one FP64 step, every cell.
 * C2 2048^2 (SSP-RK2 and MUSCL-Hancock) and C4 (10^6 Voronoi cells): two
   FP64 steps on the oracle's own step schedule, every cell compared (the
   oracle finishes a step in about a second on the host's cores); the FP32
@@ -77,6 +78,24 @@ def test_c2_full_size(oracle, torch_cuda):
         got = _run_gpu(s, U0, dts).double().cpu().numpy()
         e = errs_hydro(got, ref, 4, 2, 1.0 / n, 12)
         print(f"C2 2048^2 {prec}, 2 steps, per-field error: {e}")
+        assert e.max() < tol, (prec, e)
+        s.close()
+
+
+def test_c2_full_size_exact_flux(oracle, torch_cuda):
+    """The C2 recipe with the exact Riemann solver (the paper's Euler flux):
+    one step on the oracle's schedule, every cell."""
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    n = 2048
+    U0 = W.c2_state(n)
+    om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    ref, dts = oracle.run(om, U0, 1, G53, 0.3, True, flux="exact")
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        s = Solver(cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), precision=prec, gamma=G53,
+                   flux="exact")
+        got = _run_gpu(s, U0, dts).double().cpu().numpy()
+        e = errs_hydro(got, ref, 4, 2, 1.0 / n, 12)
+        print(f"C2 2048^2 exact flux {prec}, 1 step, per-field error: {e}")
         assert e.max() < tol, (prec, e)
         s.close()
 

@@ -96,6 +96,31 @@ def test_mh_shear_100_steps_small(oracle, torch_cuda):
         assert e.max() < tol, (prec, e)
 
 
+def test_mh_sod_100_steps(oracle, torch_cuda):
+    """The paper's Sod tube (Sec. 3.2) along x on a periodic [-1, 1] (left
+    state for |x| < 1/2), HLL, limiter on: 100 steps on the oracle's schedule.
+    Ahead of the rarefactions the slopes decay into the denormal range, where
+    the limiter's ratio D/dm must stay finite."""
+    n = 256
+    h = 2.0 / n
+    x = -1.0 + h * (np.arange(n) + 0.5)
+    U = np.zeros((12, n))
+    U[0] = np.where(np.abs(x) < 0.5, 1.0, 0.25)
+    U[9] = np.where(np.abs(x) < 0.5, 1.0, 0.1795) / (G14 - 1.0)
+    U0 = U.reshape(-1)
+    om = oracle.Mesh.cartesian((n, 1), (-1.0, 0.0), (1.0, h))
+    ref, dts = oracle.run(om, U0, 100, G14, 0.3, True, integrator="mh")
+    s = _solver((n, 1), (-1.0, 0.0), (1.0, h), G14)
+    Ug = s.to_device(U0)
+    V = s.empty()
+    for dt in dts:
+        s.step_mh(Ug, dt, out=V)
+        Ug, V = V, Ug
+    s.check()
+    e = field_errors(Ug.cpu().numpy(), ref, h)
+    assert e.max() < 1e-11, e
+
+
 def test_mh_fused_cfl_and_graph_run(torch_cuda):
     torch = torch_cuda
     n, lo, hi = (96, 80), (0.0, 0.0), (1.0, 1.0)
