@@ -57,7 +57,8 @@ def lib():
         L.or_rhs.restype = ctypes.c_int
         L.or_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
                              _dp]
-        L.or_limit.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+        L.or_limit.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
+                               _dp]
         L.or_step.restype = ctypes.c_int
         L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               ctypes.c_double, _dp, ctypes.c_double, _dp]
@@ -196,11 +197,16 @@ def rhs(mesh: Mesh, U, gamma: float, mhd: bool = False, check: bool = True,
     return out
 
 
-def limit(mesh: Mesh, U, mhd: bool = False) -> np.ndarray:
-    """Slope limiter Pi(U) (means unchanged, gradients scaled by alpha)."""
+_LIMITER = {False: 0, True: 1, "arepo": 1, "weno": 2}
+
+
+def limit(mesh: Mesh, U, mhd: bool = False, kind: str = "arepo",
+          gamma: float = 1.4) -> np.ndarray:
+    """Slope limiter Pi(U), means unchanged: "arepo" scales the gradients by
+    alpha; "weno" (Euler) blends the stencil and DG primitive slopes."""
     U = _state(mesh, U, mhd)
     out = np.empty_like(U)
-    lib().or_limit(mesh._h, int(mhd), _p(U), _p(out))
+    lib().or_limit(mesh._h, int(mhd), _LIMITER[kind], gamma, _p(U), _p(out))
     return out
 
 
@@ -209,7 +215,7 @@ def step(mesh: Mesh, U, dt: float, gamma: float, limiter: bool, mhd: bool = Fals
     """One SSP-RK2 step with the limiter at the start of each stage."""
     U = _state(mesh, U, mhd)
     out = np.empty_like(U)
-    rc = lib().or_step(mesh._h, int(mhd), _RIEMANN[flux], int(limiter), gamma, _p(U), dt,
+    rc = lib().or_step(mesh._h, int(mhd), _RIEMANN[flux], _LIMITER[limiter], gamma, _p(U), dt,
                        _p(out))
     if rc and check:
         raise NonPhysical("non-physical state in step")
@@ -250,7 +256,7 @@ def step_mh(mesh: Mesh, U, dt: float, gamma: float, limiter: bool,
     """One MUSCL-Hancock step (Euler): Ua = Pi(U), U' = Ua + dt L_MH(Ua; dt/2)."""
     U = _state(mesh, U, False)
     out = np.empty_like(U)
-    if lib().or_step_mh(mesh._h, _RIEMANN[flux], int(limiter), gamma, _p(U), dt, _p(out)):
+    if lib().or_step_mh(mesh._h, _RIEMANN[flux], _LIMITER[limiter], gamma, _p(U), dt, _p(out)):
         raise NonPhysical("non-physical state in the MUSCL-Hancock step")
     return out
 

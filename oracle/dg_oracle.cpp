@@ -1104,6 +1104,111 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
   store_poly(P, Ul, nc, e, q);
 }
 
+// The WENO-type limiter of Sec. 2.5 on one cell (Euler).  For each primitive
+// variable phi (rho, v, p) there are two candidate gradients: the stencil
+// gradient, a least-squares fit to the face neighbours' primitive means (the
+// FV method's slope), limited as in the Arepo limiter; and the cell's own
+// unlimited DG gradient, the primitive gradient at the centroid from the
+// conserved mean and gradients by the chain rule.  Each candidate k gets the
+// oscillation factor
+//   o_k = sum over faces j of |dphi_kj| + |phi_j - (phi_i + dphi_kj)|,
+// with dphi_kj = grad_k . (face centroid - cell centroid) and phi_j the
+// neighbour's primitive mean; the new gradient is the average of the
+// candidates weighted by (eps + o_k)^(-1/2), eps the FP64 machine epsilon.
+// The conserved gradients are then recomputed from the primitive ones at the
+// centroid (chain rule); the means are unchanged.
+template <class T> void limit_cell_weno(const Ctx& C, const T* U, T* Ul, int64_t e) {
+  const Mesh& M = *C.mesh;
+  const Phys& P = C.P;
+  const int dim = P.dim, nh = P.nhyd();
+  const int64_t nc = M.nc;
+  Poly<T> q;
+  load_poly(P, U, nc, e, q);
+  Prim<T> pr;
+  predict_prim(P, q, 0.0, pr);  // centroid values and DG primitive gradients
+  int64_t fids[64];
+  int sides[64];
+  const int nfc = M.cell_faces(e, fids, sides);
+  T wn[64][5];
+  double rf[64][3], dn[64][3];
+  for (int m = 0; m < nfc; ++m) {
+    FaceGeo fg;
+    M.face(fids[m], fg);
+    const int64_t nb = sides[m] == 0 ? fg.R : fg.L;
+    Poly<T> qn;
+    load_poly(P, U, nc, nb, qn);
+    Prim<T> pn;
+    predict_prim(P, qn, 0.0, pn);
+    for (int k = 0; k < nh; ++k) wn[m][k] = pn.w[k];
+    for (int d = 0; d < 3; ++d) {
+      const double off = sides[m] == 0 ? 0.0 : fg.dLR[d];
+      rf[m][d] = d < dim ? fg.rc[d] - off : 0.0;
+      // neighbour centroid relative to this cell's centroid
+      dn[m][d] = d < dim ? (sides[m] == 0 ? fg.dLR[d] : -fg.dLR[d]) : 0.0;
+    }
+  }
+  // least-squares normal matrix of the stencil
+  double A[9] = {0};
+  for (int m = 0; m < nfc; ++m)
+    for (int i = 0; i < dim; ++i)
+      for (int j = 0; j < dim; ++j) A[i * dim + j] += dn[m][i] * dn[m][j];
+  const double eps = 2.220446049250313e-16;
+  T gnew[5][3];
+  for (int k = 0; k < nh; ++k) {
+    // stencil candidate
+    T b[3] = {T(0), T(0), T(0)}, gs[3] = {T(0), T(0), T(0)};
+    for (int m = 0; m < nfc; ++m)
+      for (int i = 0; i < dim; ++i) b[i] += T(dn[m][i]) * (wn[m][k] - pr.w[k]);
+    solve_small(dim, A, b, gs);
+    T hi = pr.w[k], lo = pr.w[k];
+    for (int m = 0; m < nfc; ++m) {
+      hi = dmax(hi, wn[m][k]);
+      lo = dmin(lo, wn[m][k]);
+    }
+    T alpha = T(1);
+    for (int m = 0; m < nfc; ++m) {
+      T dphi = T(0);
+      for (int d = 0; d < dim; ++d) dphi += gs[d] * T(rf[m][d]);
+      T psi = T(1);
+      if (dphi > T(0))
+        psi = (hi - pr.w[k]) / dphi;
+      else if (dphi < T(0))
+        psi = (lo - pr.w[k]) / dphi;
+      alpha = dmin(alpha, psi);
+    }
+    for (int d = 0; d < dim; ++d) gs[d] = alpha * gs[d];
+    // oscillation factors and weights
+    const T* cand[2] = {gs, pr.gw[k]};
+    T wsum = T(0), acc[3] = {T(0), T(0), T(0)};
+    for (int c = 0; c < 2; ++c) {
+      T o = T(0);
+      for (int m = 0; m < nfc; ++m) {
+        T dphi = T(0);
+        for (int d = 0; d < dim; ++d) dphi += cand[c][d] * T(rf[m][d]);
+        o += dabs(dphi) + dabs(wn[m][k] - (pr.w[k] + dphi));
+      }
+      const T w = T(1) / dsqrt(T(eps) + o);
+      wsum += w;
+      for (int d = 0; d < dim; ++d) acc[d] += w * cand[c][d];
+    }
+    for (int d = 0; d < dim; ++d) gnew[k][d] = acc[d] / wsum;
+  }
+  // conserved gradients from the primitive ones at the centroid
+  const T rho = pr.w[0];
+  T v2 = T(0);
+  for (int i = 0; i < dim; ++i) v2 += pr.w[1 + i] * pr.w[1 + i];
+  for (int d = 0; d < dim; ++d) {
+    q.g[0][d] = gnew[0][d];
+    T vgv = T(0);
+    for (int i = 0; i < dim; ++i) {
+      q.g[1 + i][d] = pr.w[1 + i] * gnew[0][d] + rho * gnew[1 + i][d];
+      vgv += pr.w[1 + i] * gnew[1 + i][d];
+    }
+    q.g[1 + dim][d] = gnew[1 + dim][d] / T(P.gamma - 1.0) + T(0.5) * v2 * gnew[0][d] + rho * vgv;
+  }
+  store_poly(P, Ul, nc, e, q);
+}
+
 template <class T> int rhs_all(const Ctx& C, const T* U, T* dUdt, double half_dt = -1.0) {
   int64_t nc = C.mesh->nc;
   int bad = 0;
@@ -1116,7 +1221,12 @@ template <class T> int rhs_all(const Ctx& C, const T* U, T* dUdt, double half_dt
 template <class T> void limit_all(const Ctx& C, const T* U, T* Ul) {
   int64_t nc = C.mesh->nc;
 #pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < nc; ++e) limit_cell(C, U, Ul, e);
+  for (int64_t e = 0; e < nc; ++e) {
+    if (C.limiter == 2)
+      limit_cell_weno(C, U, Ul, e);
+    else
+      limit_cell(C, U, Ul, e);
+  }
 }
 
 // One SSP-RK2 step with the limiter at the start of each stage:
@@ -1288,8 +1398,10 @@ int or_rhs(void* h, int mhd, int riemann, double gamma, const double* U, double*
   return rhs_all(C, U, dUdt) ? 5 : 0;
 }
 
-void or_limit(void* h, int mhd, const double* U, double* Ul) {
-  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, 1.4}, 1};
+// kind: 1 the Arepo limiter, 2 the WENO-type limiter (Euler; gamma is used
+// for the primitive variables).
+void or_limit(void* h, int mhd, int kind, double gamma, const double* U, double* Ul) {
+  Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, mhd, gamma}, kind};
   limit_all(C, U, Ul);
 }
 
