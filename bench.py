@@ -76,6 +76,9 @@ def parse():
     p.add_argument("--flux", choices=["hll", "exact"], default="hll",
                    help="c2: the Euler face flux, HLL (default) or the exact Riemann solver "
                         "(the paper's Euler flux)")
+    p.add_argument("--limiter", choices=["arepo", "weno"], default="arepo",
+                   help="c2: the slope limiter of Sec. 2.5, the Arepo limiter (default) or the "
+                        "WENO-type limiter")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 5 device copies of 1 GiB (the reference kernel that scales "
                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counts to bytes) and exit")
@@ -114,11 +117,13 @@ def pmc_traffic(profile: str, kernel: str, shape: str, source: str):
     return traffic
 
 
-def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3, flux=None):
+def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3, flux=None,
+            limiter=True):
     import torch
 
     from paper_1305_5536_amd.solver import Solver
-    s = Solver(mesh, physics=physics, precision=precision, limiter=True, gamma=gamma, flux=flux)
+    s = Solver(mesh, physics=physics, precision=precision, limiter=limiter, gamma=gamma,
+               flux=flux)
     U = s.to_device(U0)
     V1 = s.empty()
     Un = s.empty()
@@ -151,6 +156,7 @@ def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3, flux=No
 
 
 def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3, flux="hll"):
+    # limiter: True / "arepo" or "weno"
     """MUSCL-Hancock steps (one kernel each, with the fused CFL minima and the
     dt reduction), HIP events around every launch pair."""
     import torch
@@ -182,14 +188,15 @@ def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3,
     return {"wall_s": wall, "event_s": tev, "step_s": tev / steps}
 
 
-def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label="", flux="hll"):
+def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label="", flux="hll",
+                 limiter=True):
     import oracle
     om = oracle.Mesh.cartesian((n,) * dim, (0.0,) * dim, (1.0,) * dim)
     dt = oracle.cfl_dt(om, U0, gamma, 0.3, mhd=mhd)
     t0 = time.perf_counter()
     U = U0
     for _ in range(nsteps):
-        U = oracle.step(om, U, dt, gamma, True, mhd=mhd, flux=flux)
+        U = oracle.step(om, U, dt, gamma, limiter, mhd=mhd, flux=flux)
     el = time.perf_counter() - t0
     return {"value": n ** dim * 2 * nsteps / el, "unit": "cell-updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
@@ -253,15 +260,18 @@ def bench_c2(a):
     log(f"generating the {n}x{n} shear-layer state")
     U0 = W.c2_state(n)
     flux = "HLL" if a.flux == "hll" else "exact Riemann solver"
+    limiter = True if a.limiter == "arepo" else "weno"
+    limname = "limiter on" if a.limiter == "arepo" else "WENO-type limiter"
     if a.integrator == "mh":
-        return bench_mh(a, U0, cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), n * n, 5.0 / 3.0, True,
+        return bench_mh(a, U0, cartesian((n, n), (0.0, 0.0), (1.0, 1.0)), n * n, 5.0 / 3.0, limiter,
                         f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, P1 Taylor "
-                        f"DG, {flux}, limiter on, CFL 0.3",
+                        f"DG, {flux}, {limname}, CFL 0.3",
                         ((n, n), (0.0, 0.0), (1.0, 1.0)))
     log("timing the GPU steps")
     elem = 8 if a.precision == "fp64" else 4
     mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
-    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup, flux=a.flux)
+    r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup, flux=a.flux,
+                limiter=limiter)
     ncells = n * n
     value = ncells * 2 * a.steps / r["event_s"]
     stage2_bytes = STAGE_VALUES[2] * elem * ncells
@@ -272,14 +282,14 @@ def bench_c2(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
-                               f"P1 Taylor DG, {flux}, limiter on, SSP-RK2 CFL 0.3",
+                               f"P1 Taylor DG, {flux}, {limname}, SSP-RK2 CFL 0.3",
                    "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, true>",
+                     "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, 1, 0>",
                                              "2048x2048", "paper_1305_5536_amd/csrc/cart2d.hip")
                                  if n == 2048 and a.precision == "fp64" and a.flux == "hll"
-                                 else None),
+                                 and a.limiter == "arepo" else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
                      "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
         "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
@@ -287,7 +297,8 @@ def bench_c2(a):
         "wall_s": r["wall_s"],
     }
     if a.also_fp32 and a.precision == "fp64":
-        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup, flux=a.flux)
+        r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup, flux=a.flux,
+                      limiter=limiter)
         out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
                        "ms_per_step": r32["event_s"] / a.steps * 1e3,
                        "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
@@ -295,7 +306,7 @@ def bench_c2(a):
     if not a.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state",
-                                           flux=a.flux)
+                                           flux=a.flux, limiter=limiter)
     return out
 
 

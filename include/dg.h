@@ -75,7 +75,7 @@ typedef enum {
 typedef enum { DG_EULER = 0, DG_MHD = 1 } dg_physics;
 typedef enum { DG_FP64 = 0, DG_FP32 = 1 } dg_precision;
 typedef enum { DG_FLUX_HLL = 0, DG_FLUX_HLLD = 1, DG_FLUX_EXACT = 2 } dg_flux;
-typedef enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1 } dg_limiter;
+typedef enum { DG_LIMITER_NONE = 0, DG_LIMITER_MINMOD = 1, DG_LIMITER_WENO = 2 } dg_limiter;
 
 /* Physics and numerics of a mesh.  Euler takes DG_FLUX_HLL (HLL with Davis
  * wave speeds) on every mesh kind, or DG_FLUX_EXACT (the exact Riemann solver
@@ -87,7 +87,11 @@ typedef struct {
   int physics;    /* dg_physics */
   int precision;  /* dg_precision */
   int flux;       /* dg_flux */
-  int limiter;    /* dg_limiter: the slope limiter of Sec. 2.5 */
+  int limiter;    /* dg_limiter: the slope limiters of Sec. 2.5: DG_LIMITER_MINMOD is the
+                   * Arepo limiter (alpha = min(1, min_j psi_ij)) on every mesh kind;
+                   * DG_LIMITER_WENO, the WENO-type blend of the stencil and DG primitive
+                   * slopes, on single 2D Cartesian Euler meshes (not with
+                   * dg_adjoint_step) */
   double gamma;
 } dg_config;
 

@@ -15,7 +15,7 @@ DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONPHYSICAL = range(6
 DG_EULER, DG_MHD = 0, 1
 DG_FP64, DG_FP32 = 0, 1
 DG_FLUX_HLL, DG_FLUX_HLLD, DG_FLUX_EXACT = 0, 1, 2
-DG_LIMITER_NONE, DG_LIMITER_MINMOD = 0, 1
+DG_LIMITER_NONE, DG_LIMITER_MINMOD, DG_LIMITER_WENO = 0, 1, 2
 DG_RUN_GRAPH = 1
 DG_RUN_MUSCL_HANCOCK = 2
 

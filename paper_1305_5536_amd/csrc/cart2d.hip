@@ -130,6 +130,103 @@ __device__ __forceinline__ void limit_cell(Cell<T>& c, const T* mS, const T* mN,
   }
 }
 
+// Primitive (rho, v_x, v_y, p) of a cell's conserved means.
+template <typename T>
+__device__ __forceinline__ void prim_of(const T* m, T gm1, T* w) {
+  const T ir = rcp(m[0]);
+  w[0] = m[0];
+  w[1] = m[1] * ir;
+  w[2] = m[2] * ir;
+  w[3] = gm1 * (m[3] - T(0.5) * (m[1] * w[1] + m[2] * w[2]));
+}
+
+// The WENO-type limiter of Sec. 2.5 on one cell.  Per primitive variable two
+// candidate slopes: the stencil slope (on a box the least-squares fit to the
+// four face neighbours' primitive means is the central difference), limited
+// as in limit_cell; and the cell's unlimited DG slope (chain rule at the
+// centroid).  Each gets the oscillation factor
+//   o = sum over the four faces of |dphi| + |phi_nb - (phi + dphi)|,
+// dphi = slope . (edge midpoint - centroid); the slopes are averaged with
+// weights (eps + o)^(-1/2), eps the working precision's machine epsilon, and
+// the conserved gradients are recomputed from the primitive ones.
+template <typename T>
+__device__ __forceinline__ void limit_cell_weno(Cell<T>& c, const T* mS, const T* mN,
+                                                const P2<T>& p) {
+  const T gm1 = p.gamma - T(1);
+  const T eps = sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
+  T mW[4], mE[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    mW[v] = lane_up(c.m[v]);
+    mE[v] = lane_down(c.m[v]);
+  }
+  T wi[4], wW[4], wE[4], wS[4], wN[4];
+  prim_of(c.m, gm1, wi);
+  prim_of(mW, gm1, wW);
+  prim_of(mE, gm1, wE);
+  prim_of(mS, gm1, wS);
+  prim_of(mN, gm1, wN);
+  const T rho = wi[0], ir = rcp(rho), vx = wi[1], vy = wi[2];
+  const T v2 = vx * vx + vy * vy;
+  // DG primitive slopes
+  T dx[4], dy[4];
+  dx[0] = c.gx[0];
+  dy[0] = c.gy[0];
+  dx[1] = (c.gx[1] - vx * dx[0]) * ir;
+  dy[1] = (c.gy[1] - vx * dy[0]) * ir;
+  dx[2] = (c.gx[2] - vy * dx[0]) * ir;
+  dy[2] = (c.gy[2] - vy * dy[0]) * ir;
+  dx[3] = gm1 * (c.gx[3] - T(0.5) * v2 * dx[0] - rho * (vx * dx[1] + vy * dx[2]));
+  dy[3] = gm1 * (c.gy[3] - T(0.5) * v2 * dy[0] - rho * (vx * dy[1] + vy * dy[2]));
+  T nx_[4], ny_[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // stencil slope, limited
+    T sx = (wE[k] - wW[k]) * p.cmx;
+    T sy = (wN[k] - wS[k]) * p.cmy;
+    const T hi = fmax(fmax(fmax(wi[k], wW[k]), fmax(wE[k], wS[k])), wN[k]);
+    const T lo = fmin(fmin(fmin(wi[k], wW[k]), fmin(wE[k], wS[k])), wN[k]);
+    // D >= 0 by definition; the clamp absorbs the rounding of a primitive
+    // value that the compiler fuses into hi - w (w = m * (1/rho) is a product),
+    // which could otherwise make D slightly negative and D/dm infinite
+    const T D = fmax(fmin(hi - wi[k], wi[k] - lo), T(0));
+    const T dm = fmax(fabs(sx) * p.hx2, fabs(sy) * p.hy2);
+    const T a = (dm > D) ? div_small(D, dm) : T(1);
+    sx *= a;
+    sy *= a;
+    // oscillation factors
+    auto osc = [&](T gx, T gy) {
+      const T ex = gx * p.hx2, ey = gy * p.hy2;
+      return T(2) * (fabs(ex) + fabs(ey)) + fabs(wE[k] - (wi[k] + ex)) +
+             fabs(wW[k] - (wi[k] - ex)) + fabs(wN[k] - (wi[k] + ey)) + fabs(wS[k] - (wi[k] - ey));
+    };
+    const T ws = rcp(sqrt_pos(eps + osc(sx, sy)));
+    const T wd = rcp(sqrt_pos(eps + osc(dx[k], dy[k])));
+    const T iw = rcp(ws + wd);
+    nx_[k] = (ws * sx + wd * dx[k]) * iw;
+    ny_[k] = (ws * sy + wd * dy[k]) * iw;
+  }
+  // conserved gradients from the primitive ones at the centroid
+  c.gx[0] = nx_[0];
+  c.gy[0] = ny_[0];
+  c.gx[1] = vx * nx_[0] + rho * nx_[1];
+  c.gy[1] = vx * ny_[0] + rho * ny_[1];
+  c.gx[2] = vy * nx_[0] + rho * nx_[2];
+  c.gy[2] = vy * ny_[0] + rho * ny_[2];
+  const T igm1 = rcp(gm1);
+  c.gx[3] = nx_[3] * igm1 + T(0.5) * v2 * nx_[0] + rho * (vx * nx_[1] + vy * nx_[2]);
+  c.gy[3] = ny_[3] * igm1 + T(0.5) * v2 * ny_[0] + rho * (vx * ny_[1] + vy * ny_[2]);
+}
+
+// The limiter selected by LIM: 1 the Arepo limiter, 2 the WENO-type limiter.
+template <typename T, int LIM>
+__device__ __forceinline__ void limit_any(Cell<T>& c, const T* mS, const T* mN, const P2<T>& p) {
+  if (LIM == 2)
+    limit_cell_weno(c, mS, mN, p);
+  else
+    limit_cell(c, mS, mN, p);
+}
+
 // HLL flux (Davis wave speeds) along axis AX between states uL, uR, written
 // as F = a F_L + b F_R + c (u_R - u_L) with (a, b, c) = (1, 0, 0) left of the
 // fan, (0, 1, 0) right of it and (S_R, -S_L, S_L S_R)/(S_R - S_L) inside.
@@ -345,7 +442,7 @@ __device__ __forceinline__ double cell_dt(const T* m, const P2<T>& p) {
 
 // One wave's tile (tile index `wave` of the mesh described by p).  RS selects
 // the face flux (0 HLL, 1 exact Riemann solver).
-template <typename T, int MODE, bool LIM, int RS = 0>
+template <typename T, int MODE, int LIM, int RS = 0>
 __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) {
   const int tx = wave % p.tiles_x, ty = wave / p.tiles_x;
   const int colu = tx * kCols + lane - 2;
@@ -406,7 +503,7 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
       load_means(p.in, nc, r2 * nx + col, nx2.m);
     r2 = next(r2);
 
-    if (LIM || MODE == kLimit) limit_cell(cur, prev.m, nx1.m, p);
+    if (LIM != 0 || MODE == kLimit) limit_any<T, (LIM == 2 ? 2 : 1)>(cur, prev.m, nx1.m, p);
     if (MODE == kMH) curP = predict(cur, p.gamma, T(0.5) * dt);
 
     if (MODE == kLimit) {
@@ -460,7 +557,7 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
         }
         if (MODE == kStage2) {
           Cell<T> ua = u0c;
-          if (LIM) limit_cell(ua, u0m, u0n.m, p);
+          if (LIM != 0) limit_any<T, LIM>(ua, u0m, u0n.m, p);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             o.m[v] = T(0.5) * (ua.m[v] + o.m[v]);
@@ -498,7 +595,7 @@ __device__ __forceinline__ void cart2d_tile(const P2<T>& p, int wave, int lane) 
   }
 }
 
-template <typename T, int MODE, bool LIM, int RS = 0>
+template <typename T, int MODE, int LIM, int RS = 0>
 __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
   const int lane = threadIdx.x & (kLanes - 1);
   const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -558,7 +655,7 @@ __device__ __forceinline__ P2<T> inst_params(const PB<T>& b, int i) {
   return p;
 }
 
-template <typename T, int MODE, bool LIM>
+template <typename T, int MODE, int LIM>
 __global__ __launch_bounds__(256) void k_cart2d_batch(PB<T> b) {
   const int lane = threadIdx.x & (kLanes - 1);
   const int nw = gridDim.x * b.wpb;
@@ -679,44 +776,49 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
   return p;
 }
 
+// One stage kernel launch for limiter LIM (0 none, 1 Arepo, 2 WENO).
+template <typename T, int MODE, int RS>
+void launch_lim(int lim, int nblocks, const P2<T>& p, hipStream_t s) {
+  if (lim == 2)
+    hipLaunchKernelGGL((k_cart2d<T, MODE, 2, RS>), dim3(nblocks), dim3(256), 0, s, p);
+  else if (lim == 1)
+    hipLaunchKernelGGL((k_cart2d<T, MODE, 1, RS>), dim3(nblocks), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_cart2d<T, MODE, 0, RS>), dim3(nblocks), dim3(256), 0, s, p);
+}
+
 template <typename T, int RS>
 hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                     const double* dt_dev, double dt_host, double cfl, double* dt_next,
                     hipStream_t s) {
   P2<T> p = make_params<T>(m, in, u0, out, dt_dev, dt_host);
   const int nblocks = (p.ntiles + 3) / 4;
-  const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
+  const int lim = m->cfg.limiter;  // 0 none, 1 Arepo, 2 WENO
   if (mode == kStage2 || mode == kMH) {
     p.dt_next = dt_next;
     p.cfl = cfl;
   }
   switch (mode) {
     case kRhs:
-      hipLaunchKernelGGL((k_cart2d<T, kRhs, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
+      hipLaunchKernelGGL((k_cart2d<T, kRhs, 0, RS>), dim3(nblocks), dim3(256), 0, s, p);
       break;
     case kLimit:
-      hipLaunchKernelGGL((k_cart2d<T, kLimit, true>), dim3(nblocks), dim3(256), 0, s, p);
+      if (lim == 2)
+        hipLaunchKernelGGL((k_cart2d<T, kLimit, 2, 0>), dim3(nblocks), dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_cart2d<T, kLimit, 1, 0>), dim3(nblocks), dim3(256), 0, s, p);
       break;
     case kStage1:
-      if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kStage1, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
-      else
-        hipLaunchKernelGGL((k_cart2d<T, kStage1, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
+      launch_lim<T, kStage1, RS>(lim, nblocks, p, s);
       break;
     case kStage2:
-      if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kStage2, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
-      else
-        hipLaunchKernelGGL((k_cart2d<T, kStage2, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
+      launch_lim<T, kStage2, RS>(lim, nblocks, p, s);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);
       break;
     case kMH:
-      if (lim)
-        hipLaunchKernelGGL((k_cart2d<T, kMH, true, RS>), dim3(nblocks), dim3(256), 0, s, p);
-      else
-        hipLaunchKernelGGL((k_cart2d<T, kMH, false, RS>), dim3(nblocks), dim3(256), 0, s, p);
+      launch_lim<T, kMH, RS>(lim, nblocks, p, s);
       if (dt_next)
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);

@@ -186,8 +186,14 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   if (!d || !cfg) return einval("dg_mesh_create: NULL descriptor or config");
   if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32)
     return einval("dg_mesh_create: unknown precision");
-  if (cfg->limiter != DG_LIMITER_NONE && cfg->limiter != DG_LIMITER_MINMOD)
+  if (cfg->limiter != DG_LIMITER_NONE && cfg->limiter != DG_LIMITER_MINMOD &&
+      cfg->limiter != DG_LIMITER_WENO)
     return einval("dg_mesh_create: unknown limiter");
+  if (cfg->limiter == DG_LIMITER_WENO &&
+      (cfg->physics != DG_EULER || d->kind != 0 || d->dim != 2)) {
+    set_error("dg_mesh_create: the WENO-type limiter is built for 2D Cartesian Euler meshes");
+    return DG_EUNSUPPORTED;
+  }
   if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma))
     return einval("dg_mesh_create: gamma must be finite and > 1");
   if (cfg->physics == DG_EULER) {
@@ -503,8 +509,9 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
                           const double* dt_dev, const void* lam_np1, void* lam_n, void* stream) {
   if (!m || !U || !lam_np1 || !lam_n) return einval("dg_adjoint_step: NULL argument");
   m->ws_a_fresh = false;
-  if (!m->adj_inst || m->cfg.flux != DG_FLUX_HLL) {
-    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes and batches with HLL");
+  if (!m->adj_inst || m->cfg.flux != DG_FLUX_HLL || m->cfg.limiter == DG_LIMITER_WENO) {
+    set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes and batches with HLL and "
+              "the Arepo limiter");
     return DG_EUNSUPPORTED;
   }
   if (!dt_dev && (!std::isfinite(dt) || dt < 0))

@@ -40,7 +40,13 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.physics = physics
         self.precision = precision
-        self.limiter = bool(limiter)
+        # limiter: False (none), True or "arepo" (the Arepo limiter), "weno"
+        # (the WENO-type limiter, 2D Cartesian Euler)
+        limiters = {False: C.DG_LIMITER_NONE, True: C.DG_LIMITER_MINMOD,
+                    "arepo": C.DG_LIMITER_MINMOD, "weno": C.DG_LIMITER_WENO}
+        if limiter not in limiters:
+            raise ValueError(f"unknown limiter {limiter!r}")
+        self.limiter = limiter
         self.gamma = float(gamma)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         # face flux: "hll" or "exact" for Euler (default "hll"), "hlld" for MHD
@@ -51,7 +57,7 @@ class Solver:
         cfg = C.dg_config(C.DG_MHD if physics == "mhd" else C.DG_EULER,
                           C.DG_FP64 if precision == "fp64" else C.DG_FP32,
                           fluxes[self.flux],
-                          C.DG_LIMITER_MINMOD if limiter else C.DG_LIMITER_NONE, self.gamma)
+                          limiters[limiter], self.gamma)
         d = C.dg_mesh_desc()
         self._keep = []
         if mesh["kind"] == "cartesian":
