@@ -93,6 +93,12 @@ def lib():
         L.or_divB.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_moving_update.restype = ctypes.c_int
+        L.or_moving_update.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, _dp, ctypes.c_double, _dp, _dp, _dp]
+        L.or_cfl_dt_moving.restype = ctypes.c_double
+        L.or_cfl_dt_moving.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp,
+                                       ctypes.c_double]
         _lib = L
     return _lib
 

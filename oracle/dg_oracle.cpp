@@ -1301,6 +1301,204 @@ double cfl_dt(const Ctx& C, const double* U, double cfl) {
 
 Mesh* as_mesh(void* h) { return static_cast<Mesh*>(h); }
 
+// ------------------------------------------------- moving mesh (Sec. 2.3) --
+// On a moving mesh the flux through a face moving with velocity w (and the
+// flux inside a cell moving with w) is the static flux minus the advection by
+// the motion, F_m = F(U) - U w^T; the Riemann problem is solved in the rest
+// frame of the face and the result carried back to the lab frame.
+//
+// Galilean boost of a conserved Euler state into the frame moving with w:
+// the density is unchanged, m' = m - rho w, E' = E - m . w + rho |w|^2 / 2.
+template <class T> void boost_state(int dim, const T* u, const double* w, T* ub) {
+  T mw = T(0);
+  double ww = 0.0;
+  ub[0] = u[0];
+  for (int d = 0; d < dim; ++d) {
+    ub[1 + d] = u[1 + d] - u[0] * T(w[d]);
+    mw += u[1 + d] * T(w[d]);
+    ww += w[d] * w[d];
+  }
+  ub[1 + dim] = u[1 + dim] - mw + T(0.5 * ww) * u[0];
+}
+
+// Lab-frame flux through a surface moving with w, F(U) - U w^T, from the flux
+// Fb of the same state in the surface's rest frame: the mass flux is the
+// same, the momentum flux gains w times the mass flux, the energy flux gains
+// w . (momentum flux) + |w|^2/2 (mass flux).
+template <class T> void unboost_flux(int dim, const T* Fb, const double* w, T* F) {
+  T wF = T(0);
+  double ww = 0.0;
+  F[0] = Fb[0];
+  for (int d = 0; d < dim; ++d) {
+    F[1 + d] = Fb[1 + d] + Fb[0] * T(w[d]);
+    wF += Fb[1 + d] * T(w[d]);
+    ww += w[d] * w[d];
+  }
+  F[1 + dim] = Fb[1 + dim] + wF + T(0.5 * ww) * Fb[0];
+}
+
+// Velocity of the Voronoi face between generators rL and rR (R's periodic
+// image next to L) that move with wL and wR, at the point f of the face: the
+// mean of the two velocities plus the normal motion of the bisector at f,
+//   w = (wL + wR)/2 + [(wL - wR) . (f - (rL + rR)/2)] (rR - rL) / |rR - rL|^2.
+// The normal part varies linearly along the face (the bisector turns when the
+// generators move relative to each other), so it is taken at each Gauss point.
+void face_velocity(const double* rL, const double* rR, const double* wL, const double* wR,
+                   const double* f, double* w) {
+  double d[2], dd = 0.0, s = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    d[k] = rR[k] - rL[k];
+    dd += d[k] * d[k];
+    s += (wL[k] - wR[k]) * (f[k] - 0.5 * (rL[k] + rR[k]));
+  }
+  for (int k = 0; k < 2; ++k) w[k] = 0.5 * (wL[k] + wR[k]) + s / dd * d[k];
+}
+
+// Periodic minimum image of a coordinate difference.
+inline double min_image(double d, double L) { return d - L * std::nearbyint(d / L); }
+
+// One cell of the moving-mesh MUSCL-Hancock update (Sec. 2.3, Sec. 2.4), 2D
+// Euler.  The generators move with constant velocities wg over the step; the
+// fluxes are taken on the mesh H of the generators at the half step
+// t^{n+1/2} (the midpoint rule in time for the moving faces and cells), and N0
+// is the mesh at t^n on which the state Ua (already limited) lives.
+// Every state is the half-step primitive prediction of its cell (Sec. 2.4),
+// centred at the t^n centroid and evaluated at the half-step position of the
+// point.  At a face Gauss point the two states are boosted into the frame of
+// the face at that point (the bisector's velocity there), the Riemann flux is
+// taken in that frame and carried back to the lab frame (F_m = F - U w^T).
+// The volume flux is F - U w_e^T on the half-step cell's quadrature points.
+// Out, in the state layout: the conserved totals Q0 = V^n ubar + dt (surface
+// terms) at k = 3v, and at 3v+1, 3v+2 the first moments about the cell's
+// origin carried along with w_e (c^n + (t - t^n) w_e),
+//   Q1 = M^n g + dt (surface + volume terms).
+template <class T>
+bool moving_cell(const Ctx& C, const Mesh& N0, const T* Ua, double dt, const double* gen,
+                 const double* wg, T* Q, int64_t e) {
+  const Mesh& H = *C.mesh;
+  const Phys& P = C.P;
+  const int dim = 2, nh = 4;
+  const int64_t nc = H.nc;
+  const double half = 0.5 * dt;
+  CellGeo c0, ch;
+  N0.cell(e, c0);
+  H.cell(e, ch);
+  Poly<T> qe;
+  load_poly(P, Ua, nc, e, qe);
+  const double* we = &wg[2 * e];
+  T S0[4], S1[4][2];
+  for (int v = 0; v < nh; ++v) S0[v] = S1[v][0] = S1[v][1] = T(0);
+  bool ok = true;
+  int64_t fids[64];
+  int sides[64];
+  const int nfc = H.cell_faces(e, fids, sides);
+  for (int m = 0; m < nfc; ++m) {
+    const int64_t f = fids[m];
+    FaceGeo fg;
+    H.face(f, fg);
+    Poly<T> qL, qR;
+    load_poly(P, Ua, nc, fg.L, qL);
+    load_poly(P, Ua, nc, fg.R, qR);
+    Prim<T> pL, pR;
+    predict_prim(P, qL, half, pL);
+    predict_prim(P, qR, half, pR);
+    CellGeo cL, cR;
+    N0.cell(fg.L, cL);
+    N0.cell(fg.R, cR);
+    double rL[2], rR[2];
+    for (int d = 0; d < 2; ++d) {
+      rL[d] = gen[2 * fg.L + d];
+      rR[d] = gen[2 * fg.R + d] + H.fsh[2 * f + d] * H.box[d];
+    }
+    for (int p = 0; p < fg.ng; ++p) {
+      // the Gauss point (in L's periodic frame at the half step), the face
+      // velocity there, and its offsets from the t^n centroids
+      double xg[2], wf[2], xL[3] = {0, 0, 0}, xR[3] = {0, 0, 0}, r[2];
+      for (int d = 0; d < 2; ++d) xg[d] = H.cc[2 * fg.L + d] + fg.rg[p][d];
+      face_velocity(rL, rR, &wg[2 * fg.L], &wg[2 * fg.R], xg, wf);
+      for (int d = 0; d < 2; ++d) {
+        xL[d] = min_image(xg[d] - cL.c[d], H.box[d]);
+        xR[d] = min_image(xg[d] - cR.c[d], H.box[d]);
+        // relative to this cell's carried origin c^n + (dt/2) w_e
+        r[d] = (sides[m] == 0 ? xL[d] : xR[d]) - half * we[d];
+      }
+      T uL[4], uR[4], bL[4], bR[4], Fb[4], F[4];
+      eval_prim(P, pL, xL, uL);
+      eval_prim(P, pR, xR, uR);
+      if (!physical(P, uL) || !physical(P, uR)) ok = false;
+      boost_state(dim, uL, wf, bL);
+      boost_state(dim, uR, wf, bR);
+      if (P.riemann == 1) {
+        if (!exact_riemann(P, bL, bR, fg.n, Fb)) ok = false;
+      } else {
+        hll(P, bL, bR, fg.n, Fb);
+      }
+      unboost_flux(dim, Fb, wf, F);
+      const T sg = sides[m] == 0 ? T(-fg.wg[p]) : T(fg.wg[p]);
+      for (int v = 0; v < nh; ++v) {
+        S0[v] += sg * F[v];
+        for (int d = 0; d < 2; ++d) S1[v][d] += sg * F[v] * T(r[d]);
+      }
+    }
+  }
+  Prim<T> pe;
+  predict_prim(P, qe, half, pe);
+  for (int q = 0; q < ch.nq; ++q) {
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < 2; ++d) x[d] = min_image(ch.c[d] + ch.rq[q][d] - c0.c[d], H.box[d]);
+    T u[4], b[4];
+    eval_prim(P, pe, x, u);
+    if (!physical(P, u)) ok = false;
+    boost_state(dim, u, we, b);
+    const T w = T(ch.wq[q]);
+    for (int d = 0; d < 2; ++d) {
+      double nd[3] = {0, 0, 0};
+      nd[d] = 1.0;
+      T Fb[4], F[4];
+      flux_n(P, b, nd, Fb);
+      unboost_flux(dim, Fb, we, F);
+      for (int v = 0; v < nh; ++v) S1[v][d] += w * F[v];
+    }
+  }
+  for (int v = 0; v < nh; ++v) {
+    Q[(int64_t)(3 * v) * nc + e] = T(c0.V) * qe.m[v] + T(dt) * S0[v];
+    for (int d = 0; d < 2; ++d) {
+      T mg = T(c0.M[d][0]) * qe.g[v][0] + T(c0.M[d][1]) * qe.g[v][1];
+      Q[(int64_t)(3 * v + 1 + d) * nc + e] = mg + T(dt) * S1[v][d];
+    }
+  }
+  return ok;
+}
+
+// CFL step on a moving mesh: dt = cfl * min_e 2 V_e / sum_f A_f (|(v_e - w_e)
+// . n_f| + c_e), the signal speed relative to the cell's own motion.
+double cfl_dt_moving(const Ctx& C, const double* U, const double* wg, double cfl) {
+  const Mesh& M = *C.mesh;
+  const Phys& P = C.P;
+  const int64_t nc = M.nc;
+  double best = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : best)
+  for (int64_t e = 0; e < nc; ++e) {
+    Poly<double> q;
+    load_poly(P, U, nc, e, q);
+    CellGeo cg;
+    M.cell(e, cg);
+    int64_t fids[64];
+    int sides[64];
+    const int nfc = M.cell_faces(e, fids, sides);
+    double s = 0;
+    for (int m = 0; m < nfc; ++m) {
+      FaceGeo fg;
+      M.face(fids[m], fg);
+      double vn = 0;
+      for (int d = 0; d < 2; ++d) vn += (q.m[1 + d] / q.m[0] - wg[2 * e + d]) * fg.n[d];
+      s += fg.A * (std::fabs(vn) + signal_speed(P, q.m, fg.n));
+    }
+    best = std::min(best, 2.0 * cg.V / s);
+  }
+  return cfl * best;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- C ABI --
@@ -1580,6 +1778,35 @@ void or_divB(void* h, const double* U, double* divB) {
     }
     divB[e] = s / cg.V;
   }
+}
+
+// Moving-mesh MUSCL-Hancock update (2D Euler): h0 the face-list mesh at t^n
+// (the state's mesh), hh the mesh of the generators at the half step,
+// gen_half[ncells][2] those generator positions, wg[ncells][2] the generator
+// velocities.  The limiter (0 none, 1 Arepo, 2 WENO-type) acts on h0 at the
+// start of the step; Q receives the totals and moments of moving_cell.
+// Returns 0, or 5 on a non-physical state.
+int or_moving_update(void* h0, void* hh, int riemann, int limiter, double gamma, const double* U,
+                     double dt, const double* gen_half, const double* wg, double* Q) {
+  Ctx C0{as_mesh(h0), Phys{2, 0, gamma, riemann}, limiter};
+  Ctx C{as_mesh(hh), Phys{2, 0, gamma, riemann}, limiter};
+  const int64_t nc = C0.mesh->nc, len = 12 * nc;
+  if (C.mesh->nc != nc) return 1;
+  std::vector<double> Ua(len);
+  if (limiter)
+    limit_all(C0, U, Ua.data());
+  else
+    std::copy(U, U + len, Ua.begin());
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t e = 0; e < nc; ++e)
+    if (!moving_cell(C, *C0.mesh, Ua.data(), dt, gen_half, wg, Q, e)) bad |= 1;
+  return bad ? 5 : 0;
+}
+
+double or_cfl_dt_moving(void* h, double gamma, const double* U, const double* wg, double cfl) {
+  Ctx C{as_mesh(h), Phys{2, 0, gamma}, 0};
+  return cfl_dt_moving(C, U, wg, cfl);
 }
 
 }  // extern "C"
