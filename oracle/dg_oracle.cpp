@@ -1408,7 +1408,7 @@ bool moving_cell(const Ctx& C, const Mesh& N0, const T* Ua, double dt, const dou
     double rL[2], rR[2];
     for (int d = 0; d < 2; ++d) {
       rL[d] = gen[2 * fg.L + d];
-      rR[d] = gen[2 * fg.R + d] + H.fsh[2 * f + d] * H.box[d];
+      rR[d] = gen[2 * fg.R + d] + H.fsh[2 * f + d];  // fsh holds shift * box
     }
     for (int p = 0; p < fg.ng; ++p) {
       // the Gauss point (in L's periodic frame at the half step), the face

@@ -151,6 +151,32 @@ def test_arepo_limiter_is_not_galilean_invariant(mv):
     assert np.abs(_boost(Ub, -V0, n) - Ua).max() > 1e-6
 
 
+def test_scale_invariance(mv):
+    """The Euler equations are invariant under x -> lam x, t -> lam t: the same
+    generators and state in a box scaled by lam, stepped with dt scaled by lam,
+    give the same cell values (gradients scaled by 1/lam) and a scaled mesh.  A
+    non-square box with a non-unit scale exercises every periodic image."""
+    n, box, lam = 600, np.array([1.3, 0.8]), 7.0
+    P = periodic_voronoi(n, seed=19, box=tuple(box))["generators"]
+    d1 = mv.voronoi(P, box)
+    dL = mv.voronoi(P * lam, box * lam)
+    U1 = random_voronoi_state(d1, G53, seed=20, amp=0.3)
+    UL = U1.reshape(12, n).copy()
+    UL[1::3] /= lam
+    UL[2::3] /= lam
+    UL = UL.reshape(-1)
+    for _ in range(4):
+        dt = mv.cfl_dt(d1, U1, G53, 0.3)
+        U1, d1 = mv.step(d1, U1, dt, G53, "weno", "exact")
+        UL, dL = mv.step(dL, UL, lam * dt, G53, "weno", "exact")
+    A, B = U1.reshape(12, n), UL.reshape(12, n)
+    h = math.sqrt(box.prod() / n)
+    e = max(np.abs(A[0::3] - B[0::3]).max(),
+            h * np.abs(A[1::3] - lam * B[1::3]).max(), h * np.abs(A[2::3] - lam * B[2::3]).max())
+    assert e < 1e-11 * np.abs(A).max(), e
+    assert np.abs(dL["generators"] - lam * d1["generators"]).max() < 1e-12 * lam
+
+
 def test_conservation_through_topology_changes(mv):
     n = 800
     d = mv.voronoi(periodic_voronoi(n, seed=4)["generators"], (1.0, 1.0))
