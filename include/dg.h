@@ -69,7 +69,8 @@ typedef enum {
   DG_ENOMEM = 2,        /* device or host allocation failed */
   DG_EHIP = 3,          /* a HIP runtime call failed (message in dg_last_error) */
   DG_EUNSUPPORTED = 4,  /* valid but not built: e.g. MHD on a face-list mesh */
-  DG_ENONPHYSICAL = 5   /* latched non-physical state (dg_check only) */
+  DG_ENONPHYSICAL = 5,  /* latched non-physical state (dg_check only) */
+  DG_EMESH = 6          /* latched moving-mesh failure (dg_check only) */
 } dg_status;
 
 typedef enum { DG_EULER = 0, DG_MHD = 1 } dg_physics;
@@ -110,7 +111,20 @@ typedef struct {
  *   Every cell must be closed: sum over its faces of A n = 0 (checked).
  * kind 2: a batch of ninst periodic 2D Cartesian Euler instances (dim = 2):
  *   inst_n[ninst][2] = (nx, ny), inst_box[ninst][4] = (lo_x, lo_y, hi_x, hi_y),
- *   host arrays copied at create. */
+ *   host arrays copied at create.
+ * kind 3: a moving periodic 2D Voronoi mesh (Sec. 2.3), 2D Euler only, in the
+ *   box [0, box[0]) x [0, box[1]) with ncells >= 64 generators
+ *   generators[ncells][2] (inside the box) and their initial Voronoi faces
+ *   face_cells[nfaces][2] with face_shift[nfaces][2] (R's generator image next
+ *   to L is generators[R] + shift * box), host arrays copied at create; the
+ *   other face-list arrays are ignored.  The library builds and owns the mesh:
+ *   the generators move with their cell's velocity (mean momentum / mean
+ *   density) and dg_step_mh rebuilds the Voronoi mesh every step on the GPU
+ *   (geometry, areas, centroids and second moments: the mass matrix of Sec.
+ *   2.2 recomputed per step).  At most 16 faces per cell; a cell's neighbours
+ *   after a step must lie within two rings of its neighbours before it (any
+ *   CFL-limited step); a failure latches DG_EMESH (dg_check).  The mesh must
+ *   be fine enough that no two cells share two faces (ncells >= 64). */
 typedef struct {
   int dim;
   int kind;
@@ -129,6 +143,7 @@ typedef struct {
   int32_t ninst;
   const int32_t* inst_n;
   const double* inst_box;
+  const double* generators;
 } dg_mesh_desc;
 
 /* Create a mesh handle: validates the descriptor and configuration, uploads
@@ -154,7 +169,12 @@ dg_status dg_rhs(dg_mesh_t mesh, const void* U, void* dUdt, void* stream);
 /* U_lim = Pi(U): the slope limiter of Sec. 2.5, alpha = min(1, min_j psi_ij)
  * per conserved variable from the means of the cell and its face neighbours
  * and the linear extrapolation to each face centroid; means are unchanged;
- * the three B components share one alpha.  U and U_lim must not alias. */
+ * the three B components share one alpha.  U and U_lim must not alias.
+ * With DG_LIMITER_WENO (2D Euler) the WENO-type limiter of Sec. 2.5 instead
+ * blends, per primitive variable, the stencil slope (limited as above) and the
+ * cell's own DG slope with weights (eps + o)^(-1/2).  On a moving mesh the
+ * limiter acts on the handle's current mesh; the stencil slope is the
+ * least-squares fit to the face neighbours' primitive means. */
 dg_status dg_limit(dg_mesh_t mesh, const void* U, void* U_lim, void* stream);
 
 /* One SSP-RK2 step of size dt with the limiter (if configured) at the start of
@@ -199,8 +219,24 @@ dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const doubl
  * flux passes of the SSP-RK2 step).  Step size: *dt_dev (one per instance on
  * a batch) when dt_dev is not NULL, else dt.  When dt_next_dev is not NULL,
  * also writes the CFL step of U_next (as dg_stage2).  U_next must not alias
- * U.  Built for 2D Euler on Cartesian meshes and batches (DG_EUNSUPPORTED
- * otherwise). */
+ * U.  Built for 2D Euler on Cartesian meshes, batches and moving meshes
+ * (DG_EUNSUPPORTED otherwise).
+ * On a moving mesh (kind 3) the step also moves the mesh held by the handle
+ * from t^n to t^{n+1}, so U must be the state on the handle's current mesh and
+ * U_next is the state on the new one.  The step (Sec. 2.3, Sec. 2.4): limit U
+ * on the mesh of t^n; move the generators with constant velocity w_e (their
+ * cell's mean velocity, or 0 after dg_set_mesh_motion(mesh, 0)); take every
+ * flux on the Voronoi mesh of the half-step generators, with both cells'
+ * half-step predictions (centred at the t^n centroids) at each face Gauss
+ * point, the Riemann problem (HLL or exact, per dg_config.flux) solved in the
+ * frame of the face at that point (the velocity of the bisector there) and
+ * carried back to the lab frame, F_m = F - U w^T, and the volume flux
+ * F - U w_e^T on the half-step cell; the conserved totals V ubar and the first
+ * moments (about the cell's origin carried with w_e) are advanced by dt, and
+ * the new state is read off the mesh of t^{n+1}: ubar = totals / V, gradients
+ * from the new mass matrix after moving the moments to the new centroid.
+ * CFL (dt_next_dev, dg_cfl_dt): cfl * min_e 2 V_e / sum_f A_f
+ * (|(v_e - w_e) . n_f| + c_e). */
 dg_status dg_step_mh(dg_mesh_t mesh, const void* U, void* U_next, double dt, const double* dt_dev,
                      double cfl, double* dt_next_dev, void* stream);
 
@@ -279,10 +315,24 @@ dg_status dg_set_tiling(dg_mesh_t mesh, int rows_per_tile);
 /* Current rows (or planes) per wave, or -1 for a NULL handle. */
 int dg_get_tiling(dg_mesh_t mesh);
 
-/* Synchronise the device, then return DG_ENONPHYSICAL if any kernel of this
- * mesh met a non-physical state since the last call (and clear the flag),
- * else DG_OK (or DG_EHIP if synchronisation failed). */
+/* Synchronise the device, then return DG_EMESH if a moving mesh failed to
+ * rebuild a cell (see kind 3), else DG_ENONPHYSICAL if any kernel of this mesh
+ * met a non-physical state since the last call (and clear the flags), else
+ * DG_OK (or DG_EHIP if synchronisation failed). */
 dg_status dg_check(dg_mesh_t mesh);
+
+/* Moving meshes (kind 3): 1 (the default) moves the generators with their
+ * cell velocity in dg_step_mh, 0 holds them still (the step is then the static
+ * MUSCL-Hancock step on the Voronoi mesh).  DG_EUNSUPPORTED on other kinds. */
+dg_status dg_set_mesh_motion(dg_mesh_t mesh, int motion);
+
+/* Moving meshes (kind 3): host copies of the current mesh (synchronises the
+ * device).  generators[ncells][2] (in [0, box)), volume[ncells],
+ * centroid[ncells][2] (generator + centroid offset, not wrapped),
+ * ring[ncells][16] the neighbours in counter-clockwise order padded with -1,
+ * degree[ncells].  Any output may be NULL.  DG_EUNSUPPORTED on other kinds. */
+dg_status dg_mesh_geometry(dg_mesh_t mesh, double* generators, double* volume, double* centroid,
+                           int32_t* ring, int32_t* degree);
 
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* dg_last_error(void);

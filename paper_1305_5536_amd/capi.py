@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdg.so")
 
-DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONPHYSICAL = range(6)
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_EUNSUPPORTED, DG_ENONPHYSICAL, DG_EMESH = range(7)
 DG_EULER, DG_MHD = 0, 1
 DG_FP64, DG_FP32 = 0, 1
 DG_FLUX_HLL, DG_FLUX_HLLD, DG_FLUX_EXACT = 0, 1, 2
@@ -20,7 +20,7 @@ DG_RUN_GRAPH = 1
 DG_RUN_MUSCL_HANCOCK = 2
 
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ENOMEM", 3: "DG_EHIP", 4: "DG_EUNSUPPORTED",
-                5: "DG_ENONPHYSICAL"}
+                5: "DG_ENONPHYSICAL", 6: "DG_EMESH"}
 
 
 class DGError(RuntimeError):
@@ -51,7 +51,7 @@ class dg_mesh_desc(ctypes.Structure):
         ("face_normal", _dp), ("face_centroid", _dp),
         ("face_shift", ctypes.POINTER(ctypes.c_int8)),
         ("ninst", ctypes.c_int32), ("inst_n", ctypes.POINTER(ctypes.c_int32)),
-        ("inst_box", _dp),
+        ("inst_box", _dp), ("generators", _dp),
     ]
 
 
@@ -95,6 +95,10 @@ SYMBOLS = [
     ("dg_set_tiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("dg_get_tiling", ctypes.c_int, [ctypes.c_void_p]),
     ("dg_check", ctypes.c_int, [ctypes.c_void_p]),
+    ("dg_set_mesh_motion", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("dg_mesh_geometry", ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     ("dg_last_error", ctypes.c_char_p, []),
 ]
 

@@ -32,6 +32,16 @@ static dg_status einval(const std::string& msg) {
 }
 
 hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt, hipStream_t s);
+hipError_t launch_moving(dg_mesh* m, int mode, const void* in, void* out, const double* dt_dev,
+                         double dt_host, double cfl, double* dt_next, hipStream_t s);
+hipError_t launch_moving_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                             hipStream_t s);
+dg_status moving_create(dg_mesh* m, const dg_mesh_desc* d);
+void moving_destroy(dg_mesh* m);
+hipError_t moving_init(dg_mesh* m);
+int moving_read(const dg_mesh* m, double* gen, double* vol, double* cen, int32_t* ring,
+                int32_t* deg);
+void moving_set_motion(dg_mesh* m, int motion);
 dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d);
 void facelist_destroy(dg_mesh* m);
 hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
@@ -89,6 +99,16 @@ static dg_status dispatch(const dg_mesh* m, int mode, const void* in, const void
                           const double* dt_dev, double dt_host, hipStream_t s,
                           double cfl = 0.0, double* dt_next = nullptr) {
   hipError_t e;
+  if (m->kind == 3) {
+    if (mode != kLimit && mode != kMH) {
+      set_error("moving Voronoi meshes step with dg_step_mh only (the moving-mesh "
+                "MUSCL-Hancock step); dg_limit is built too");
+      return DG_EUNSUPPORTED;
+    }
+    e = launch_moving(const_cast<dg_mesh*>(m), mode, in, out, dt_dev, dt_host, cfl, dt_next, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DG_OK;
+  }
   if (m->kind == 1)
     e = launch_facelist(m, mode, in, u0, out, dt_dev, dt_host, cfl, dt_next, s);
   else if (m->kind == 2)
@@ -190,8 +210,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
       cfg->limiter != DG_LIMITER_WENO)
     return einval("dg_mesh_create: unknown limiter");
   if (cfg->limiter == DG_LIMITER_WENO &&
-      (cfg->physics != DG_EULER || d->kind != 0 || d->dim != 2)) {
-    set_error("dg_mesh_create: the WENO-type limiter is built for 2D Cartesian Euler meshes");
+      (cfg->physics != DG_EULER || (d->kind != 0 && d->kind != 3) || d->dim != 2)) {
+    set_error("dg_mesh_create: the WENO-type limiter is built for 2D Euler on Cartesian and "
+              "moving Voronoi meshes");
     return DG_EUNSUPPORTED;
   }
   if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma))
@@ -201,8 +222,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
       set_error("dg_mesh_create: Euler takes the HLL or the exact Riemann flux");
       return DG_EUNSUPPORTED;
     }
-    if (cfg->flux == DG_FLUX_EXACT && (d->kind != 0 || d->dim != 2)) {
-      set_error("dg_mesh_create: the exact Riemann flux is built for 2D Cartesian meshes");
+    if (cfg->flux == DG_FLUX_EXACT && ((d->kind != 0 && d->kind != 3) || d->dim != 2)) {
+      set_error("dg_mesh_create: the exact Riemann flux is built for 2D Cartesian and moving "
+                "Voronoi meshes");
       return DG_EUNSUPPORTED;
     }
   } else if (cfg->physics == DG_MHD) {
@@ -217,8 +239,12 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   } else {
     return einval("dg_mesh_create: unknown physics");
   }
-  if (d->kind != 0 && d->kind != 1 && d->kind != 2)
+  if (d->kind != 0 && d->kind != 1 && d->kind != 2 && d->kind != 3)
     return einval("dg_mesh_create: unknown mesh kind");
+  if (d->kind == 3 && (cfg->physics != DG_EULER || d->dim != 2)) {
+    set_error("dg_mesh_create: moving Voronoi meshes are built for 2D Euler");
+    return DG_EUNSUPPORTED;
+  }
   if (d->kind == 2) {
     if (cfg->physics != DG_EULER) {
       set_error("dg_mesh_create: batches are built for 2D Euler only");
@@ -347,6 +373,15 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
       return st;
     }
     nwaves = maxtiles;
+  } else if (d->kind == 3) {
+    m->ncoef = 12;
+    m->ncells = d->ncells;
+    dg_status st = moving_create(m, d);
+    if (st != DG_OK) {
+      delete m;
+      return st;
+    }
+    nwaves = (m->ncells + 63) / 64;
   } else {
     m->ncoef = 12;
     dg_status st = facelist_create(m, d);
@@ -378,6 +413,23 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     dg_mesh_destroy(m);
     return e == hipErrorOutOfMemory ? DG_ENOMEM : st;
   }
+  if (m->kind == 3) {
+    // the mesh of the initial generators, built by the same clip as every step
+    e = moving_init(m);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flag, m->status, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      dg_status st = hip_fail(e, "dg_mesh_create: initial moving mesh");
+      dg_mesh_destroy(m);
+      return st;
+    }
+    if (flag) {
+      dg_mesh_destroy(m);
+      return einval("dg_mesh_create: the initial faces do not give a Voronoi mesh of the "
+                    "generators");
+    }
+  }
   *out = m;
   return DG_OK;
 }
@@ -386,6 +438,7 @@ void dg_mesh_destroy(dg_mesh_t m) {
   if (!m) return;
   (void)hipDeviceSynchronize();
   if (m->kind == 1) facelist_destroy(m);
+  if (m->kind == 3) moving_destroy(m);
   drop_graph(m);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
   (void)hipFree(m->run_ws);
@@ -491,7 +544,9 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
   if (!(cfl > 0) || !std::isfinite(cfl)) return einval("dg_cfl_dt: cfl must be > 0");
   hipError_t e;
   hipStream_t s = (hipStream_t)stream;
-  if (m->kind == 1)
+  if (m->kind == 3)
+    e = launch_moving_cfl(m, U, cfl, dt_dev, s);
+  else if (m->kind == 1)
     e = launch_facelist_cfl(m, U, cfl, dt_dev, s);
   else if (m->kind == 2)
     e = launch_cart2d_batch_cfl(m, U, cfl, dt_dev, s);
@@ -538,7 +593,8 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
 }
 
 static bool mh_supported(const dg_mesh* m) {
-  return m->cfg.physics == DG_EULER && ((m->kind == 0 && m->dim == 2) || m->kind == 2);
+  return m->cfg.physics == DG_EULER &&
+         ((m->kind == 0 && m->dim == 2) || m->kind == 2 || m->kind == 3);
 }
 
 dg_status dg_step_mh(dg_mesh_t m, const void* U, void* Un, double dt, const double* dt_dev,
@@ -546,7 +602,7 @@ dg_status dg_step_mh(dg_mesh_t m, const void* U, void* Un, double dt, const doub
   if (!m || !U || !Un) return einval("dg_step_mh: NULL argument");
   m->ws_a_fresh = false;
   if (!mh_supported(m)) {
-    set_error("dg_step_mh: built for 2D Euler Cartesian meshes and batches");
+    set_error("dg_step_mh: built for 2D Euler Cartesian meshes, batches and moving meshes");
     return DG_EUNSUPPORTED;
   }
   if (U == Un) return einval("dg_step_mh: U_next must not alias U");
@@ -566,6 +622,10 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
   if (nsteps == 1 && U_out == U_in) return einval("dg_run: U_out may equal U_in only for >= 2 steps");
   if (flags & ~(DG_RUN_GRAPH | DG_RUN_MUSCL_HANCOCK)) return einval("dg_run: unknown flag");
   const bool mh = (flags & DG_RUN_MUSCL_HANCOCK) != 0;
+  if (m->kind == 3) {
+    set_error("dg_run: not built for moving meshes (step them with dg_step_mh)");
+    return DG_EUNSUPPORTED;
+  }
   if (mh && !mh_supported(m)) {
     set_error("dg_run: MUSCL-Hancock is built for 2D Euler Cartesian meshes and batches");
     return DG_EUNSUPPORTED;
@@ -745,9 +805,37 @@ dg_status dg_check(dg_mesh_t m) {
   if (flag) {
     e = hipMemset(m->status, 0, sizeof(int));
     if (e != hipSuccess) return hip_fail(e, "dg_check: clear status");
+    if (flag & 2) {
+      set_error("moving mesh: a cell's Voronoi polygon could not be built from its previous "
+                "neighbourhood, exceeded 16 faces, or its neighbours disagree");
+      return DG_EMESH;
+    }
     set_error("non-physical state (rho <= 0, p <= 0 or non-finite) at a quadrature point");
     return DG_ENONPHYSICAL;
   }
+  return DG_OK;
+}
+
+dg_status dg_set_mesh_motion(dg_mesh_t m, int motion) {
+  if (!m) return einval("dg_set_mesh_motion: NULL handle");
+  if (m->kind != 3) {
+    set_error("dg_set_mesh_motion: only moving meshes have generator motion");
+    return DG_EUNSUPPORTED;
+  }
+  if (motion != 0 && motion != 1) return einval("dg_set_mesh_motion: motion must be 0 or 1");
+  moving_set_motion(m, motion);
+  return DG_OK;
+}
+
+dg_status dg_mesh_geometry(dg_mesh_t m, double* generators, double* volume, double* centroid,
+                           int32_t* ring, int32_t* degree) {
+  if (!m) return einval("dg_mesh_geometry: NULL handle");
+  if (m->kind != 3) {
+    set_error("dg_mesh_geometry: built for moving meshes");
+    return DG_EUNSUPPORTED;
+  }
+  const int r = moving_read(m, generators, volume, centroid, ring, degree);
+  if (r) return hip_fail((hipError_t)r, "dg_mesh_geometry: copy");
   return DG_OK;
 }
 

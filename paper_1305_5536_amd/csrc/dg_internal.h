@@ -42,6 +42,7 @@ struct FaceList2D {
   int nblocks;
 };
 struct FLDev;
+struct MVDev;  // moving Voronoi mesh (moving2d.hip)
 
 // One 2D Cartesian instance of the adjoint kernel: a mesh of nx x ny cells
 // starting at cell `off` of the global state arrays, whose adjoint tiles
@@ -101,6 +102,7 @@ struct dg_mesh {
   dg::Cart3D c3{};
   dg::FaceList2D fl{};
   dg::FLDev* fld = nullptr;
+  dg::MVDev* mvd = nullptr;   // kind 3
   size_t elem = 8;            // sizeof(element)
   void* v1 = nullptr;         // workspace: stage-1 output
   void* tmp = nullptr;        // workspace: staging for in-place steps (lazy)

@@ -28,8 +28,10 @@ def _ptr(t: torch.Tensor):
 class Solver:
     """One mesh handle: geometry on the device, configuration, workspace.
 
-    ``mesh`` is ``{"kind": "cartesian", "n": (nx, ny[, nz]), "lo": ..., "hi": ...}``
-    or a 2D face-list descriptor (see ``workloads.voronoi``) with ``"kind": "facelist"``.
+    ``mesh`` is ``{"kind": "cartesian", "n": (nx, ny[, nz]), "lo": ..., "hi": ...}``,
+    a 2D face-list descriptor (see ``workloads.voronoi``) with ``"kind": "facelist"``,
+    or ``moving(descriptor)``: a moving Voronoi mesh built from the descriptor's
+    generators and faces, which ``step_mh`` moves with the flow.
     """
 
     def __init__(self, mesh: dict, physics: str = "euler", precision: str = "fp64",
@@ -85,6 +87,20 @@ class Solver:
             d.nfaces = len(arrs["face_area"])
             d.box[0], d.box[1] = float(mesh["box"][0]), float(mesh["box"][1])
             self._keep = [arrs, fc, fs]
+            self.ncells = int(d.ncells)
+        elif mesh["kind"] == "moving":
+            d.dim = 2
+            d.kind = 3
+            gen = np.ascontiguousarray(mesh["generators"], dtype=np.float64).reshape(-1, 2)
+            fc = np.ascontiguousarray(mesh["face_cells"], dtype=np.int32)
+            fs = np.ascontiguousarray(mesh["face_shift"], dtype=np.int8)
+            d.generators = _f64p(gen)
+            d.face_cells = fc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.face_shift = fs.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+            d.ncells = len(gen)
+            d.nfaces = len(fc)
+            d.box[0], d.box[1] = float(mesh["box"][0]), float(mesh["box"][1])
+            self._keep = [gen, fc, fs]
             self.ncells = int(d.ncells)
         elif mesh["kind"] == "batch":
             n = np.ascontiguousarray(mesh["n"], dtype=np.int32).reshape(-1, 2)
@@ -304,8 +320,28 @@ class Solver:
         C.check(C.lib().dg_set_launch(self._h, int(wg[0]), int(wg[1])), "dg_set_launch")
 
     def check(self) -> None:
-        """Synchronise and raise NonPhysicalState if a kernel met one."""
+        """Synchronise and raise NonPhysicalState if a kernel met one (DGError
+        with DG_EMESH if a moving mesh failed to rebuild)."""
         C.check(C.lib().dg_check(self._h), "dg_check")
+
+    def set_motion(self, motion: int) -> None:
+        """Moving meshes: 1 moves the generators with the flow, 0 holds them."""
+        C.check(C.lib().dg_set_mesh_motion(self._h, int(motion)), "dg_set_mesh_motion")
+
+    def geometry(self) -> dict:
+        """Moving meshes: host copy of the current generators, volumes,
+        centroids (generator + offset, not wrapped) and neighbour rings."""
+        n = self.ncells
+        gen = np.empty((n, 2))
+        vol = np.empty(n)
+        cen = np.empty((n, 2))
+        ring = np.empty((n, 16), dtype=np.int32)
+        deg = np.empty(n, dtype=np.int32)
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        C.check(C.lib().dg_mesh_geometry(self._h, _f64p(gen), _f64p(vol), _f64p(cen),
+                                         ring.ctypes.data_as(i32), deg.ctypes.data_as(i32)),
+                "dg_mesh_geometry")
+        return {"generators": gen, "volume": vol, "centroid": cen, "ring": ring, "degree": deg}
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -323,6 +359,13 @@ def batch(sizes, boxes=None) -> dict:
     """Batch of periodic 2D Cartesian instances: sizes [(nx, ny), ...], boxes
     [(lo_x, lo_y, hi_x, hi_y), ...] (default: the unit square)."""
     return {"kind": "batch", "n": [tuple(int(v) for v in n) for n in sizes], "box": boxes}
+
+
+def moving(mesh: dict) -> dict:
+    """A moving Voronoi mesh from a face-list descriptor with generators (its
+    generators and faces give the initial mesh; the library builds the rest)."""
+    return {"kind": "moving", "generators": mesh["generators"], "face_cells": mesh["face_cells"],
+            "face_shift": mesh["face_shift"], "box": mesh["box"]}
 
 
 def cartesian(n, lo, hi) -> dict:
