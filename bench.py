@@ -57,11 +57,13 @@ FACELIST_BYTES_PER_CELL_STAGE = {"fp64": 464, "fp32": 232}
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5", "ot"], default="c2",
+    p.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5", "ot", "moving"],
+                   default="c2",
                    help="c2: 2D Euler shear layer 2048^2 (default); c1: isentropic vortex "
                         "64^2; c3: 3D MHD 256^3; c4: static Voronoi mesh of 1M cells; c5: "
                         "256 batched instances N^2, N in {64..512}, with the adjoint; ot: 2D "
-                        "MHD Orszag-Tang vortex 512^2")
+                        "MHD Orszag-Tang vortex 512^2; moving: Kelvin-Helmholtz on a moving "
+                        "Voronoi mesh of 512^2 cells")
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--n", type=int, default=None, help="cells per side")
@@ -87,7 +89,7 @@ def parse():
     # CPU baseline sized to about 10-30 s of host work)
     dflt = {"c1": (64, 100, 10, 8000), "c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 12),
             "c4": (1000000, 100, 5, 50), "c5": (256, 200, 20, 800),
-            "ot": (512, 1000, 20, 16)}[a.config]
+            "ot": (512, 1000, 20, 16), "moving": (262144, 200, 10, 3)}[a.config]
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]
@@ -513,6 +515,127 @@ def bench_c4(a):
     return out
 
 
+# Moving Voronoi mesh: FP64 operations per cell of each kernel of the step
+# (wave-level VALU FP64 instruction counts from rocprofv3 --pmc, times 64 lanes,
+# FMA counted twice, over the cells of a launch; see the kernel profile), and
+# the algorithmic bytes per cell (state, positions, rings and geometry each
+# kernel must read and write once).
+MOVING_KERNELS = ("k_mv_lim", "k_mv_walk + k_mv_geom (half step)", "k_mv_upd",
+                  "k_mv_walk + k_mv_geom (new mesh + state)")
+MOVING_FLOPS_PER_CELL = {"k_mv_upd": None}
+MOVING_BYTES_PER_CELL = {"k_mv_lim": 96 + 96 + 16 + 64 + 4 + 48 + 32,
+                         "k_mv_walk + k_mv_geom (half step)": 16 + 64 + 4 + 64 + 4 + 48,
+                         "k_mv_upd": 96 + 96 + 16 + 16 + 64 + 4 + 48 + 48,
+                         "k_mv_walk + k_mv_geom (new mesh + state)":
+                             16 + 64 + 4 + 64 + 4 + 48 + 48 + 96 + 96 + 32}
+
+
+def run_gpu_moving(mesh, U0, gamma, precision, steps, warmup, cfl=0.3):
+    """Moving-mesh MUSCL-Hancock steps with the fused CFL step on the device:
+    HIP events around the timed loop, then a second loop with the library's
+    per-kernel events."""
+    import torch
+
+    from paper_1305_5536_amd.solver import Solver, moving
+    s = Solver(moving(mesh), precision=precision, limiter="weno", gamma=gamma, flux="exact")
+    U = s.to_device(U0)
+    Un = s.empty()
+    dt = s.cfl_dt(U, cfl)
+    for _ in range(warmup):
+        s.step_mh(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    s.check()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        s.step_mh(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.check()
+    tev = e0.elapsed_time(e1) * 1e-3
+    s.set_timing(True)
+    for _ in range(min(steps, 50)):
+        s.step_mh(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    ms, nt = s.kernel_times()
+    s.set_timing(False)
+    s.check()
+    s.close()
+    return {"wall_s": wall, "event_s": tev, "step_s": tev / steps,
+            "kernel_ms": dict(zip(MOVING_KERNELS, ms.tolist())), "timed_steps": nt}
+
+
+def bench_moving(a):
+    from workloads.voronoi import kh_voronoi_state, periodic_voronoi
+    n = a.n
+    gamma = 5.0 / 3.0
+    t0 = time.perf_counter()
+    log(f"building the periodic Voronoi mesh of {n} cells (2 Lloyd iterations)")
+    mesh = periodic_voronoi(n, seed=1006)
+    U0 = kh_voronoi_state(mesh, gamma)
+    tgen = time.perf_counter() - t0
+    log(f"input built in {tgen:.0f} s; timing the GPU steps")
+    r = run_gpu_moving(mesh, U0, gamma, a.precision, a.steps, a.warmup)
+    km = r["kernel_ms"]
+    dom = max(km, key=km.get)
+    flops = MOVING_FLOPS_PER_CELL.get(dom)
+    avg = km[dom] * 1e-3
+    if flops:
+        peak = FP64_VALU_PEAK_TFLOPS if a.precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+        achieved = flops * n / avg / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": dom,
+                "flops_per_launch": flops * n, "avg_launch_s": avg}
+    else:
+        elem = 8 if a.precision == "fp64" else 4
+        per = MOVING_BYTES_PER_CELL[dom] * n
+        achieved = per / avg / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "bytes_per_launch": per, "avg_launch_s": avg, "elem": elem}
+    out = {
+        "metric": METRIC, "value": n * a.steps / r["event_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["step_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"2D Euler Kelvin-Helmholtz setup of the paper on a moving "
+                               f"periodic Voronoi mesh of {n} cells (generators move with the "
+                               "flow, mesh rebuilt every step on the GPU), gamma 5/3, exact "
+                               "Riemann flux in the face frames, WENO-type limiter, "
+                               "MUSCL-Hancock (one flux pass per step)",
+                   "cells": n, "flux_passes_per_step": 1, "parallelism": "single GPU",
+                   "input_generation_s": tgen},
+        "roofline": roof,
+        "kernels_avg_ms": km,
+        "wall_s": r["wall_s"],
+    }
+    if a.also_fp32 and a.precision == "fp64":
+        r32 = run_gpu_moving(mesh, U0, gamma, "fp32", a.steps, a.warmup)
+        out["fp32"] = {"value": n * a.steps / r32["event_s"], "ms_per_step": r32["step_s"] * 1e3,
+                       "kernels_avg_ms": r32["kernel_ms"]}
+    if not a.no_cpu:
+        import oracle
+        from oracle import moving as mv
+        log("timing the CPU oracle (moving mesh)")
+        d = mv.voronoi(mesh["generators"], mesh["box"])
+        dt = mv.cfl_dt(d, U0, gamma, 0.3)
+        t1 = time.perf_counter()
+        Uc = U0
+        for _ in range(a.cpu_steps):
+            Uc, d = mv.step(d, Uc, dt, gamma, "weno", "exact")
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": n * a.cpu_steps / el, "unit": "cell-updates/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{a.cpu_steps} moving-mesh steps of the same state "
+                                         f"(two Delaunay rebuilds per step), FP64, {el:.1f} s"}
+    return out
+
+
 def _pool_map(fn, args):
     """Run host-side input generation in worker processes (forked before the
     GPU is touched; the workers only run numpy)."""
@@ -740,7 +863,7 @@ def main():
         copy_calibration()
         return
     out = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-           "c5": bench_c5, "ot": bench_ot}[a.config](a)
+           "c5": bench_c5, "ot": bench_ot, "moving": bench_moving}[a.config](a)
     print(json.dumps(out))
 
 

@@ -334,6 +334,17 @@ dg_status dg_set_mesh_motion(dg_mesh_t mesh, int motion);
 dg_status dg_mesh_geometry(dg_mesh_t mesh, double* generators, double* volume, double* centroid,
                            int32_t* ring, int32_t* degree);
 
+/* Moving meshes (kind 3): on != 0 makes every following dg_step_mh record HIP
+ * events on its stream around its four kernels (limiter; mesh of the half-step
+ * generators; fluxes and update; mesh of t^{n+1} with the new state and the dt
+ * reduction); 0 stops and drops the record.  dg_moving_timing synchronises the
+ * device and writes the average duration of each of the four, in ms, over the
+ * steps timed since the last call into avg_ms[4] (and their count into
+ * *nsteps when not NULL), then starts a fresh record.  DG_EUNSUPPORTED on
+ * other kinds. */
+dg_status dg_set_moving_timing(dg_mesh_t mesh, int on);
+dg_status dg_moving_timing(dg_mesh_t mesh, double* avg_ms, int* nsteps);
+
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* dg_last_error(void);
 

@@ -96,6 +96,8 @@ SYMBOLS = [
     ("dg_get_tiling", ctypes.c_int, [ctypes.c_void_p]),
     ("dg_check", ctypes.c_int, [ctypes.c_void_p]),
     ("dg_set_mesh_motion", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("dg_set_moving_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("dg_moving_timing", ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int)]),
     ("dg_mesh_geometry", ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp,
                                         ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),

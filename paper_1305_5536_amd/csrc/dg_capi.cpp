@@ -42,6 +42,8 @@ hipError_t moving_init(dg_mesh* m);
 int moving_read(const dg_mesh* m, double* gen, double* vol, double* cen, int32_t* ring,
                 int32_t* deg);
 void moving_set_motion(dg_mesh* m, int motion);
+void moving_set_timing(dg_mesh* m, int on);
+int moving_timing(dg_mesh* m, double* avg_ms, int* nsteps);
 dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d);
 void facelist_destroy(dg_mesh* m);
 hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
@@ -824,6 +826,27 @@ dg_status dg_set_mesh_motion(dg_mesh_t m, int motion) {
   }
   if (motion != 0 && motion != 1) return einval("dg_set_mesh_motion: motion must be 0 or 1");
   moving_set_motion(m, motion);
+  return DG_OK;
+}
+
+dg_status dg_set_moving_timing(dg_mesh_t m, int on) {
+  if (!m) return einval("dg_set_moving_timing: NULL handle");
+  if (m->kind != 3) {
+    set_error("dg_set_moving_timing: built for moving meshes");
+    return DG_EUNSUPPORTED;
+  }
+  moving_set_timing(m, on);
+  return DG_OK;
+}
+
+dg_status dg_moving_timing(dg_mesh_t m, double* avg_ms, int* nsteps) {
+  if (!m || !avg_ms) return einval("dg_moving_timing: NULL argument");
+  if (m->kind != 3) {
+    set_error("dg_moving_timing: built for moving meshes");
+    return DG_EUNSUPPORTED;
+  }
+  const int r = moving_timing(m, avg_ms, nsteps);
+  if (r) return hip_fail((hipError_t)r, "dg_moving_timing");
   return DG_OK;
 }
 

@@ -6,10 +6,12 @@
 // step).  Every step rebuilds it on the GPU, one thread per cell, with no
 // atomics and no global triangulation:
 //   * the cell of generator i is the intersection of the half-planes closer to
-//     i than to each candidate j, clipped from a bounding square (a convex
-//     polygon clip per candidate); the candidates are i's neighbours and their
+//     i than to each candidate j; the candidates are i's neighbours and their
 //     neighbours in the previous mesh (a cell's new neighbours over one CFL
-//     step were among them);
+//     step were among them).  Its faces are found by walking around it
+//     counter-clockwise from the nearest candidate: the next face is the
+//     candidate whose bisector first cuts the current face's bisector (no
+//     polygon is stored, only the ring of neighbours);
 //   * each Voronoi vertex is then recomputed as the circumcentre of its three
 //     generators, in the frame of the smallest of the three indices, so that
 //     every cell that shares a vertex or a face derives it from the same
@@ -28,7 +30,7 @@
 //              conserved coefficients, or the WENO-type limiter on primitive
 //              variables with a least-squares stencil slope), and the
 //              generator positions at t^{n+1/2} and t^{n+1};
-//   k_mv_mesh  the mesh of the half-step generators;
+//   k_mv_walk, k_mv_geom  the mesh of the half-step generators;
 //   k_mv_upd   per cell of the half-step mesh: for each face and Gauss point,
 //              both cells' half-step primitive predictions (centred at the
 //              t^n centroids) at the point, boosted into the frame of the face
@@ -38,7 +40,7 @@
 //              cell's 4-point rule; out: the conserved totals V^n ubar +
 //              dt (...) and the first moments about the cell's origin carried
 //              along with w_e (c^n + t w_e);
-//   k_mv_mesh  the mesh of t^{n+1}, then the new state: means = totals /
+//   k_mv_walk, k_mv_geom  the mesh of t^{n+1}, then the new state: means = totals /
 //              V^{n+1}, gradients = (M^{n+1})^-1 (moments - (c^{n+1} - c^n -
 //              dt w_e) totals), and the cell's CFL bound.
 // Geometry is FP64 (absolute positions in a box); the state is T.
@@ -57,8 +59,7 @@
 namespace dg {
 
 constexpr int kRing = 16;  // neighbours a cell may have
-constexpr int kCand = 64;  // distinct candidates of one clip
-constexpr int kPoly = 32;  // vertices of a polygon during the clip
+constexpr int kPoly = kRing + 1;  // ring entries during the walk
 constexpr int kGeo = 6;    // V, centroid - generator (2), Mxx, Mxy, Myy
 
 struct MVDev {
@@ -71,6 +72,8 @@ struct MVDev {
   int* deg[3] = {nullptr, nullptr, nullptr};     // [n]
   double* geo[3] = {nullptr, nullptr, nullptr};  // [kGeo][n]
   void* ua = nullptr;                            // limited state
+  bool timing = false;                           // record events around each kernel
+  std::vector<hipEvent_t> ev;                    // 5 per timed step
 };
 
 namespace {
@@ -402,95 +405,124 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
 }
 
 // ----------------------------------------------------------------- mesh --
-// Voronoi cell of every generator of positions `x` by clipping against the
-// 2-ring of the mesh `src`; writes the ring, degree and geometry of `dst`.
-// FINISH: also turns the totals and moments in p.out into the new state (the
-// mesh of t^n in p.s0, the limited state p.ua for w_e), and writes the cell's
-// CFL bound into the per-wave minima when p.dtpart is set.
+// The mesh of the positions dst.x in two launches.  k_mv_walk: the ring of
+// every cell from the 2-ring of the mesh `src` (written to dst.ring, dst.deg).
+// k_mv_geom: the cell geometry from the ring (canonical vertices, polygon
+// moments); with FINISH also the new state from the totals and moments in
+// p.out (the mesh of t^n in p.s0, the limited state p.ua for w_e) and the
+// cell's CFL bound in the per-wave minima when p.dtpart is set.  Split in two
+// so that the walk, a chain of dependent gathers, runs at a higher occupancy
+// than the register-heavy geometry and update.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < p.n) {
+    const int n = p.n;
+    const double* X = dst.x;
+    const double xe = X[e], ye = X[n + e];
+    bool bad = false;
+    // The cell is walked counter-clockwise, one face at a time, over the
+    // candidates k (the previous neighbours and their neighbours, in src).  The
+    // nearest candidate is a neighbour (the midpoint of the two generators lies
+    // on their common face).  The face of neighbour j lies on the bisector
+    // x(t) = d_j/2 + t perp(d_j), perp(d) = (-d_y, d_x); candidate k bounds it
+    // from the counter-clockwise side at t_k = (|d_k|^2 - d_j . d_k) / (2
+    // perp(d_j) . d_k) when perp(d_j) . d_k > 0, and the next neighbour is the
+    // candidate with the smallest t_k.  The walk ends back at the first
+    // neighbour; nothing but the ring is stored.
+    const int d0 = min(src.deg[e], kRing);
+    const double iLx = 1.0 / p.Lx, iLy = 1.0 / p.Ly;
+    int j0 = -1;
+    double best = 1e300;
+    for (int a = 0; a < d0; ++a) {
+      const int j = src.ring[e * kRing + a];
+      const int dj = min(src.deg[j], kRing);
+      for (int b = -1; b < dj; ++b) {
+        const int k = b < 0 ? j : src.ring[j * kRing + b];
+        if (k == e) continue;
+        double dx = X[k] - xe, dy = X[n + k] - ye;
+        dx -= p.Lx * rint(dx * iLx);
+        dy -= p.Ly * rint(dy * iLy);
+        const double dd = dx * dx + dy * dy;
+        if (dd < best || (dd == best && k < j0)) {
+          best = dd;
+          j0 = k;
+        }
+      }
+    }
+    bad |= j0 < 0;
+    int ring[kPoly];
+    int d = 0;
+    int cur = j0;
+    while (!bad) {
+      if (d > kRing) {
+        bad = true;
+        break;
+      }
+      ring[d++] = cur;
+      double cx = X[cur] - xe, cy = X[n + cur] - ye;
+      cx -= p.Lx * rint(cx * iLx);
+      cy -= p.Ly * rint(cy * iLy);
+      // smallest t_k = num_k / (2 den_k), compared as num_k den_b < num_b den_k
+      int nxt = -1;
+      double nb_ = 1.0, db_ = 0.0;
+      for (int a = 0; a < d0; ++a) {
+        const int j = src.ring[e * kRing + a];
+        const int dj = min(src.deg[j], kRing);
+        for (int b = -1; b < dj; ++b) {
+          const int k = b < 0 ? j : src.ring[j * kRing + b];
+          if (k == e || k == cur) continue;
+          double kx = X[k] - xe, ky = X[n + k] - ye;
+          kx -= p.Lx * rint(kx * iLx);
+          ky -= p.Ly * rint(ky * iLy);
+          const double den = cx * ky - cy * kx;  // perp(d_cur) . d_k
+          if (!(den > 0.0)) continue;
+          const double num = kx * kx + ky * ky - (cx * kx + cy * ky);
+          const double l = num * db_, r = nb_ * den;
+          if (nxt < 0 || l < r || (l == r && k < nxt)) {
+            nb_ = num;
+            db_ = den;
+            nxt = k;
+          }
+        }
+      }
+      if (nxt < 0) {
+        bad = true;
+        break;
+      }
+      if (nxt == j0) break;
+      cur = nxt;
+    }
+    bad |= d > kRing;
+    if (!bad) {
+      for (int k = 0; k < d; ++k) dst.ring[e * kRing + k] = ring[k];
+      for (int k = d; k < kRing; ++k) dst.ring[e * kRing + k] = -1;
+      dst.deg[e] = d;
+    } else {
+      dst.deg[e] = 0;
+      for (int k = 0; k < kRing; ++k) dst.ring[e * kRing + k] = -1;
+      atomicOr(p.status, 2);
+    }
+  }
+}
+
 template <typename T, bool FINISH>
-__global__ __launch_bounds__(256) void k_mv_mesh(PM<T> p, MSet src, MOut dst) {
+__global__ __launch_bounds__(256) void k_mv_geom(PM<T> p, MOut dst) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   double dtb = 1e300;
   if (e < p.n) {
     const int n = p.n;
     const double* X = dst.x;
     const double xe = X[e], ye = X[n + e];
-    bool bad = false;
-    // candidates: neighbours and neighbours of neighbours in src
-    int cand[kCand];
-    int nc = 0;
-    const int d0 = min(src.deg[e], kRing);
-    for (int a = -1; a < d0; ++a) {
-      const int j = a < 0 ? e : src.ring[e * kRing + a];
-      const int dj = min(src.deg[j], kRing);
-      for (int b = -1; b < dj; ++b) {
-        const int k = b < 0 ? j : src.ring[j * kRing + b];
-        if (k == e) continue;
-        bool seen = false;
-        for (int c = 0; c < nc; ++c) seen |= cand[c] == k;
-        if (seen) continue;
-        if (nc == kCand) {
-          bad = true;
-          continue;
-        }
-        cand[nc++] = k;
-      }
-    }
-    // clip a bounding square by the bisector half-planes
-    double R = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      const int j = cand[c];
-      R = fmax(R, fmax(fabs(mimg(X[j] - xe, p.Lx)), fabs(mimg(X[n + j] - ye, p.Ly))));
-    }
-    R = 2.0 * R + 1e-300;
-    double px[2][kPoly], py[2][kPoly];
-    int pt[2][kPoly];
-    int m = 4, cb = 0;
-    px[0][0] = -R; py[0][0] = -R; pt[0][0] = -1;
-    px[0][1] = R;  py[0][1] = -R; pt[0][1] = -1;
-    px[0][2] = R;  py[0][2] = R;  pt[0][2] = -1;
-    px[0][3] = -R; py[0][3] = R;  pt[0][3] = -1;
-    for (int c = 0; c < nc && !bad; ++c) {
-      const int j = cand[c];
-      const double dx = mimg(X[j] - xe, p.Lx), dy = mimg(X[n + j] - ye, p.Ly);
-      const double h2 = 0.5 * (dx * dx + dy * dy);
-      bool cut = false;
-      for (int k = 0; k < m; ++k) cut |= px[cb][k] * dx + py[cb][k] * dy - h2 > 0.0;
-      if (!cut) continue;
-      const int nb = cb ^ 1;
-      int mo = 0;
-      for (int k = 0; k < m && !bad; ++k) {
-        const int k1 = k + 1 == m ? 0 : k + 1;
-        const double ax = px[cb][k], ay = py[cb][k], bx = px[cb][k1], by = py[cb][k1];
-        const double sa = ax * dx + ay * dy - h2, sb = bx * dx + by * dy - h2;
-        if (sa <= 0.0) {
-          if (mo == kPoly) { bad = true; break; }
-          px[nb][mo] = ax; py[nb][mo] = ay; pt[nb][mo] = pt[cb][k]; ++mo;
-          if (sb > 0.0) {
-            if (mo == kPoly) { bad = true; break; }
-            const double t = sa / (sa - sb);
-            px[nb][mo] = ax + t * (bx - ax); py[nb][mo] = ay + t * (by - ay); pt[nb][mo] = j; ++mo;
-          }
-        } else if (sb <= 0.0) {
-          if (mo == kPoly) { bad = true; break; }
-          const double t = sa / (sa - sb);
-          px[nb][mo] = ax + t * (bx - ax); py[nb][mo] = ay + t * (by - ay); pt[nb][mo] = pt[cb][k];
-          ++mo;
-        }
-      }
-      m = mo;
-      cb = nb;
-      if (m < 3) bad = true;
-    }
-    // the ring: the tags in counter-clockwise order, tiny faces dropped
-    int ring[kPoly];
-    int d = 0;
-    for (int k = 0; k < m && !bad; ++k) {
-      bad |= pt[cb][k] < 0;
-      ring[d++] = pt[cb][k];
-    }
+    int d = dst.deg[e];
+    bool bad = d < 3 || d > kRing;
+    int ring[kRing];
+    for (int k = 0; k < kRing; ++k) ring[k] = dst.ring[e * kRing + k];
     if (!bad) {
-      int keep[kPoly];
+      // drop the faces shorter than 1e-10 of their generators' distance (their
+      // existence is decided by rounding); both cells of such a face decide it
+      // from the same canonical operands
+      int keep[kRing];
       int dk = 0;
       for (int k = 0; k < d; ++k) {
         const int j = ring[k];
@@ -500,11 +532,20 @@ __global__ __launch_bounds__(256) void k_mv_mesh(PM<T> p, MSet src, MOut dst) {
                       ring[k + 1 == d ? 0 : k + 1], g);
         if (g.A >= 1e-10 * sqrt(g.dx * g.dx + g.dy * g.dy)) keep[dk++] = j;
       }
+      for (int k = 0; k < dk; ++k)
+        for (int k2 = k + 1; k2 < dk; ++k2) bad |= keep[k] == keep[k2];
+      bad |= dk < 3;
+      if (dk != d && !bad) {
+        for (int k = 0; k < dk; ++k) dst.ring[e * kRing + k] = keep[k];
+        for (int k = dk; k < kRing; ++k) dst.ring[e * kRing + k] = -1;
+        dst.deg[e] = dk;
+      }
       d = dk;
       for (int k = 0; k < d; ++k) ring[k] = keep[k];
-      for (int k = 0; k < d; ++k)
-        for (int k2 = k + 1; k2 < d; ++k2) bad |= ring[k] == ring[k2];
-      bad |= d < 3 || d > kRing;
+      if (bad) {
+        dst.deg[e] = 0;
+        atomicOr(p.status, 2);
+      }
     }
     double geo[kGeo] = {0, 0, 0, 0, 0, 0};
     double vx[kRing], vy[kRing];
@@ -513,21 +554,17 @@ __global__ __launch_bounds__(256) void k_mv_mesh(PM<T> p, MSet src, MOut dst) {
         circumcentre(X, n, p.Lx, p.Ly, e, ring[k == 0 ? d - 1 : k - 1], ring[k], e, vx[k], vy[k]);
       polygon_moments(vx, vy, d, geo);
       bad |= !(geo[0] > 0.0) || !(geo[3] * geo[5] - geo[4] * geo[4] > 0.0);
+      if (bad) atomicOr(p.status, 2);
     }
-    if (!bad) {
-      for (int k = 0; k < d; ++k) dst.ring[e * kRing + k] = ring[k];
-      for (int k = d; k < kRing; ++k) dst.ring[e * kRing + k] = -1;
-      dst.deg[e] = d;
-    } else {
+    if (bad) {
       d = 0;
-      dst.deg[e] = 0;
-      for (int k = 0; k < kRing; ++k) dst.ring[e * kRing + k] = -1;
       geo[0] = 1.0;
       geo[1] = geo[2] = geo[4] = 0.0;
       geo[3] = geo[5] = 1.0;
     }
     for (int k = 0; k < kGeo; ++k) dst.geo[(size_t)k * n + e] = geo[k];
-    if (bad) atomicOr(p.status, 2);
+    (void)xe;
+    (void)ye;
     if (FINISH) {
       const double dt = step_size(p);
       T Q[12];
@@ -880,21 +917,39 @@ hipError_t step_t(dg_mesh* m, const void* in, void* out, const double* dt_dev, d
   p.dt_host = dt_host;
   p.write_pos = 1;
   const dim3 g((p.n + 255) / 256), b(256);
-  hipError_t e = lim_launch(p, m->cfg.limiter, s);
+  hipEvent_t ev[4];
+  int nev = 0;
+  auto mark = [&]() {
+    if (!v.timing) return hipSuccess;
+    hipError_t r = hipEventCreate(&ev[nev]);
+    if (r == hipSuccess) r = hipEventRecord(ev[nev], s);
+    if (r == hipSuccess) ++nev;
+    return r;
+  };
+  hipError_t e = mark();
+  if (e == hipSuccess) e = lim_launch(p, m->cfg.limiter, s);
+  if (e == hipSuccess) e = mark();
   if (e != hipSuccess) return e;
   // mesh of the half-step generators (candidates from t^n)
-  hipLaunchKernelGGL((k_mv_mesh<T, false>), g, b, 0, s, p, p.s0,
-                     MOut{v.pos[1], v.ring[1], v.deg[1], v.geo[1]});
+  const MOut half{v.pos[1], v.ring[1], v.deg[1], v.geo[1]};
+  hipLaunchKernelGGL((k_mv_walk<T>), g, b, 0, s, p, p.s0, half);
+  hipLaunchKernelGGL((k_mv_geom<T, false>), g, b, 0, s, p, half);
+  e = mark();
+  if (e != hipSuccess) return e;
   if (m->cfg.flux == DG_FLUX_EXACT)
     hipLaunchKernelGGL((k_mv_upd<T, 1>), g, b, 0, s, p);
   else
     hipLaunchKernelGGL((k_mv_upd<T, 0>), g, b, 0, s, p);
+  e = mark();
+  if (e != hipSuccess) return e;
   // mesh of t^{n+1} (candidates from the half step) and the new state
   if (want_dt) p.dtpart = m->dtpart;
-  hipLaunchKernelGGL((k_mv_mesh<T, true>), g, b, 0, s, p, p.sh,
-                     MOut{v.pos[v.nxt], v.ring[v.nxt], v.deg[v.nxt], v.geo[v.nxt]});
+  const MOut next{v.pos[v.nxt], v.ring[v.nxt], v.deg[v.nxt], v.geo[v.nxt]};
+  hipLaunchKernelGGL((k_mv_walk<T>), g, b, 0, s, p, p.sh, next);
+  hipLaunchKernelGGL((k_mv_geom<T, true>), g, b, 0, s, p, next);
   e = hipGetLastError();
   if (e == hipSuccess) std::swap(v.cur, v.nxt);
+  for (int k = 0; k < nev; ++k) v.ev.push_back(ev[k]);
   return e;
 }
 
@@ -920,6 +975,14 @@ hipError_t launch_moving(dg_mesh* m, int mode, const void* in, void* out, const 
                      : step_t<float>(m, in, out, dt_dev, dt_host, dt_next != nullptr, s);
   if (e == hipSuccess && dt_next)
     e = launch_min_finalize(m->dtpart, (int)((m->ncells + 63) / 64), cfl, dt_next, s);
+  MVDev& v = *m->mvd;
+  if (e == hipSuccess && v.timing) {
+    // the fifth event closes the new-mesh kernel and the dt reduction
+    hipEvent_t last;
+    e = hipEventCreate(&last);
+    if (e == hipSuccess) e = hipEventRecord(last, s);
+    if (e == hipSuccess) v.ev.push_back(last);
+  }
   return e;
 }
 
@@ -944,6 +1007,7 @@ hipError_t launch_moving_cfl(const dg_mesh* m, const void* U, double cfl, double
 void moving_destroy(dg_mesh* m) {
   if (!m->mvd) return;
   MVDev& v = *m->mvd;
+  for (hipEvent_t e : v.ev) (void)hipEventDestroy(e);
   for (int k = 0; k < 3; ++k) {
     (void)hipFree(v.pos[k]);
     (void)hipFree(v.ring[k]);
@@ -1057,9 +1121,10 @@ hipError_t moving_init(dg_mesh* m) {
   p.Ly = v.box[1];
   p.gamma = m->cfg.gamma;
   const dim3 g((v.n + 255) / 256), b(256);
-  hipLaunchKernelGGL((k_mv_mesh<double, false>), g, b, 0, nullptr, p,
-                     MSet{v.pos[0], v.ring[1], v.deg[1], v.geo[1]},
-                     MOut{v.pos[0], v.ring[0], v.deg[0], v.geo[0]});
+  const MOut first{v.pos[0], v.ring[0], v.deg[0], v.geo[0]};
+  hipLaunchKernelGGL((k_mv_walk<double>), g, b, 0, nullptr, p,
+                     MSet{v.pos[0], v.ring[1], v.deg[1], v.geo[1]}, first);
+  hipLaunchKernelGGL((k_mv_geom<double, false>), g, b, 0, nullptr, p, first);
   return hipGetLastError();
 }
 
@@ -1098,5 +1163,35 @@ int moving_read(const dg_mesh* m, double* gen, double* vol, double* cen, int32_t
 }
 
 void moving_set_motion(dg_mesh* m, int motion) { m->mvd->motion = motion ? 1 : 0; }
+
+static void drop_events(MVDev& v) {
+  for (hipEvent_t e : v.ev) (void)hipEventDestroy(e);
+  v.ev.clear();
+}
+
+void moving_set_timing(dg_mesh* m, int on) {
+  drop_events(*m->mvd);
+  m->mvd->timing = on != 0;
+}
+
+// Average durations (ms) of the four kernels of the timed steps since the
+// last call, then a fresh record.
+int moving_timing(dg_mesh* m, double* avg_ms, int* nsteps) {
+  MVDev& v = *m->mvd;
+  hipError_t e = hipDeviceSynchronize();
+  const int ns = (int)(v.ev.size() / 5);
+  double acc[4] = {0, 0, 0, 0};
+  for (int k = 0; k < ns && e == hipSuccess; ++k)
+    for (int j = 0; j < 4 && e == hipSuccess; ++j) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, v.ev[5 * k + j], v.ev[5 * k + j + 1]);
+      acc[j] += ms;
+    }
+  drop_events(v);
+  if (e != hipSuccess) return (int)e;
+  for (int j = 0; j < 4; ++j) avg_ms[j] = ns ? acc[j] / ns : 0.0;
+  if (nsteps) *nsteps = ns;
+  return 0;
+}
 
 }  // namespace dg

@@ -328,6 +328,19 @@ class Solver:
         """Moving meshes: 1 moves the generators with the flow, 0 holds them."""
         C.check(C.lib().dg_set_mesh_motion(self._h, int(motion)), "dg_set_mesh_motion")
 
+    def set_timing(self, on: bool) -> None:
+        """Moving meshes: record HIP events around the four kernels of each step."""
+        C.check(C.lib().dg_set_moving_timing(self._h, int(bool(on))), "dg_set_moving_timing")
+
+    def kernel_times(self):
+        """Moving meshes: (average ms of the limiter, half-step mesh, update and
+        new-mesh kernels over the steps timed since the last call, step count)."""
+        ms = np.zeros(4)
+        ns = ctypes.c_int()
+        C.check(C.lib().dg_moving_timing(self._h, _f64p(ms), ctypes.byref(ns)),
+                "dg_moving_timing")
+        return ms, ns.value
+
     def geometry(self) -> dict:
         """Moving meshes: host copy of the current generators, volumes,
         centroids (generator + offset, not wrapped) and neighbour rings."""

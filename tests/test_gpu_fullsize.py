@@ -9,6 +9,9 @@
 * C3 256^3 MHD: one FP64 step against the oracle, every cell.
 * 2D MHD Orszag-Tang at the paper's 512^2: two FP64 steps (limiter on, fused
   CFL minima, device step sizes) against the oracle, every cell.
+* The moving Voronoi mesh at the paper's Kelvin-Helmholtz size (512^2 = 262144
+  cells): two FP64 steps with the device step size and fused CFL, every cell
+  and the rebuilt mesh compared with the oracle's; FP32 stated.
 * C5 (256 instances, N in {64..512}): the full batch in its bench launch shape;
   four sampled instances (the first, the largest and two others) carry the
   seeded recipe and are compared with the oracle; the others hold a uniform
@@ -176,6 +179,42 @@ def test_orszag_tang_512_full_size(oracle, torch_cuda):
         print(f"Orszag-Tang 512^2 {prec}, 2 steps, per-field error: {e}, B: {eb:.3e}")
         assert e.max() < tol and eb < tol, (prec, e, eb)
         s.close()
+
+
+def test_moving_kh_full_size(oracle, torch_cuda):
+    torch = torch_cuda
+    from oracle import moving as mv
+    from paper_1305_5536_amd.solver import Solver, moving
+    from workloads.voronoi import kh_voronoi_state, periodic_voronoi
+    n = 262144
+    mesh = periodic_voronoi(n, seed=1006)
+    U0 = kh_voronoi_state(mesh, G53)
+    d = mv.voronoi(mesh["generators"], mesh["box"])
+    dt0 = mv.cfl_dt(d, U0, G53, 0.3)
+    ref, d1 = mv.step(d, U0, dt0, G53, "weno", "exact")
+    dt1 = mv.cfl_dt(d1, ref, G53, 0.3)
+    ref, d2 = mv.step(d1, ref, dt1, G53, "weno", "exact")
+    h = 1.0 / math.sqrt(n)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-4)):
+        s = Solver(moving(mesh), precision=prec, limiter="weno", gamma=G53, flux="exact")
+        U = s.to_device(U0)
+        V = s.empty()
+        dt = s.cfl_dt(U, 0.3)
+        if prec == "fp64":
+            assert abs(float(dt.cpu()) - dt0) <= 1e-13 * dt0
+        for _ in range(2):
+            s.step_mh(U, dt, out=V, cfl=0.3, dt_next=dt)
+            U, V = V, U
+        s.check()
+        e = errs_hydro(U.double().cpu().numpy(), ref, 4, 2, h, 12)
+        print(f"moving KH 512^2, 2 steps, {prec}: {e}")
+        assert e.max() < tol, (prec, e)
+        if prec == "fp64":
+            geo = s.geometry()
+            assert np.abs(geo["volume"] - d2["cell_volume"]).max() < 1e-13 * h * h
+            nb = mv.neighbours(d2)
+            assert all(sorted(geo["ring"][i, :geo["degree"][i]].tolist()) == nb[i]
+                       for i in range(0, n, 97))
 
 
 def test_c5_full_batch_sampled(oracle, torch_cuda):

@@ -228,3 +228,35 @@ def test_refused(mv, torch_cuda):
     c = Solver(cartesian((8, 8), (0, 0), (1, 1)), gamma=G53)
     with pytest.raises(DGError):
         c.set_motion(0)
+
+
+def test_kernel_timing(mv, torch_cuda):
+    """dg_set_moving_timing / dg_moving_timing: four positive averages over the
+    timed steps, a fresh record after each read, and results unchanged."""
+    d = mv.voronoi(periodic_voronoi(500, seed=21)["generators"], (1.0, 1.0))
+    U0 = random_voronoi_state(d, G53, seed=22, amp=0.2)
+    dt = mv.cfl_dt(d, U0, G53, 0.3)
+    a, b = _solver(d), _solver(d)
+    ua, ub = a.to_device(U0), b.to_device(U0)
+    b.set_timing(True)
+    ra = a.step_mh(ua, dt)
+    rb = b.step_mh(ub, dt)
+    b.step_mh(rb, dt)
+    ms, n = b.kernel_times()
+    assert n == 2 and np.all(ms > 0), (ms, n)
+    ms, n = b.kernel_times()
+    assert n == 0 and np.all(ms == 0)
+    b.set_timing(False)
+    a.check()
+    b.check()
+    U1, _ = mv.step(d, U0, dt, G53, "weno", "exact")
+    # the first timed step of b computes what a's untimed step does
+    b2 = _solver(d)
+    b2.set_timing(True)
+    assert np.array_equal(b2.step_mh(b2.to_device(U0), dt).cpu().numpy(), ra.cpu().numpy())
+    assert field_errors(ra.cpu().numpy(), U1, 1.0 / math.sqrt(500)).max() < 1e-12
+    from paper_1305_5536_amd.capi import DGError
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    c = Solver(cartesian((8, 8), (0, 0), (1, 1)), gamma=G53)
+    with pytest.raises(DGError):
+        c.set_timing(True)

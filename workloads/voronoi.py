@@ -225,3 +225,23 @@ def random_voronoi_state(mesh, gamma, seed, amp=0.1):
         return [rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)]
 
     return project_voronoi(f, mesh)
+
+
+def kh_voronoi_state(mesh, gamma=5.0 / 3.0, w0=0.1, sigma=0.5 / math.sqrt(2.0)):
+    """The Kelvin-Helmholtz setup of Sec. 3.6 on a periodic unit box: p = 2.5;
+    rho = 2, v_x = 0.5 in the strip |y - 1/2| < 1/4, rho = 1, v_x = -0.5 outside;
+    v_y = w0 sin(4 pi x) (exp(-(y - 1/4)^2 / (2 sigma^2)) + exp(-(y - 3/4)^2 /
+    (2 sigma^2))).  Readings of the printed text: gamma 5/3 (printed "5.3") and a
+    Gaussian exp(-(y - y0)^2 / (2 sigma^2)) (the printed exponent carries an
+    extra minus sign)."""
+
+    def f(X, Y):
+        inside = np.abs(Y - 0.5) < 0.25
+        rho = np.where(inside, 2.0, 1.0)
+        u = np.where(inside, 0.5, -0.5)
+        v = w0 * np.sin(4 * math.pi * X) * (np.exp(-(Y - 0.25) ** 2 / (2 * sigma ** 2)) +
+                                           np.exp(-(Y - 0.75) ** 2 / (2 * sigma ** 2)))
+        p = 2.5 + 0.0 * X
+        return [rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)]
+
+    return project_voronoi(f, mesh)
