@@ -23,7 +23,10 @@
 //     a moving mesh recomputes every step) are the exact polygon moments.
 // A cell whose candidates do not bound it, a polygon beyond the capacities
 // below, or a neighbour that does not list the cell back, latches status bit 2
-// (reported by dg_check).
+// (reported by dg_check).  Every kernel maps its blocks XCD by XCD
+// (xcd_remap): with cells numbered along a space-filling curve each XCD's L2
+// then holds the positions, rings and states of one compact region, which the
+// neighbour gathers reuse.
 //
 // One step, n -> n+1 (sets: t^n, the half step, t^{n+1}):
 //   k_mv_lim   limiter on the mesh of t^n (none, the Arepo limiter on the
@@ -254,7 +257,7 @@ __device__ __forceinline__ void prim4(const T* m, T gm1, T* w) {
 // cell back.
 template <typename T, int LIM>
 __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (e >= p.n) return;
   const int n = p.n;
   T q[12];
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
 // than the register-heavy geometry and update.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (e < p.n) {
     const int n = p.n;
     const double* X = dst.x;
@@ -508,7 +511,7 @@ __global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
 
 template <typename T, bool FINISH>
 __global__ __launch_bounds__(256) void k_mv_geom(PM<T> p, MOut dst) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   double dtb = 1e300;
   if (e < p.n) {
     const int n = p.n;
@@ -721,7 +724,7 @@ __device__ __forceinline__ void riemann_n(const T* uL, const T* uR, T nx, T ny, 
 
 template <typename T, int RS>
 __global__ __launch_bounds__(256) void k_mv_upd(PM<T> p) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (e >= p.n) return;
   const int n = p.n;
   const double dt = step_size(p);
@@ -849,7 +852,7 @@ __global__ __launch_bounds__(256) void k_mv_upd(PM<T> p) {
 // CFL bound on the mesh of t^n (dg_cfl_dt).
 template <typename T>
 __global__ __launch_bounds__(256) void k_mv_cfl(PM<T> p) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   double dtb = 1e300;
   if (e < p.n) {
     const int n = p.n;
