@@ -64,6 +64,7 @@ namespace dg {
 constexpr int kRing = 16;  // neighbours a cell may have
 constexpr int kPoly = kRing + 1;  // ring entries during the walk
 constexpr int kGeo = 6;    // V, centroid - generator (2), Mxx, Mxy, Myy
+constexpr int kChunk = 4;  // candidates gathered together in the walk
 
 struct MVDev {
   int n = 0;
@@ -424,35 +425,61 @@ __global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
     const double* X = dst.x;
     const double xe = X[e], ye = X[n + e];
     bool bad = false;
-    // The cell is walked counter-clockwise, one face at a time, over the
-    // candidates k (the previous neighbours and their neighbours, in src).  The
-    // nearest candidate is a neighbour (the midpoint of the two generators lies
-    // on their common face).  The face of neighbour j lies on the bisector
+    const int d0 = min(src.deg[e], kRing);
+    const double iLx = 1.0 / p.Lx, iLy = 1.0 / p.Ly;
+    // Visit every candidate: the previous neighbours j and the entries of
+    // their rings, kChunk at a time (the ring entries, then their positions, are
+    // loaded together so that the gathers overlap).  f(k, dx, dy) sees each
+    // candidate's offset from this generator (duplicates included: they give
+    // equal values and the index tie-break makes them harmless).
+    auto visit = [&](auto&& f) {
+      for (int a = 0; a < d0; ++a) {
+        const int j = src.ring[e * kRing + a];
+        const int dj = min(src.deg[j], kRing);
+        const int* rj = src.ring + j * kRing;
+        for (int b0 = -1; b0 < dj; b0 += kChunk) {
+          int kk[kChunk];
+          double kx[kChunk], ky[kChunk];
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) {
+            const int b = b0 + q;
+            kk[q] = b < 0 ? j : (b < dj ? rj[b] : -1);
+          }
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) {
+            const int k = kk[q] < 0 ? e : kk[q];
+            kx[q] = X[k];
+            ky[q] = X[n + k];
+          }
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) {
+            const int k = kk[q];
+            if (k < 0 || k == e) continue;
+            double dx = kx[q] - xe, dy = ky[q] - ye;
+            dx -= p.Lx * rint(dx * iLx);
+            dy -= p.Ly * rint(dy * iLy);
+            f(k, dx, dy);
+          }
+        }
+      }
+    };
+    // The cell is walked counter-clockwise, one face at a time.  The nearest
+    // candidate is a neighbour (the midpoint of the two generators lies on
+    // their common face).  The face of neighbour j lies on the bisector
     // x(t) = d_j/2 + t perp(d_j), perp(d) = (-d_y, d_x); candidate k bounds it
     // from the counter-clockwise side at t_k = (|d_k|^2 - d_j . d_k) / (2
     // perp(d_j) . d_k) when perp(d_j) . d_k > 0, and the next neighbour is the
     // candidate with the smallest t_k.  The walk ends back at the first
     // neighbour; nothing but the ring is stored.
-    const int d0 = min(src.deg[e], kRing);
-    const double iLx = 1.0 / p.Lx, iLy = 1.0 / p.Ly;
     int j0 = -1;
     double best = 1e300;
-    for (int a = 0; a < d0; ++a) {
-      const int j = src.ring[e * kRing + a];
-      const int dj = min(src.deg[j], kRing);
-      for (int b = -1; b < dj; ++b) {
-        const int k = b < 0 ? j : src.ring[j * kRing + b];
-        if (k == e) continue;
-        double dx = X[k] - xe, dy = X[n + k] - ye;
-        dx -= p.Lx * rint(dx * iLx);
-        dy -= p.Ly * rint(dy * iLy);
-        const double dd = dx * dx + dy * dy;
-        if (dd < best || (dd == best && k < j0)) {
-          best = dd;
-          j0 = k;
-        }
+    visit([&](int k, double dx, double dy) {
+      const double dd = dx * dx + dy * dy;
+      if (dd < best || (dd == best && k < j0)) {
+        best = dd;
+        j0 = k;
       }
-    }
+    });
     bad |= j0 < 0;
     int ring[kPoly];
     int d = 0;
@@ -469,26 +496,18 @@ __global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
       // smallest t_k = num_k / (2 den_k), compared as num_k den_b < num_b den_k
       int nxt = -1;
       double nb_ = 1.0, db_ = 0.0;
-      for (int a = 0; a < d0; ++a) {
-        const int j = src.ring[e * kRing + a];
-        const int dj = min(src.deg[j], kRing);
-        for (int b = -1; b < dj; ++b) {
-          const int k = b < 0 ? j : src.ring[j * kRing + b];
-          if (k == e || k == cur) continue;
-          double kx = X[k] - xe, ky = X[n + k] - ye;
-          kx -= p.Lx * rint(kx * iLx);
-          ky -= p.Ly * rint(ky * iLy);
-          const double den = cx * ky - cy * kx;  // perp(d_cur) . d_k
-          if (!(den > 0.0)) continue;
-          const double num = kx * kx + ky * ky - (cx * kx + cy * ky);
-          const double l = num * db_, r = nb_ * den;
-          if (nxt < 0 || l < r || (l == r && k < nxt)) {
-            nb_ = num;
-            db_ = den;
-            nxt = k;
-          }
+      visit([&](int k, double kx, double ky) {
+        if (k == cur) return;
+        const double den = cx * ky - cy * kx;  // perp(d_cur) . d_k
+        if (!(den > 0.0)) return;
+        const double num = kx * kx + ky * ky - (cx * kx + cy * ky);
+        const double l = num * db_, r = nb_ * den;
+        if (nxt < 0 || l < r || (l == r && k < nxt)) {
+          nb_ = num;
+          db_ = den;
+          nxt = k;
         }
-      }
+      });
       if (nxt < 0) {
         bad = true;
         break;
