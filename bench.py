@@ -99,17 +99,19 @@ def parse():
     return a
 
 
-def pmc_traffic(profile: str, kernel: str, shape: str, source: str):
+def pmc_traffic(profile: str, kernel: str, shape: str, source: str,
+                what: str = "pmc_traffic_bytes_per_launch"):
     """HBM bytes per launch of ``kernel`` measured with rocprofv3 --pmc
     (FETCH_SIZE and WRITE_SIZE, copy-calibrated) as recorded in the committed
-    profile summary, or None when the kernel source has changed since."""
+    profile summary (or another recorded figure, ``what``), or None when the
+    kernel source has changed since."""
     import hashlib
     try:
         text = open(os.path.join(ROOT, "profiles", profile)).read()
         sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
     except OSError:
         return None
-    want = f"pmc_traffic_bytes_per_launch({kernel}, {shape}): "
+    want = f"{what}({kernel}, {shape}): "
     traffic = None
     for line in text.splitlines():
         if line.startswith(want):
@@ -515,14 +517,15 @@ def bench_c4(a):
     return out
 
 
-# Moving Voronoi mesh: FP64 operations per cell of each kernel of the step
-# (wave-level VALU FP64 instruction counts from rocprofv3 --pmc, times 64 lanes,
-# FMA counted twice, over the cells of a launch; see the kernel profile), and
-# the algorithmic bytes per cell (state, positions, rings and geometry each
-# kernel must read and write once).
+# Moving Voronoi mesh: the four phases of a step (the library's per-kernel
+# events), and the algorithmic bytes per cell of each (state, positions, rings
+# and geometry it must read and write once).  The FP64 operations per cell of
+# each phase (wave-level VALU FP64 instruction counts from rocprofv3 --pmc,
+# times 64 lanes, FMA counted twice) and its measured traffic are read from the
+# committed profile while moving2d.hip is unchanged.
+MOVING_PROFILE = "k_mv_walk_kh_512.md"
 MOVING_KERNELS = ("k_mv_lim", "k_mv_walk + k_mv_geom (half step)", "k_mv_upd",
                   "k_mv_walk + k_mv_geom (new mesh + state)")
-MOVING_FLOPS_PER_CELL = {"k_mv_upd": None}
 MOVING_BYTES_PER_CELL = {"k_mv_lim": 96 + 96 + 16 + 64 + 4 + 48 + 32,
                          "k_mv_walk + k_mv_geom (half step)": 16 + 64 + 4 + 64 + 4 + 48,
                          "k_mv_upd": 96 + 96 + 16 + 16 + 64 + 4 + 48 + 48,
@@ -583,14 +586,21 @@ def bench_moving(a):
     r = run_gpu_moving(mesh, U0, gamma, a.precision, a.steps, a.warmup)
     km = r["kernel_ms"]
     dom = max(km, key=km.get)
-    flops = MOVING_FLOPS_PER_CELL.get(dom)
     avg = km[dom] * 1e-3
+    src = "paper_1305_5536_amd/csrc/moving2d.hip"
+    shape = f"{int(round(n ** 0.5))}x{int(round(n ** 0.5))}"
+    flops = traffic = None
+    if a.precision == "fp64":
+        flops = pmc_traffic(MOVING_PROFILE, dom, shape, src, what="pmc_flops_per_cell")
+        traffic = pmc_traffic(MOVING_PROFILE, dom, shape, src)
     if flops:
-        peak = FP64_VALU_PEAK_TFLOPS if a.precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+        # latency-bound gathers: reported against the FP64 VALU peak with the
+        # executed FP64 work per cell of the phase (PMC)
         achieved = flops * n / avg / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": dom,
-                "flops_per_launch": flops * n, "avg_launch_s": avg}
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": dom, "flops_per_launch": flops * n, "avg_launch_s": avg,
+                "algorithmic_bytes_per_launch": MOVING_BYTES_PER_CELL[dom] * n}
     else:
         elem = 8 if a.precision == "fp64" else 4
         per = MOVING_BYTES_PER_CELL[dom] * n
