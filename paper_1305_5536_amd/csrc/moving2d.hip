@@ -264,12 +264,11 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
   T q[12];
   load12(p.in, n, e, q);
   const MSet& s = p.s0;
-  int nb[kRing];
-  double vx[kRing], vy[kRing];
-  const int d = cell_polygon(s, n, p.Lx, p.Ly, e, vx, vy, nb);
+  const int* re = s.ring + e * kRing;
+  const int d = min(s.deg[e], kRing);
   bool meshbad = s.deg[e] > kRing || s.deg[e] < 3;
   for (int k = 0; k < d; ++k) {
-    const int j = nb[k];
+    const int j = re[k];
     bool back = false;
     const int dj = min(s.deg[j], kRing);
     for (int a = 0; a < dj; ++a) back |= s.ring[j * kRing + a] == e;
@@ -277,54 +276,67 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
   }
   if (meshbad) atomicOr(p.status, 2);
   const double dcx = s.geo[1 * n + e], dcy = s.geo[2 * n + e];
+  // The faces are visited in passes that recompute what they need (the face
+  // centroid from the two circumcentres that end the face, the neighbour's
+  // centroid offset and means) instead of keeping per-face arrays, which
+  // would live in per-lane scratch memory.
+  // Face centroids, in order: vertex k is the circumcentre of (e, ring[k-1],
+  // ring[k]); face k runs from vertex k to vertex k+1.
+  auto faces = [&](auto&& f) {
+    if (d < 3) return;
+    double ax, ay;
+    circumcentre(s.x, n, p.Lx, p.Ly, e, re[d - 1], re[0], e, ax, ay);
+    const double a0x = ax, a0y = ay;
+    for (int k = 0; k < d; ++k) {
+      double bx = a0x, by = a0y;
+      if (k + 1 < d) circumcentre(s.x, n, p.Lx, p.Ly, e, re[k], re[k + 1], e, bx, by);
+      f(k, re[k], (T)(0.5 * (ax + bx) - dcx), (T)(0.5 * (ay + by) - dcy));
+      ax = bx;
+      ay = by;
+    }
+  };
   if (LIM != 0) {
     const T gm1 = p.gamma - T(1);
-    // face-centroid and neighbour-centroid offsets from this cell's centroid
-    T rfx[kRing], rfy[kRing], dnx[kRing], dny[kRing];
-    for (int k = 0; k < d; ++k) {
-      const int k1 = k + 1 == d ? 0 : k + 1;
-      const int j = nb[k];
-      rfx[k] = (T)(0.5 * (vx[k] + vx[k1]) - dcx);
-      rfy[k] = (T)(0.5 * (vy[k] + vy[k1]) - dcy);
-      dnx[k] = (T)(mimg(s.x[j] - s.x[e], p.Lx) + s.geo[1 * n + j] - dcx);
-      dny[k] = (T)(mimg(s.x[n + j] - s.x[n + e], p.Ly) + s.geo[2 * n + j] - dcy);
-    }
     if (LIM == 1) {
-      T hi[4], lo[4];
+      T hi[4], lo[4], alpha[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
+      for (int v = 0; v < 4; ++v) {
+        hi[v] = lo[v] = q[3 * v];
+        alpha[v] = T(1);
+      }
       for (int k = 0; k < d; ++k) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const T m = p.in[(size_t)(3 * v) * n + nb[k]];
+          const T m = p.in[(size_t)(3 * v) * n + re[k]];
           hi[v] = fmax(hi[v], m);
           lo[v] = fmin(lo[v], m);
         }
       }
+      faces([&](int, int, T rx, T ry) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        T alpha = T(1);
-        for (int k = 0; k < d; ++k) {
-          const T dd = q[3 * v + 1] * rfx[k] + q[3 * v + 2] * rfy[k];
+        for (int v = 0; v < 4; ++v) {
+          const T dd = q[3 * v + 1] * rx + q[3 * v + 2] * ry;
           const T num = dd > T(0) ? hi[v] - q[3 * v] : lo[v] - q[3 * v];
           const T psi = dd > T(0) ? div_small(num, dd) : (dd < T(0) ? div_small(-num, -dd) : T(1));
-          alpha = fmin(alpha, psi);
+          alpha[v] = fmin(alpha[v], psi);
         }
-        q[3 * v + 1] *= alpha;
-        q[3 * v + 2] *= alpha;
+      });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        q[3 * v + 1] *= alpha[v];
+        q[3 * v + 2] *= alpha[v];
       }
     } else {
       const T eps = sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
       T mi[4] = {q[0], q[3], q[6], q[9]};
       T wi[4];
       prim4(mi, gm1, wi);
-      T wn[kRing][4];
-      for (int k = 0; k < d; ++k) {
+      auto nbr_prim = [&](int j, T* w) {
         T mj[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) mj[v] = p.in[(size_t)(3 * v) * n + nb[k]];
-        prim4(mj, gm1, wn[k]);
-      }
+        for (int v = 0; v < 4; ++v) mj[v] = p.in[(size_t)(3 * v) * n + j];
+        prim4(mj, gm1, w);
+      };
       const T rho = wi[0], ir = rcp(rho), ux = wi[1], uy = wi[2];
       const T v2 = ux * ux + uy * uy;
       // DG primitive slopes (chain rule at the centroid)
@@ -337,48 +349,76 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
       gy[2] = (q[8] - uy * gy[0]) * ir;
       gx[3] = gm1 * (q[10] - T(0.5) * v2 * gx[0] - rho * (ux * gx[1] + uy * gx[2]));
       gy[3] = gm1 * (q[11] - T(0.5) * v2 * gy[0] - rho * (ux * gy[1] + uy * gy[2]));
-      // least-squares normal matrix of the stencil
-      T a00 = T(0), a01 = T(0), a11 = T(0);
+      // pass 1: least-squares normal equations of the stencil, bounds
+      T a00 = T(0), a01 = T(0), a11 = T(0), b0[4], b1[4], hi[4], lo[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        b0[v] = b1[v] = T(0);
+        hi[v] = lo[v] = wi[v];
+      }
       for (int k = 0; k < d; ++k) {
-        a00 += dnx[k] * dnx[k];
-        a01 += dnx[k] * dny[k];
-        a11 += dny[k] * dny[k];
+        const int j = re[k];
+        const T dnx = (T)(mimg(s.x[j] - s.x[e], p.Lx) + s.geo[1 * n + j] - dcx);
+        const T dny = (T)(mimg(s.x[n + j] - s.x[n + e], p.Ly) + s.geo[2 * n + j] - dcy);
+        a00 += dnx * dnx;
+        a01 += dnx * dny;
+        a11 += dny * dny;
+        T wj[4];
+        nbr_prim(j, wj);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T dw = wj[v] - wi[v];
+          b0[v] += dnx * dw;
+          b1[v] += dny * dw;
+          hi[v] = fmax(hi[v], wj[v]);
+          lo[v] = fmin(lo[v], wj[v]);
+        }
       }
       const T idet = rcp(a00 * a11 - a01 * a01);
+      T sx[4], sy[4], alpha[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sx[v] = (a11 * b0[v] - a01 * b1[v]) * idet;
+        sy[v] = (a00 * b1[v] - a01 * b0[v]) * idet;
+        alpha[v] = T(1);
+      }
+      // pass 2: the stencil slope limited as in the Arepo limiter
+      faces([&](int, int, T rx, T ry) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T dd = sx[v] * rx + sy[v] * ry;
+          // the clamp absorbs rounding of hi - w (w a product): D >= 0
+          const T num = dd > T(0) ? fmax(hi[v] - wi[v], T(0)) : fmin(lo[v] - wi[v], T(0));
+          const T psi = dd > T(0) ? div_small(num, dd) : (dd < T(0) ? div_small(-num, -dd) : T(1));
+          alpha[v] = fmin(alpha[v], psi);
+        }
+      });
+      // pass 3: oscillation factors of the two candidates
+      T os[4], od[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sx[v] *= alpha[v];
+        sy[v] *= alpha[v];
+        os[v] = od[v] = T(0);
+      }
+      faces([&](int, int j, T rx, T ry) {
+        T wj[4];
+        nbr_prim(j, wj);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T ds = sx[v] * rx + sy[v] * ry;
+          const T dg = gx[v] * rx + gy[v] * ry;
+          os[v] += fabs(ds) + fabs(wj[v] - (wi[v] + ds));
+          od[v] += fabs(dg) + fabs(wj[v] - (wi[v] + dg));
+        }
+      });
       T ngx[4], ngy[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        T b0 = T(0), b1 = T(0), hi = wi[v], lo = wi[v];
-        for (int k = 0; k < d; ++k) {
-          const T dw = wn[k][v] - wi[v];
-          b0 += dnx[k] * dw;
-          b1 += dny[k] * dw;
-          hi = fmax(hi, wn[k][v]);
-          lo = fmin(lo, wn[k][v]);
-        }
-        T sx = (a11 * b0 - a01 * b1) * idet;
-        T sy = (a00 * b1 - a01 * b0) * idet;
-        T alpha = T(1);
-        for (int k = 0; k < d; ++k) {
-          const T dd = sx * rfx[k] + sy * rfy[k];
-          // the clamp absorbs rounding of hi - w (w a product): D >= 0
-          const T num = dd > T(0) ? fmax(hi - wi[v], T(0)) : fmin(lo - wi[v], T(0));
-          const T psi = dd > T(0) ? div_small(num, dd) : (dd < T(0) ? div_small(-num, -dd) : T(1));
-          alpha = fmin(alpha, psi);
-        }
-        sx *= alpha;
-        sy *= alpha;
-        T os = T(0), od = T(0);
-        for (int k = 0; k < d; ++k) {
-          const T ds = sx * rfx[k] + sy * rfy[k];
-          const T dg = gx[v] * rfx[k] + gy[v] * rfy[k];
-          os += fabs(ds) + fabs(wn[k][v] - (wi[v] + ds));
-          od += fabs(dg) + fabs(wn[k][v] - (wi[v] + dg));
-        }
-        const T ws = rcp(sqrt_pos(eps + os)), wd = rcp(sqrt_pos(eps + od));
+        const T ws = rcp(sqrt_pos(eps + os[v])), wd = rcp(sqrt_pos(eps + od[v]));
         const T iw = rcp(ws + wd);
-        ngx[v] = (ws * sx + wd * gx[v]) * iw;
-        ngy[v] = (ws * sy + wd * gy[v]) * iw;
+        ngx[v] = (ws * sx[v] + wd * gx[v]) * iw;
+        ngy[v] = (ws * sy[v] + wd * gy[v]) * iw;
       }
       q[1] = ngx[0];
       q[2] = ngy[0];
