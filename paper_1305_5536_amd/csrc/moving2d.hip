@@ -50,6 +50,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -65,6 +66,8 @@ constexpr int kRing = 16;  // neighbours a cell may have
 constexpr int kPoly = kRing + 1;  // ring entries during the walk
 constexpr int kGeo = 6;    // V, centroid - generator (2), Mxx, Mxy, Myy
 constexpr int kChunk = 4;  // candidates gathered together in the walk
+constexpr int kCand = 40;  // distinct candidates of one cell's walk kept in LDS
+constexpr int kWalkThreads = 128;  // threads per block of the walk (LDS: kCand ints each)
 
 struct MVDev {
   int n = 0;
@@ -76,6 +79,7 @@ struct MVDev {
   int* deg[3] = {nullptr, nullptr, nullptr};     // [n]
   double* geo[3] = {nullptr, nullptr, nullptr};  // [kGeo][n]
   void* ua = nullptr;                            // limited state
+  int cand_cap = kCand;                          // LDS list length of the walk (<= kCand)
   bool timing = false;                           // record events around each kernel
   std::vector<hipEvent_t> ev;                    // 5 per timed step
 };
@@ -110,6 +114,7 @@ struct PM {
   double Lx, Ly;
   T gamma;
   int motion;
+  int cand_cap;   // k_mv_walk: candidates kept in LDS before streaming them
   int write_pos;  // k_mv_lim: write the half-step and next positions
   MSet s0;        // t^n
   MSet sh;        // half step
@@ -458,8 +463,11 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
 // so that the walk, a chain of dependent gathers, runs at a higher occupancy
 // than the register-heavy geometry and update.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
-  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+__global__ __launch_bounds__(kWalkThreads) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
+  // each thread's distinct candidates, in a column of its own (no barrier)
+  __shared__ int cl[kCand * kWalkThreads];
+  const int tl = threadIdx.x;
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * kWalkThreads + tl;
   if (e < p.n) {
     const int n = p.n;
     const double* X = dst.x;
@@ -467,39 +475,69 @@ __global__ __launch_bounds__(256) void k_mv_walk(PM<T> p, MSet src, MOut dst) {
     bool bad = false;
     const int d0 = min(src.deg[e], kRing);
     const double iLx = 1.0 / p.Lx, iLy = 1.0 / p.Ly;
-    // Visit every candidate: the previous neighbours j and the entries of
-    // their rings, kChunk at a time (the ring entries, then their positions, are
-    // loaded together so that the gathers overlap).  f(k, dx, dy) sees each
-    // candidate's offset from this generator (duplicates included: they give
-    // equal values and the index tie-break makes them harmless).
+    // The candidates (the previous neighbours and the entries of their
+    // rings) are listed once, without repeats, in LDS; a cell with more than
+    // kCand of them streams them from the rings instead (repeats included:
+    // they give equal values and the index tie-break makes them harmless).
+    int nc = 0;
+    bool stream = false;
+    for (int a = 0; a < d0 && !stream; ++a) {
+      const int j = src.ring[e * kRing + a];
+      const int dj = min(src.deg[j], kRing);
+      for (int b = -1; b < dj; ++b) {
+        const int k = b < 0 ? j : src.ring[j * kRing + b];
+        if (k == e) continue;
+        bool seen = false;
+        for (int c = 0; c < nc; ++c) seen |= cl[c * kWalkThreads + tl] == k;
+        if (seen) continue;
+        if (nc == p.cand_cap) {
+          stream = true;
+          break;
+        }
+        cl[nc++ * kWalkThreads + tl] = k;
+      }
+    }
+    auto offset = [&](int k, double& dx, double& dy) {
+      dx = X[k] - xe;
+      dy = X[n + k] - ye;
+      dx -= p.Lx * rint(dx * iLx);
+      dy -= p.Ly * rint(dy * iLy);
+    };
+    // f(k, dx, dy) for every candidate: its offset from this generator; the
+    // positions of kChunk candidates are loaded together so that the gathers
+    // overlap.
     auto visit = [&](auto&& f) {
-      for (int a = 0; a < d0; ++a) {
-        const int j = src.ring[e * kRing + a];
-        const int dj = min(src.deg[j], kRing);
-        const int* rj = src.ring + j * kRing;
-        for (int b0 = -1; b0 < dj; b0 += kChunk) {
-          int kk[kChunk];
-          double kx[kChunk], ky[kChunk];
-#pragma unroll
-          for (int q = 0; q < kChunk; ++q) {
-            const int b = b0 + q;
-            kk[q] = b < 0 ? j : (b < dj ? rj[b] : -1);
-          }
-#pragma unroll
-          for (int q = 0; q < kChunk; ++q) {
-            const int k = kk[q] < 0 ? e : kk[q];
-            kx[q] = X[k];
-            ky[q] = X[n + k];
-          }
-#pragma unroll
-          for (int q = 0; q < kChunk; ++q) {
-            const int k = kk[q];
-            if (k < 0 || k == e) continue;
-            double dx = kx[q] - xe, dy = ky[q] - ye;
-            dx -= p.Lx * rint(dx * iLx);
-            dy -= p.Ly * rint(dy * iLy);
+      if (stream) {
+        for (int a = 0; a < d0; ++a) {
+          const int j = src.ring[e * kRing + a];
+          const int dj = min(src.deg[j], kRing);
+          for (int b = -1; b < dj; ++b) {
+            const int k = b < 0 ? j : src.ring[j * kRing + b];
+            if (k == e) continue;
+            double dx, dy;
+            offset(k, dx, dy);
             f(k, dx, dy);
           }
+        }
+        return;
+      }
+      for (int c0 = 0; c0 < nc; c0 += kChunk) {
+        int kk[kChunk];
+        double kx[kChunk], ky[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) kk[q] = c0 + q < nc ? cl[(c0 + q) * kWalkThreads + tl] : e;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+          kx[q] = X[kk[q]];
+          ky[q] = X[n + kk[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+          if (c0 + q >= nc) continue;
+          double dx = kx[q] - xe, dy = ky[q] - ye;
+          dx -= p.Lx * rint(dx * iLx);
+          dy -= p.Ly * rint(dy * iLy);
+          f(kk[q], dx, dy);
         }
       }
     };
@@ -951,6 +989,7 @@ PM<T> make_params(const dg_mesh* m, const void* in, void* out) {
   p.Ly = v.box[1];
   p.gamma = (T)m->cfg.gamma;
   p.motion = v.motion;
+  p.cand_cap = v.cand_cap;
   p.s0 = MSet{v.pos[v.cur], v.ring[v.cur], v.deg[v.cur], v.geo[v.cur]};
   p.sh = MSet{v.pos[1], v.ring[1], v.deg[1], v.geo[1]};
   p.xh = v.pos[1];
@@ -994,7 +1033,8 @@ hipError_t step_t(dg_mesh* m, const void* in, void* out, const double* dt_dev, d
   if (e != hipSuccess) return e;
   // mesh of the half-step generators (candidates from t^n)
   const MOut half{v.pos[1], v.ring[1], v.deg[1], v.geo[1]};
-  hipLaunchKernelGGL((k_mv_walk<T>), g, b, 0, s, p, p.s0, half);
+  const dim3 gw((p.n + kWalkThreads - 1) / kWalkThreads), bw(kWalkThreads);
+  hipLaunchKernelGGL((k_mv_walk<T>), gw, bw, 0, s, p, p.s0, half);
   hipLaunchKernelGGL((k_mv_geom<T, false>), g, b, 0, s, p, half);
   e = mark();
   if (e != hipSuccess) return e;
@@ -1007,7 +1047,7 @@ hipError_t step_t(dg_mesh* m, const void* in, void* out, const double* dt_dev, d
   // mesh of t^{n+1} (candidates from the half step) and the new state
   if (want_dt) p.dtpart = m->dtpart;
   const MOut next{v.pos[v.nxt], v.ring[v.nxt], v.deg[v.nxt], v.geo[v.nxt]};
-  hipLaunchKernelGGL((k_mv_walk<T>), g, b, 0, s, p, p.sh, next);
+  hipLaunchKernelGGL((k_mv_walk<T>), gw, bw, 0, s, p, p.sh, next);
   hipLaunchKernelGGL((k_mv_geom<T, true>), g, b, 0, s, p, next);
   e = hipGetLastError();
   if (e == hipSuccess) std::swap(v.cur, v.nxt);
@@ -1151,6 +1191,10 @@ dg_status moving_create(dg_mesh* m, const dg_mesh_desc* d) {
   v.motion = 1;
   v.cur = 0;
   v.nxt = 2;
+  // DG_MOVING_CANDIDATES caps the walk's LDS candidate list (tests use it to
+  // drive every cell through the streaming path)
+  if (const char* env = std::getenv("DG_MOVING_CANDIDATES"))
+    v.cand_cap = std::max(0, std::min(kCand, std::atoi(env)));
   hipError_t e = hipSuccess;
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     e = hipMalloc((void**)&v.pos[k], sizeof(double) * 2 * n);
@@ -1178,13 +1222,15 @@ hipError_t moving_init(dg_mesh* m) {
   PM<double> p;
   std::memset(&p, 0, sizeof(p));
   p.status = m->status;
+  p.cand_cap = v.cand_cap;
   p.n = v.n;
   p.Lx = v.box[0];
   p.Ly = v.box[1];
   p.gamma = m->cfg.gamma;
   const dim3 g((v.n + 255) / 256), b(256);
   const MOut first{v.pos[0], v.ring[0], v.deg[0], v.geo[0]};
-  hipLaunchKernelGGL((k_mv_walk<double>), g, b, 0, nullptr, p,
+  const dim3 gw((v.n + kWalkThreads - 1) / kWalkThreads), bw(kWalkThreads);
+  hipLaunchKernelGGL((k_mv_walk<double>), gw, bw, 0, nullptr, p,
                      MSet{v.pos[0], v.ring[1], v.deg[1], v.geo[1]}, first);
   hipLaunchKernelGGL((k_mv_geom<double, false>), g, b, 0, nullptr, p, first);
   return hipGetLastError();

@@ -260,3 +260,34 @@ def test_kernel_timing(mv, torch_cuda):
     c = Solver(cartesian((8, 8), (0, 0), (1, 1)), gamma=G53)
     with pytest.raises(DGError):
         c.set_timing(True)
+
+
+@pytest.mark.parametrize("cap", [None, "4"])
+def test_high_degree_cell(mv, torch_cuda, monkeypatch, cap):
+    """A generator ringed by 16 close neighbours (the most a ring holds), with the
+    walk's candidate list in LDS and, with DG_MOVING_CANDIDATES=4, with every cell's
+    candidates streamed from the rings instead: the mesh and a step match the
+    oracle either way."""
+    if cap is not None:
+        monkeypatch.setenv("DG_MOVING_CANDIDATES", cap)
+    rng = np.random.default_rng(23)
+    n0 = 700
+    P = periodic_voronoi(n0, seed=24)["generators"]
+    c = np.array([0.5, 0.5])
+    h = 1.0 / math.sqrt(n0)
+    keep = np.linalg.norm(P - c, axis=1) > 2.2 * h
+    ang = 2 * math.pi * (np.arange(16) + rng.uniform(-0.05, 0.05, 16)) / 16
+    ring = c + 1.0 * h * np.stack([np.cos(ang), np.sin(ang)], 1)
+    P = np.concatenate([P[keep], c[None], ring])
+    d = mv.voronoi(P, (1.0, 1.0))
+    ic = int(np.sum(keep))
+    assert len(mv.neighbours(d)[ic]) == 16
+    s = _solver(d)
+    compare_mesh(s.geometry(), d)
+    U = random_voronoi_state(d, G53, seed=25, amp=0.2)
+    dt = mv.cfl_dt(d, U, G53, 0.3)
+    ref, d1 = mv.step(d, U, dt, G53, "weno", "exact")
+    got = s.step_mh(s.to_device(U), dt).cpu().numpy()
+    s.check()
+    assert field_errors(got, ref, h).max() < 1e-12
+    compare_mesh(s.geometry(), d1)
