@@ -99,25 +99,35 @@ def parse():
     return a
 
 
-def pmc_traffic(profile: str, kernel: str, shape: str, source: str,
+CSRC = "paper_1305_5536_amd/csrc"
+
+
+def pmc_traffic(profile: str, kernel: str, shape: str, sources,
                 what: str = "pmc_traffic_bytes_per_launch"):
     """HBM bytes per launch of ``kernel`` measured with rocprofv3 --pmc
     (FETCH_SIZE and WRITE_SIZE, copy-calibrated) as recorded in the committed
-    profile summary (or another recorded figure, ``what``), or None when the
-    kernel source has changed since."""
+    profile summary (or another recorded figure, ``what``), or None when any of
+    the kernel's source files (the .hip file and the headers it uses) has
+    changed since, or the profile records no hash for one of them."""
     import hashlib
+    if isinstance(sources, str):
+        sources = (sources,)
     try:
         text = open(os.path.join(ROOT, "profiles", profile)).read()
-        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+        shas = {src: hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+                for src in sources}
     except OSError:
         return None
     want = f"{what}({kernel}, {shape}): "
     traffic = None
+    recorded = {}
     for line in text.splitlines():
         if line.startswith(want):
             traffic = float(line[len(want):])
-        if line.startswith(f"kernel_source_sha256({source}): ") and line.split()[-1] != sha:
-            return None
+        if line.startswith("kernel_source_sha256(") and "): " in line:
+            recorded[line[len("kernel_source_sha256("):line.index("): ")]] = line.split()[-1]
+    if any(recorded.get(src) != sha for src, sha in shas.items()):
+        return None
     return traffic
 
 
@@ -291,7 +301,7 @@ def bench_c2(a):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, 1, 0>",
-                                             "2048x2048", "paper_1305_5536_amd/csrc/cart2d.hip")
+                                             "2048x2048", (f"{CSRC}/cart2d.hip", f"{CSRC}/dg_math.h"))
                                  if n == 2048 and a.precision == "fp64" and a.flux == "hll"
                                  and a.limiter == "arepo" else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
@@ -375,7 +385,8 @@ def bench_ot(a):
     # holds the 4-us one-workgroup dt reduction)
     achieved = MHD2D_FLOPS_PER_CELL_STAGE * ncells / r["stage2_s"] / 1e12
     traffic = pmc_traffic("k_mhd2d_ot_512.md", "k_mhd2d<double, 2, true>", f"{n}x{n}",
-                          "paper_1305_5536_amd/csrc/mhd2d.hip") if a.precision == "fp64" else None
+                          (f"{CSRC}/mhd2d.hip", f"{CSRC}/dg_math.h", f"{CSRC}/mhd_hlld.h")
+                          ) if a.precision == "fp64" else None
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
@@ -587,7 +598,7 @@ def bench_moving(a):
     km = r["kernel_ms"]
     dom = max(km, key=km.get)
     avg = km[dom] * 1e-3
-    src = "paper_1305_5536_amd/csrc/moving2d.hip"
+    src = (f"{CSRC}/moving2d.hip", f"{CSRC}/dg_math.h", f"{CSRC}/euler_exact.h")
     shape = f"{int(round(n ** 0.5))}x{int(round(n ** 0.5))}"
     flops = traffic = None
     if a.precision == "fp64":

@@ -7,13 +7,26 @@
 // (p* <= p_K, isentropic with a Riemann invariant).  Across the wave of side K
 // the normal velocity changes by f_K(p*), so p* is the root of
 //   f_L(p) + f_R(p) + u_R - u_L = 0,
-// solved by Newton's method from the two-rarefaction value (the root when
-// both waves are rarefactions); u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2.
+// solved by Newton's method; u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2.
 // The flux is the physical flux of the solution on the face (x/t = 0), with
 // the tangential velocity of the side upwind of the contact.  A lane that
 // meets vacuum generation or a non-physical input raises `bad` (its flux is
 // then not meaningful); every lane leaves the Newton loop after at most
 // kExactMaxIter iterations.
+//
+// FP64 powers are software routines on gfx950, so the solver avoids them
+// where an algebraically equal form exists:
+// * the Newton start is the linearised (primitive-variable) estimate
+//   p = (p_L + p_R)/2 - (u_R - u_L)(rho_L + rho_R)(c_L + c_R)/8 when the two
+//   pressures are within a factor 2 and the estimate lies between them (weak
+//   waves, where it is accurate to second order in the jump); otherwise the
+//   two-rarefaction value, exact when both waves are rarefactions;
+// * when the Newton step falls below the tolerance, f_L and f_R are carried
+//   to the new p* along their tangents (the neglected term is of the order of
+//   the squared step) instead of being evaluated again;
+// * behind a rarefaction of side K the sound speed follows from the Riemann
+//   invariant, c* = c_K + (gamma - 1) f_K(p*)/2, and the density from the
+//   isentrope, rho* = gamma p*/c*^2; in the fan p = rho c^2/gamma.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,31 +88,43 @@ __device__ __forceinline__ void exact_flux(const T* uL, const T* uR, T gamma, T*
   const T du = s[1].u - s[0].u;
   bad |= !(T(2) * rcp(gm1) * (s[0].c + s[1].c) > du);
   const T z = gm1 * rcp(T(2) * gamma);
-  T ps = pow_pos((s[0].c + s[1].c - T(0.5) * gm1 * du) *
+  const T pmin = fmin(s[0].p, s[1].p), pmax = fmax(s[0].p, s[1].p);
+  T ps = T(0.5) * (s[0].p + s[1].p) - T(0.125) * du * (s[0].r + s[1].r) * (s[0].c + s[1].c);
+  if (!(pmax <= T(2) * pmin && ps >= pmin && ps <= pmax))
+    ps = pow_pos((s[0].c + s[1].c - T(0.5) * gm1 * du) *
                      rcp(s[0].c * pow_pos(s[0].p, -z) + s[1].c * pow_pos(s[1].p, -z)),
                  rcp(z));
   T fL, dfL, fR, dfR;
+  bool conv = false;
   for (int it = 0; it < kExactMaxIter; ++it) {
     wave_relation(ps, s[0], gamma, fL, dfL);
     wave_relation(ps, s[1], gamma, fR, dfR);
     T pn = ps - (fL + fR + du) * rcp(dfL + dfR);
     if (!(pn > T(0))) pn = T(0.5) * ps;
-    const bool done = fabs(pn - ps) <= tol * (pn + ps);
+    const T step = pn - ps;
     ps = pn;
-    if (done) break;
+    if (fabs(step) <= tol * (pn + pn - step)) {
+      fL += dfL * step;
+      fR += dfR * step;
+      conv = true;
+      break;
+    }
   }
-  wave_relation(ps, s[0], gamma, fL, dfL);
-  wave_relation(ps, s[1], gamma, fR, dfR);
+  if (!conv) {
+    wave_relation(ps, s[0], gamma, fL, dfL);
+    wave_relation(ps, s[1], gamma, fR, dfR);
+  }
   const T us = T(0.5) * (s[0].u + s[1].u) + T(0.5) * (fR - fL);
   // The side of the contact the face lies on; the right side is mirrored
   // (velocities negated) onto the left-side formulas.
   const bool left = us >= T(0);
   const T sg = left ? T(1) : T(-1);
   const ESide<T> a = left ? s[0] : s[1];
+  const T fa = left ? fL : fR;
   const T ua = sg * a.u, usa = sg * us, vt = left ? ut[0] : ut[1];
-  const T pr_ratio = ps * rcp(a.p);
   T rho, u, pr;
   if (ps > a.p) {
+    const T pr_ratio = ps * rcp(a.p);
     const T S = ua - a.c * sqrt_pos((gamma + T(1)) * rcp(T(2) * gamma) * pr_ratio + z);
     const T g6 = gm1 * rcp(gamma + T(1));
     if (S >= T(0)) {
@@ -112,22 +137,22 @@ __device__ __forceinline__ void exact_flux(const T* uL, const T* uR, T gamma, T*
       pr = ps;
     }
   } else {
+    const T cs = a.c + T(0.5) * gm1 * fa;
     const T head = ua - a.c;
-    const T tail = usa - a.c * pow_pos(pr_ratio, z);
+    const T tail = usa - cs;
     if (head >= T(0)) {
       rho = a.r;
       u = ua;
       pr = a.p;
     } else if (tail < T(0)) {
-      rho = a.r * pow_pos(pr_ratio, rcp(gamma));
+      rho = gamma * ps * rcp(cs * cs);
       u = usa;
       pr = ps;
     } else {  // inside the rarefaction fan, where u = c
       const T cf = T(2) * rcp(gamma + T(1)) * (a.c + T(0.5) * gm1 * ua);
-      const T cr = cf * rcp(a.c);
       u = cf;
-      rho = a.r * pow_pos(cr, T(2) * rcp(gm1));
-      pr = a.p * pow_pos(cr, T(2) * gamma * rcp(gm1));
+      rho = a.r * pow_pos(cf * rcp(a.c), T(2) * rcp(gm1));
+      pr = rho * cf * cf * rcp(gamma);
     }
   }
   u = sg * u;

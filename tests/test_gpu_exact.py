@@ -2,6 +2,7 @@
 against the oracle's exact solver, through the C ABI:
 
 * single RHS / step / MUSCL-Hancock calls on ragged meshes, limiter on and off;
+* every face a strong or weak Riemann problem (Toro's five, random jumps);
 * 100 FP64 steps on the oracle's schedule at 1e-11 per field: the C2 shear
   recipe at 128^2 and the paper's Sod tube (Sec. 3.2) along x and along y
   (two interfaces on a periodic [-1, 1]); the FP32 error is stated;
@@ -75,6 +76,67 @@ def test_rhs_step_mh_match_oracle(oracle, torch_cuda, n):
         e = field_errors(sl.step_mh(ul, dt).cpu().numpy(), ref, h)
         assert e.max() < 1e-13, ("mh", limiter, e)
         sl.check()
+
+
+# The five standard Riemann problems of Toro's textbook (Ch. 4), (rho, u, p) left and
+# right, gamma 1.4: Sod's, two strong rarefactions near vacuum, a strong
+# rarefaction against a strong shock, the mirror of it, two colliding shocks.
+TORO = [((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),
+        ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),
+        ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01)),
+        ((1.0, 0.0, 0.01), (1.0, 0.0, 100.0)),
+        ((5.99924, 19.5975, 460.894), (5.99242, -6.19633, 46.0950))]
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_riemann_problems_face_by_face(oracle, torch_cuda, axis):
+    """Piecewise-constant cells whose faces are Toro's five problems (in both
+    orders) and random strong and weak jumps (pressure ratios up to ~1e4, both
+    wave types on either side): with the limiter off, the RHS of every cell is
+    the difference of two exact-solver fluxes, checked against the oracle's
+    along x and along y.  The FP32 error is stated."""
+    rng = np.random.default_rng(31 + axis)
+    cells = []
+    for L, R in TORO:
+        cells += [L, R, R, L]
+
+    def sound(c):
+        return np.sqrt(G14 * c[2] / c[0])
+
+    while len(cells) < 116:
+        c = (float(np.exp(rng.normal(0, 1))), float(rng.normal(0, 1.5)),
+             float(np.exp(rng.normal(0, 2.0))))
+        # keep a margin from vacuum generation against both neighbours
+        ok = all(c[1] - a[1] < 2 * (sound(a) + sound(c)) / (G14 - 1) / 1.5 and
+                 a[1] - c[1] < 2 * (sound(a) + sound(c)) / (G14 - 1) / 1.5
+                 for a in (cells[-1], cells[0]))
+        if ok:
+            cells.append(c)
+    base = (1.2, 0.3, 2.5)
+    for _ in range(64):
+        e = 10.0 ** rng.uniform(-7, -1)
+        cells.append(tuple(b * (1 + e * rng.normal()) for b in base))
+    n = len(cells)
+    U = np.zeros((12, n))
+    for i, (r, u, p) in enumerate(cells):
+        v = 0.1 * (i % 7 - 3)
+        U[0, i] = r
+        U[3 + 3 * axis, i] = r * u
+        U[6 - 3 * axis, i] = r * v
+        U[9, i] = p / (G14 - 1) + 0.5 * r * (u * u + v * v)
+    U0 = U.reshape(-1)
+    shape = (n, 1) if axis == 0 else (1, n)
+    hi = (1.0, 1.0 / n) if axis == 0 else (1.0 / n, 1.0)
+    om = oracle.Mesh.cartesian(shape, (0.0, 0.0), hi)
+    ref = oracle.rhs(om, U0, G14, flux="exact")
+    floor = np.abs(ref.reshape(12, -1)[0::3]).max()
+    for prec, tol in (("fp64", 1e-13), ("fp32", 1e-5)):
+        s = _solver(shape, (0.0, 0.0), hi, G14, limiter=False, precision=prec)
+        got = s.rhs(s.to_device(U0)).double().cpu().numpy()
+        e = field_errors(got, ref, 1.0 / n, floor)
+        print(f"exact flux, Toro + random jumps along axis {axis}, {prec}: {e}")
+        assert e.max() < tol, (prec, e)
+        s.check()
 
 
 def _run(s, U0, dts, mh=False):
