@@ -124,7 +124,10 @@ typedef struct {
  *   2.2 recomputed per step).  At most 16 faces per cell; a cell's neighbours
  *   after a step must lie within two rings of its neighbours before it (any
  *   CFL-limited step); a failure latches DG_EMESH (dg_check).  The mesh must
- *   be fine enough that no two cells share two faces (ncells >= 64). */
+ *   be fine enough that no two cells share two faces (ncells >= 64).  Every
+ *   step reads and rewrites the mesh the handle holds, so the calls on one
+ *   moving mesh must be issued in order on one stream (calls that overlap
+ *   race). */
 typedef struct {
   int dim;
   int kind;

@@ -416,7 +416,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     return e == hipErrorOutOfMemory ? DG_ENOMEM : st;
   }
   if (m->kind == 3) {
-    // the mesh of the initial generators, built by the same clip as every step
+    // the mesh of the initial generators, built by the same walk as every step
     e = moving_init(m);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     int flag = 0;

@@ -1018,14 +1018,15 @@ hipError_t step_t(dg_mesh* m, const void* in, void* out, const double* dt_dev, d
   p.dt_host = dt_host;
   p.write_pos = 1;
   const dim3 g((p.n + 255) / 256), b(256);
-  hipEvent_t ev[4];
-  int nev = 0;
+  // per-phase events go straight into the record (launch_moving drops the
+  // ones of a step that fails)
   auto mark = [&]() {
     if (!v.timing) return hipSuccess;
-    hipError_t r = hipEventCreate(&ev[nev]);
-    if (r == hipSuccess) r = hipEventRecord(ev[nev], s);
-    if (r == hipSuccess) ++nev;
-    return r;
+    hipEvent_t ev;
+    hipError_t r = hipEventCreate(&ev);
+    if (r != hipSuccess) return r;
+    v.ev.push_back(ev);
+    return hipEventRecord(ev, s);
   };
   hipError_t e = mark();
   if (e == hipSuccess) e = lim_launch(p, m->cfg.limiter, s);
@@ -1051,7 +1052,6 @@ hipError_t step_t(dg_mesh* m, const void* in, void* out, const double* dt_dev, d
   hipLaunchKernelGGL((k_mv_geom<T, true>), g, b, 0, s, p, next);
   e = hipGetLastError();
   if (e == hipSuccess) std::swap(v.cur, v.nxt);
-  for (int k = 0; k < nev; ++k) v.ev.push_back(ev[k]);
   return e;
 }
 
@@ -1073,17 +1073,25 @@ hipError_t launch_moving(dg_mesh* m, int mode, const void* in, void* out, const 
     return lim_launch(p, m->cfg.limiter, s);
   }
   if (mode != kMH) return hipErrorInvalidValue;
+  MVDev& v = *m->mvd;
+  const size_t ev0 = v.ev.size();
   hipError_t e = f64 ? step_t<double>(m, in, out, dt_dev, dt_host, dt_next != nullptr, s)
                      : step_t<float>(m, in, out, dt_dev, dt_host, dt_next != nullptr, s);
   if (e == hipSuccess && dt_next)
     e = launch_min_finalize(m->dtpart, (int)((m->ncells + 63) / 64), cfl, dt_next, s);
-  MVDev& v = *m->mvd;
   if (e == hipSuccess && v.timing) {
     // the fifth event closes the new-mesh kernel and the dt reduction
     hipEvent_t last;
     e = hipEventCreate(&last);
-    if (e == hipSuccess) e = hipEventRecord(last, s);
-    if (e == hipSuccess) v.ev.push_back(last);
+    if (e == hipSuccess) {
+      v.ev.push_back(last);
+      e = hipEventRecord(last, s);
+    }
+  }
+  if (e != hipSuccess) {
+    // a failed step leaves no partial record: the timings stay in groups of five
+    for (size_t k = ev0; k < v.ev.size(); ++k) (void)hipEventDestroy(v.ev[k]);
+    v.ev.resize(ev0);
   }
   return e;
 }
