@@ -603,6 +603,20 @@ __global__ __launch_bounds__(256) void k_cart2d(P2<T> p) {
   cart2d_tile<T, MODE, LIM, RS>(p, wave, lane);
 }
 
+// The same tile with the register budget of two waves per SIMD.  Used for
+// stage 1 with the exact Riemann solver in FP64, where the second wave hides
+// the latency of the divergent Newton loops and pays for the ~160 B per lane
+// the cap spills (0.99 -> 0.88 ms at 2048^2); the other stage kernels spill
+// far more under the cap (stage 2: 350-770 B) and run one wave per SIMD.
+template <typename T, int MODE, int LIM, int RS = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_cart2d_w2(P2<T> p) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (wave >= p.ntiles) return;
+  cart2d_tile<T, MODE, LIM, RS>(p, wave, lane);
+}
+
 // ---------------------------------------------------------------- batches --
 // A batch of independent meshes stored one after another in the same
 // coefficient-major arrays (stride nc = total cells of the batch).  Tile t
@@ -779,6 +793,15 @@ P2<T> make_params(const dg_mesh* m, const void* in, const void* u0, void* out,
 // One stage kernel launch for limiter LIM (0 none, 1 Arepo, 2 WENO).
 template <typename T, int MODE, int RS>
 void launch_lim(int lim, int nblocks, const P2<T>& p, hipStream_t s) {
+  if constexpr (MODE == kStage1 && RS == 1 && sizeof(T) == 8) {
+    if (lim == 2)
+      hipLaunchKernelGGL((k_cart2d_w2<T, MODE, 2, RS>), dim3(nblocks), dim3(256), 0, s, p);
+    else if (lim == 1)
+      hipLaunchKernelGGL((k_cart2d_w2<T, MODE, 1, RS>), dim3(nblocks), dim3(256), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_cart2d_w2<T, MODE, 0, RS>), dim3(nblocks), dim3(256), 0, s, p);
+    return;
+  }
   if (lim == 2)
     hipLaunchKernelGGL((k_cart2d<T, MODE, 2, RS>), dim3(nblocks), dim3(256), 0, s, p);
   else if (lim == 1)
