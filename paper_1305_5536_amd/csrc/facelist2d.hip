@@ -111,34 +111,56 @@ __device__ __forceinline__ void hll_n(const T* uL, const T* uR, T nx, T ny, T ga
 // ------------------------------------------------------------- limiter --
 template <typename T>
 __global__ __launch_bounds__(256) void k_fl_lim(PF<T> p) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  // blocks mapped XCD by XCD: neighbouring blocks (Morton-ordered cells) share
+  // their neighbours' means in the same L2
+  const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (e >= p.ncells) return;
   T q[12];
   load12(p.in, p.nc, e, q);
   T hi[4], lo[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
+  // Incidences are taken kBatch at a time, every load of a batch issued before
+  // any is used (a per-incidence loop waits out one gather chain per face);
+  // padding slots repeat the cell itself, which changes no max, min or bound.
+  constexpr int kBatch = 8;
   const int i0 = p.lim_inc0[e], i1 = p.lim_inc0[e + 1];
-  for (int i = i0; i < i1; ++i) {
-    const int nb = p.lim_nbr[i];
+  for (int b0 = i0; b0 < i1; b0 += kBatch) {
+    int nb[kBatch];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T m = p.in[(3 * v) * p.nc + nb];
-      hi[v] = fmax(hi[v], m);
-      lo[v] = fmin(lo[v], m);
-    }
+    for (int u = 0; u < kBatch; ++u) nb[u] = b0 + u < i1 ? p.lim_nbr[b0 + u] : e;
+    T m[kBatch][4];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) m[u][v] = p.in[(3 * v) * p.nc + nb[u]];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        hi[v] = fmax(hi[v], m[u][v]);
+        lo[v] = fmin(lo[v], m[u][v]);
+      }
   }
   T alpha[4] = {T(1), T(1), T(1), T(1)};
-  for (int i = i0; i < i1; ++i) {
-    const T rx = p.lim_geo[4 * i], ry = p.lim_geo[4 * i + 1];
+  for (int b0 = i0; b0 < i1; b0 += kBatch) {
+    T rx[kBatch], ry[kBatch];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T d = q[3 * v + 1] * rx + q[3 * v + 2] * ry;
-      // psi = (max - phi)/d for d > 0, (min - phi)/d for d < 0, 1 for d = 0
-      const T num = d > T(0) ? hi[v] - q[3 * v] : lo[v] - q[3 * v];
-      const T psi = d > T(0) ? div_small(num, d) : (d < T(0) ? div_small(-num, -d) : T(1));
-      alpha[v] = fmin(alpha[v], psi);
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = b0 + u < i1 ? b0 + u : b0;
+      rx[u] = p.lim_geo[4 * i];
+      ry[u] = p.lim_geo[4 * i + 1];
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T d = q[3 * v + 1] * rx[u] + q[3 * v + 2] * ry[u];
+        // psi = (max - phi)/d for d > 0, (min - phi)/d for d < 0, 1 for d = 0
+        const T num = d > T(0) ? hi[v] - q[3 * v] : lo[v] - q[3 * v];
+        const T psi = d > T(0) ? div_small(num, d) : (d < T(0) ? div_small(-num, -d) : T(1));
+        alpha[v] = fmin(alpha[v], psi);
+      }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
