@@ -74,7 +74,9 @@ struct MVDev {
   double box[2] = {1.0, 1.0};
   int motion = 1;
   int cur = 0, nxt = 2;  // sets holding t^n and t^{n+1}; set 1 is the half step
-  double* pos[3] = {nullptr, nullptr, nullptr};  // [2][n]: x block, then y block
+  // [4][n]: x block, y block, then the same positions interleaved (x, y) per
+  // generator, which the walk gathers with one 16-byte load per candidate
+  double* pos[3] = {nullptr, nullptr, nullptr};
   int* ring[3] = {nullptr, nullptr, nullptr};    // [n][kRing], counter-clockwise
   int* deg[3] = {nullptr, nullptr, nullptr};     // [n]
   double* geo[3] = {nullptr, nullptr, nullptr};  // [kGeo][n]
@@ -88,7 +90,7 @@ namespace {
 
 // One set of mesh arrays as kernels see it.
 struct MSet {
-  const double* x;  // x block of the positions (y = x + n)
+  const double* x;  // x block of the positions (y = x + n, interleaved pairs from x + 2n)
   const int* ring;
   const int* deg;
   const double* geo;
@@ -446,10 +448,14 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
       wy = (double)q[6] / (double)q[0];
     }
     const double x = s.x[e], y = s.x[n + e];
-    p.xh[e] = advance(x, 0.5 * dt, wx, p.Lx);
-    p.xh[n + e] = advance(y, 0.5 * dt, wy, p.Ly);
-    p.x1[e] = advance(x, dt, wx, p.Lx);
-    p.x1[n + e] = advance(y, dt, wy, p.Ly);
+    const double hx = advance(x, 0.5 * dt, wx, p.Lx), hy = advance(y, 0.5 * dt, wy, p.Ly);
+    const double nx1 = advance(x, dt, wx, p.Lx), ny1 = advance(y, dt, wy, p.Ly);
+    p.xh[e] = hx;
+    p.xh[n + e] = hy;
+    reinterpret_cast<double2*>(p.xh + 2 * (size_t)n)[e] = make_double2(hx, hy);
+    p.x1[e] = nx1;
+    p.x1[n + e] = ny1;
+    reinterpret_cast<double2*>(p.x1 + 2 * (size_t)n)[e] = make_double2(nx1, ny1);
   }
 }
 
@@ -470,8 +476,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_mv_walk(PM<T> p, MSet src, MOu
   const int e = xcd_remap(blockIdx.x, gridDim.x) * kWalkThreads + tl;
   if (e < p.n) {
     const int n = p.n;
-    const double* X = dst.x;
-    const double xe = X[e], ye = X[n + e];
+    const double2* XY = reinterpret_cast<const double2*>(dst.x + 2 * (size_t)n);
+    const double2 pe = XY[e];
+    const double xe = pe.x, ye = pe.y;
     bool bad = false;
     const int d0 = min(src.deg[e], kRing);
     const double iLx = 1.0 / p.Lx, iLy = 1.0 / p.Ly;
@@ -498,8 +505,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_mv_walk(PM<T> p, MSet src, MOu
       }
     }
     auto offset = [&](int k, double& dx, double& dy) {
-      dx = X[k] - xe;
-      dy = X[n + k] - ye;
+      const double2 pk = XY[k];
+      dx = pk.x - xe;
+      dy = pk.y - ye;
       dx -= p.Lx * rint(dx * iLx);
       dy -= p.Ly * rint(dy * iLy);
     };
@@ -528,8 +536,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_mv_walk(PM<T> p, MSet src, MOu
         for (int q = 0; q < kChunk; ++q) kk[q] = c0 + q < nc ? cl[(c0 + q) * kWalkThreads + tl] : e;
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {
-          kx[q] = X[kk[q]];
-          ky[q] = X[n + kk[q]];
+          const double2 pk = XY[kk[q]];
+          kx[q] = pk.x;
+          ky[q] = pk.y;
         }
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {
@@ -568,7 +577,8 @@ __global__ __launch_bounds__(kWalkThreads) void k_mv_walk(PM<T> p, MSet src, MOu
         break;
       }
       ring[d++] = cur;
-      double cx = X[cur] - xe, cy = X[n + cur] - ye;
+      const double2 pc = XY[cur];
+      double cx = pc.x - xe, cy = pc.y - ye;
       cx -= p.Lx * rint(cx * iLx);
       cy -= p.Ly * rint(cy * iLy);
       // smallest t_k = num_k / (2 den_k), compared as num_k den_b < num_b den_k
@@ -1150,7 +1160,7 @@ dg_status moving_create(dg_mesh* m, const dg_mesh_desc* d) {
     set_error("dg_mesh_create: moving mesh box must be positive");
     return DG_EINVAL;
   }
-  std::vector<double> pos(2 * n);
+  std::vector<double> pos(4 * n);
   for (int64_t i = 0; i < n; ++i) {
     const double x = d->generators[2 * i], y = d->generators[2 * i + 1];
     if (!std::isfinite(x) || !std::isfinite(y) || x < 0 || x >= Lx || y < 0 || y >= Ly) {
@@ -1159,6 +1169,8 @@ dg_status moving_create(dg_mesh* m, const dg_mesh_desc* d) {
     }
     pos[i] = x;
     pos[n + i] = y;
+    pos[2 * n + 2 * i] = x;
+    pos[2 * n + 2 * i + 1] = y;
   }
   // initial rings: each cell's face neighbours sorted by angle
   std::vector<std::vector<std::pair<double, int>>> nbr(n);
@@ -1211,14 +1223,14 @@ dg_status moving_create(dg_mesh* m, const dg_mesh_desc* d) {
     v.cand_cap = std::max(0, std::min(kCand, std::atoi(env)));
   hipError_t e = hipSuccess;
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-    e = hipMalloc((void**)&v.pos[k], sizeof(double) * 2 * n);
+    e = hipMalloc((void**)&v.pos[k], sizeof(double) * 4 * n);
     if (e == hipSuccess) e = hipMalloc((void**)&v.ring[k], sizeof(int) * kRing * n);
     if (e == hipSuccess) e = hipMalloc((void**)&v.deg[k], sizeof(int) * n);
     if (e == hipSuccess) e = hipMalloc((void**)&v.geo[k], sizeof(double) * kGeo * n);
   }
   if (e == hipSuccess) e = hipMalloc(&v.ua, m->elem * 12 * n);
   if (e == hipSuccess)
-    e = hipMemcpy(v.pos[0], pos.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice);
+    e = hipMemcpy(v.pos[0], pos.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(v.ring[1], ring.data(), sizeof(int) * kRing * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(v.deg[1], deg.data(), sizeof(int) * n, hipMemcpyHostToDevice);
