@@ -299,6 +299,52 @@ def test_hlld_stationary_contact_and_tangential(oracle):
     assert abs(F[1] - (pL + 0.5 * BL @ BL)) < 1e-13
 
 
+def test_hlld_isolated_rotational_discontinuity(oracle):
+    """An isolated rotational (Alfven) discontinuity is resolved exactly, which pins the
+    HLLD middle (Alfven) states that the contact and tangential cases leave free.  With
+    normal field b, density rho and pressure continuous, the tangential field rotating
+    at fixed magnitude and v_t - s B_t / sqrt(rho) continuous (s = sign(b) sign(u_n - V)),
+    the jump conditions hold for the speed V = u_n - s |b| / sqrt(rho) (checked here:
+    F(u_R) - F(u_L) = V (u_R - u_L)), so the exact flux on the face is F(u_L) for V > 0
+    and F(u_R) for V < 0.  A two-wave HLL flux with the same outer speeds misses it."""
+    rng = np.random.default_rng(21)
+    n = np.array([1.0, 0.0, 0.0])
+    for _ in range(200):
+        rho, p = float(np.exp(rng.normal(0, 0.5))), float(np.exp(rng.normal(0, 0.5)))
+        b = float(rng.uniform(0.2, 1.5)) * rng.choice([-1.0, 1.0])
+        side = rng.choice([-1.0, 1.0])
+        V = float(rng.uniform(-0.5, 0.5))
+        un = side * abs(b) / math.sqrt(rho) + V
+        mag = float(rng.uniform(0.1, 1.0))
+        th = rng.uniform(0, 2 * math.pi, 2)
+        Bt = [mag * np.array([math.cos(a), math.sin(a)]) for a in th]
+        v0 = rng.normal(0, 0.3, 2)
+        s = math.copysign(1.0, b) * side
+
+        def state(bt):
+            v = np.array([un, *(v0 + s * bt / math.sqrt(rho))])
+            B = np.array([b, *bt])
+            return np.array([rho, *(rho * v), p / (G53 - 1) + 0.5 * rho * v @ v + 0.5 * B @ B, *B])
+
+        uL, uR = state(Bt[0]), state(Bt[1])
+        FL = oracle.flux(uL, n, G53, mhd=True)
+        FR = oracle.flux(uR, n, G53, mhd=True)
+        assert np.allclose(FR - FL, V * (uR - uL), rtol=0, atol=1e-12)
+        exact = FL if V > 0 else FR
+        F = oracle.hlld(uL, uR, n, G53)
+        assert np.allclose(F, exact, rtol=1e-13, atol=1e-13), (F, exact)
+        if abs(V) < 0.1 and mag > 0.3 and abs(math.cos(th[0] - th[1])) < 0.5:
+            # outer fast speeds (Davis), then the two-wave HLL average
+            def cf(u):
+                a2 = G53 * p / rho
+                B2 = u[5:8] @ u[5:8] / rho
+                return math.sqrt(0.5 * (a2 + B2 + math.sqrt((a2 + B2) ** 2 - 4 * a2 * b * b / rho)))
+            SL = min(un - cf(uL), un - cf(uR))
+            SR = max(un + cf(uL), un + cf(uR))
+            Fh = (SR * FL - SL * FR + SL * SR * (uR - uL)) / (SR - SL)
+            assert np.abs(Fh - exact).max() > 1e-3
+
+
 # ------------------------------------------------------------------- limiter
 def test_limiter_1d_closed_form(oracle):
     """On data varying along x only, the limited slope is
