@@ -202,20 +202,50 @@ def run_gpu_mh(U0, mesh, gamma, precision, steps, warmup, limiter=True, cfl=0.3,
     return {"wall_s": wall, "event_s": tev, "step_s": tev / steps}
 
 
+def host_cpu() -> str:
+    """The host CPU model (first "model name" of /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(U0, n, nsteps, dim=2, mhd=False, gamma=5.0 / 3.0, label="", flux="hll",
-                 limiter=True):
+                 limiter=True, single_thread_steps=0):
+    """The oracle timed on the host's cores (all of its OpenMP threads); with
+    single_thread_steps > 0 also on one thread for that many steps."""
     import oracle
     om = oracle.Mesh.cartesian((n,) * dim, (0.0,) * dim, (1.0,) * dim)
     dt = oracle.cfl_dt(om, U0, gamma, 0.3, mhd=mhd)
-    t0 = time.perf_counter()
-    U = U0
-    for _ in range(nsteps):
-        U = oracle.step(om, U, dt, gamma, limiter, mhd=mhd, flux=flux)
-    el = time.perf_counter() - t0
-    return {"value": n ** dim * 2 * nsteps / el, "unit": "cell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nsteps} limited SSP-RK2 steps of {label} at {'x'.join([str(n)] * dim)}, "
-                      f"FP64, {el:.1f} s of CPU time"}
+
+    def timed(steps):
+        t0 = time.perf_counter()
+        U = U0
+        for _ in range(steps):
+            U = oracle.step(om, U, dt, gamma, limiter, mhd=mhd, flux=flux)
+        return time.perf_counter() - t0
+
+    el = timed(nsteps)
+    cells = "x".join([str(n)] * dim)
+    out = {"value": n ** dim * 2 * nsteps / el, "unit": "cell-updates/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{nsteps} limited SSP-RK2 steps of {label} at {cells}, "
+                     f"FP64, {el:.1f} s of CPU time",
+           "host_cpu": host_cpu()}
+    if single_thread_steps > 0:
+        threads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        try:
+            el1 = timed(single_thread_steps)
+        finally:
+            oracle.set_num_threads(threads)
+        out["single_thread"] = {"value": n ** dim * 2 * single_thread_steps / el1,
+                                "sample": f"{single_thread_steps} step(s) at {cells} on one "
+                                          f"thread, {el1:.1f} s"}
+    return out
 
 
 def log(msg):
@@ -262,6 +292,7 @@ def bench_mh(a, U0, mesh, ncells, gamma, limiter, workload, oracle_mesh):
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": ncells * a.cpu_steps / el, "unit": "cell-updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
+                               "host_cpu": host_cpu(),
                                "sample": f"{a.cpu_steps} MUSCL-Hancock steps of the same state, "
                                          f"FP64, {el:.1f} s"}
     return out
@@ -320,7 +351,8 @@ def bench_c2(a):
     if not a.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state",
-                                           flux=a.flux, limiter=limiter)
+                                           flux=a.flux, limiter=limiter,
+                                           single_thread_steps=1 if a.flux == "hll" else 0)
     return out
 
 
@@ -470,6 +502,7 @@ def bench_c1(a):
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n * n * 2 * a.cpu_steps / el, "unit": "cell-updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
+                               "host_cpu": host_cpu(),
                                "sample": f"{a.cpu_steps} SSP-RK2 steps of the same {n}x{n} "
                                          f"vortex, FP64, {el:.1f} s"}
     return out
@@ -523,6 +556,7 @@ def bench_c4(a):
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": n * 2 * a.cpu_steps / el, "unit": "cell-updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
+                               "host_cpu": host_cpu(),
                                "sample": f"{a.cpu_steps} limited SSP-RK2 steps on the same "
                                          f"{n}-cell mesh and state, FP64, {el:.1f} s"}
     return out
@@ -652,6 +686,7 @@ def bench_moving(a):
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": n * a.cpu_steps / el, "unit": "cell-updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
+                               "host_cpu": host_cpu(),
                                "sample": f"{a.cpu_steps} moving-mesh steps of the same state "
                                          f"(two Delaunay rebuilds per step), FP64, {el:.1f} s"}
     return out
@@ -855,7 +890,7 @@ def bench_c5(a):
         el = time.perf_counter() - tc
         out_j["cpu_baseline"] = {"value": N0 * N0 * 2 * a.cpu_steps / el,
                                  "unit": "cell-updates/s", "cores": oracle.num_threads(),
-                                 "kind": "oracle",
+                                 "kind": "oracle", "host_cpu": host_cpu(),
                                  "sample": f"{a.cpu_steps} limited SSP-RK2 steps of instance 0 "
                                            f"({N0}x{N0}), FP64, {el:.1f} s"}
     return out_j
