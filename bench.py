@@ -321,6 +321,7 @@ def bench_c2(a):
     value = ncells * 2 * a.steps / r["event_s"]
     stage2_bytes = STAGE_VALUES[2] * elem * ncells
     achieved = stage2_bytes / r["stage2_s"] / 1e9
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
@@ -337,6 +338,8 @@ def bench_c2(a):
                                  and a.limiter == "arepo" else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
                      "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
+        # the same achieved rate against a measured 1 GiB device copy (read + write)
+        "copy_reference": {"copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
                     "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9},
         "wall_s": r["wall_s"],
@@ -894,6 +897,26 @@ def bench_c5(a):
                                  "sample": f"{a.cpu_steps} limited SSP-RK2 steps of instance 0 "
                                            f"({N0}x{N0}), FP64, {el:.1f} s"}
     return out_j
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy rate (GB/s, bytes read + written) of an nbytes
+    buffer on torch's current stream: the practical ceiling of a streaming
+    kernel on this GPU."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
 
 
 def copy_calibration():
