@@ -147,16 +147,19 @@ __device__ __forceinline__ void circumcentre(const double* __restrict__ X, int n
   if (a > b) { t = a; a = b; b = t; }
   if (b > c) { t = b; b = c; c = t; }
   if (a > b) { t = a; a = b; b = t; }
-  const double* Y = X + n;
-  const double px = mimg(X[b] - X[a], Lx), py = mimg(Y[b] - Y[a], Ly);
-  const double qx = mimg(X[c] - X[a], Lx), qy = mimg(Y[c] - Y[a], Ly);
+  // the interleaved copy of the positions: one 16-byte load per generator
+  const double2* P = reinterpret_cast<const double2*>(X + 2 * (size_t)n);
+  const double2 pa = P[a], pb = P[b], pc = P[c];
+  const double px = mimg(pb.x - pa.x, Lx), py = mimg(pb.y - pa.y, Ly);
+  const double qx = mimg(pc.x - pa.x, Lx), qy = mimg(pc.y - pa.y, Ly);
   const double D = 2.0 * (px * qy - py * qx);
   const double pp = px * px + py * py, qq = qx * qx + qy * qy;
   double ux = (qy * pp - py * qq) / D;
   double uy = (px * qq - qx * pp) / D;
   if (a != f) {
-    ux += mimg(X[a] - X[f], Lx);
-    uy += mimg(Y[a] - Y[f], Ly);
+    const double2 pf = P[f];
+    ux += mimg(pa.x - pf.x, Lx);
+    uy += mimg(pa.y - pf.y, Ly);
   }
   ox = ux;
   oy = uy;
@@ -179,7 +182,9 @@ __device__ __forceinline__ void face_geometry(const double* __restrict__ X, int 
   double ax, ay, bx, by;
   circumcentre(X, n, Lx, Ly, L, R, ka, L, ax, ay);
   circumcentre(X, n, Lx, Ly, L, R, kb, L, bx, by);
-  const double dx = mimg(X[R] - X[L], Lx), dy = mimg(X[n + R] - X[n + L], Ly);
+  const double2* P = reinterpret_cast<const double2*>(X + 2 * (size_t)n);
+  const double2 pL = P[L], pR = P[R];
+  const double dx = mimg(pR.x - pL.x, Lx), dy = mimg(pR.y - pL.y, Ly);
   double ex = bx - ax, ey = by - ay;
   if (ey * dx - ex * dy < 0.0) {
     double t = ax; ax = bx; bx = t;
@@ -363,10 +368,13 @@ __global__ __launch_bounds__(256) void k_mv_lim(PM<T> p) {
         b0[v] = b1[v] = T(0);
         hi[v] = lo[v] = wi[v];
       }
+      const double2* P = reinterpret_cast<const double2*>(s.x + 2 * (size_t)n);
+      const double2 pe = P[e];
       for (int k = 0; k < d; ++k) {
         const int j = re[k];
-        const T dnx = (T)(mimg(s.x[j] - s.x[e], p.Lx) + s.geo[1 * n + j] - dcx);
-        const T dny = (T)(mimg(s.x[n + j] - s.x[n + e], p.Ly) + s.geo[2 * n + j] - dcy);
+        const double2 pj = P[j];
+        const T dnx = (T)(mimg(pj.x - pe.x, p.Lx) + s.geo[1 * n + j] - dcx);
+        const T dny = (T)(mimg(pj.y - pe.y, p.Ly) + s.geo[2 * n + j] - dcy);
         a00 += dnx * dnx;
         a01 += dnx * dny;
         a11 += dny * dny;
@@ -846,6 +854,9 @@ void k_mv_upd(PM<T> p) {
   const MSet& s0 = p.s0;
   const MSet& sh = p.sh;
   const double* Xh = sh.x;
+  // interleaved (x, y) positions of the half step and of t^n
+  const double2* PH = reinterpret_cast<const double2*>(Xh + 2 * (size_t)n);
+  const double2* P0 = reinterpret_cast<const double2*>(s0.x + 2 * (size_t)n);
   bool bad = false;
   T qe[12];
   load12(p.ua, n, e, qe);
@@ -869,10 +880,11 @@ void k_mv_upd(PM<T> p) {
     const T wLx = p.motion ? qL[3] / qL[0] : T(0), wLy = p.motion ? qL[6] / qL[0] : T(0);
     const T wRx = p.motion ? qR[3] / qR[0] : T(0), wRy = p.motion ? qR[6] / qR[0] : T(0);
     // offsets of L's half-step generator from its t^n centroid, and R's
-    const double oLx = mimg(Xh[L] - s0.x[L], p.Lx) - s0.geo[1 * n + L];
-    const double oLy = mimg(Xh[n + L] - s0.x[n + L], p.Ly) - s0.geo[2 * n + L];
-    const double oRx = mimg(Xh[R] - s0.x[R], p.Lx) - s0.geo[1 * n + R] - g.dx;
-    const double oRy = mimg(Xh[n + R] - s0.x[n + R], p.Ly) - s0.geo[2 * n + R] - g.dy;
+    const double2 hL = PH[L], hR = PH[R], zL = P0[L], zR = P0[R];
+    const double oLx = mimg(hL.x - zL.x, p.Lx) - s0.geo[1 * n + L];
+    const double oLy = mimg(hL.y - zL.y, p.Ly) - s0.geo[2 * n + L];
+    const double oRx = mimg(hR.x - zR.x, p.Lx) - s0.geo[1 * n + R] - g.dx;
+    const double oRy = mimg(hR.y - zR.y, p.Ly) - s0.geo[2 * n + R] - g.dy;
     const double dd = g.dx * g.dx + g.dy * g.dy;
     const T nx = (T)g.nx, ny = (T)g.ny, wq = (T)(0.5 * g.A);
     const double mx = 0.5 * (g.ax + g.bx), my = 0.5 * (g.ay + g.by);
@@ -908,8 +920,9 @@ void k_mv_upd(PM<T> p) {
   {
     const double Vh = sh.geo[e], a = sh.geo[3 * n + e], b = sh.geo[4 * n + e],
                  c = sh.geo[5 * n + e];
-    const double ox = mimg(Xh[e] - s0.x[e], p.Lx) + sh.geo[1 * n + e] - s0.geo[1 * n + e];
-    const double oy = mimg(Xh[n + e] - s0.x[n + e], p.Ly) + sh.geo[2 * n + e] - s0.geo[2 * n + e];
+    const double2 he = PH[e], ze = P0[e];
+    const double ox = mimg(he.x - ze.x, p.Lx) + sh.geo[1 * n + e] - s0.geo[1 * n + e];
+    const double oy = mimg(he.y - ze.y, p.Ly) + sh.geo[2 * n + e] - s0.geo[2 * n + e];
     const double tr = 0.5 * (a + c), disc = sqrt(0.25 * (a - c) * (a - c) + b * b);
     const double lam[2] = {tr + disc, tr - disc};
     double ev[2][2];
