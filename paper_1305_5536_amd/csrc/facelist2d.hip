@@ -35,6 +35,7 @@ namespace dg {
 // working precision for geometry).
 struct FLDev {
   int ncells, nblocks, max_slots;
+  int64_t ninc;       // incidences of the global CSR (2 x faces)
   int* blk_cell0;     // [nblocks+1] first cell of each block
   int* blk_slot0;     // [nblocks+1] first slot of each block
   int* slot_cells;    // [2*nslots] global L, R
@@ -44,7 +45,7 @@ struct FLDev {
   void* cell_geo;     // [ncells][8] 1/V, Minv00, Minv01, Minv11, a1x, a1y, a2x, a2y
   int* lim_inc0;      // [ncells+1] global CSR for the limiter and the CFL bound
   int* lim_nbr;       // neighbour cell of each incidence
-  void* lim_geo;      // [ninc][4] face-centroid offset (2), A n outward (2)
+  void* lim_geo;      // [ninc][2] face-centroid offsets, then [ninc][2] A n outward
   void* cell_perim;   // [ncells] sum of face lengths
 };
 
@@ -73,7 +74,8 @@ struct PF {
   const T* cell_geo;
   const int* lim_inc0;
   const int* lim_nbr;
-  const T* lim_geo;
+  const T* lim_geo;  // face-centroid offsets (the limiter)
+  const T* lim_an;   // A n outward (the CFL bound)
   const T* perim;
 };
 
@@ -148,8 +150,8 @@ __global__ __launch_bounds__(256) void k_fl_lim(PF<T> p) {
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int i = b0 + u < i1 ? b0 + u : b0;
-      rx[u] = p.lim_geo[4 * i];
-      ry[u] = p.lim_geo[4 * i + 1];
+      rx[u] = p.lim_geo[2 * i];
+      ry[u] = p.lim_geo[2 * i + 1];
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
       const double cs = sqrt((double)p.gamma * pr * ir);
       double s = cs * (double)p.perim[e];
       for (int i = p.lim_inc0[e]; i < p.lim_inc0[e + 1]; ++i)
-        s += fabs(ux * (double)p.lim_geo[4 * i + 2] + uy * (double)p.lim_geo[4 * i + 3]);
+        s += fabs(ux * (double)p.lim_an[2 * i] + uy * (double)p.lim_an[2 * i + 1]);
       dtmin = 2.0 / ((double)iV * s);
     }
   }
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(256) void k_fl_cfl(PF<T> p) {
     const double cs = sqrt((double)p.gamma * pr * ir);
     double s = cs * (double)p.perim[e];
     for (int i = p.lim_inc0[e]; i < p.lim_inc0[e + 1]; ++i)
-      s += fabs(ux * (double)p.lim_geo[4 * i + 2] + uy * (double)p.lim_geo[4 * i + 3]);
+      s += fabs(ux * (double)p.lim_an[2 * i] + uy * (double)p.lim_an[2 * i + 1]);
     d = 2.0 / ((double)p.cell_geo[8 * (size_t)e] * s);
   }
   d = wave_min(d);
@@ -365,6 +367,7 @@ PF<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.lim_inc0 = f.lim_inc0;
   p.lim_nbr = f.lim_nbr;
   p.lim_geo = static_cast<const T*>(f.lim_geo);
+  p.lim_an = p.lim_geo + 2 * f.ninc;
   p.perim = static_cast<const T*>(f.cell_perim);
   return p;
 }
@@ -526,7 +529,9 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   }
   for (int64_t e = 0; e < nc; ++e) inc0[e + 1] += inc0[e];
   std::vector<int> fill(inc0.begin(), inc0.end() - 1), nbr(inc0[nc]);
-  std::vector<double> lgeo(4 * (size_t)inc0[nc]);
+  // offsets of all incidences, then their A n (the limiter reads only the first block)
+  const size_t ninc = (size_t)inc0[nc];
+  std::vector<double> lgeo(4 * ninc);
   // face geometry offsets (from each side's centroid)
   auto offsets = [&](int64_t f, double* rc, double* dLR) {
     const int L = d->face_cells[2 * f], R = d->face_cells[2 * f + 1];
@@ -543,16 +548,16 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
     const double A = d->face_area[f], nx = d->face_normal[2 * f], ny = d->face_normal[2 * f + 1];
     int i = fill[L]++;
     nbr[i] = R;
-    lgeo[4 * i] = rc[0];
-    lgeo[4 * i + 1] = rc[1];
-    lgeo[4 * i + 2] = A * nx;
-    lgeo[4 * i + 3] = A * ny;
+    lgeo[2 * i] = rc[0];
+    lgeo[2 * i + 1] = rc[1];
+    lgeo[2 * ninc + 2 * i] = A * nx;
+    lgeo[2 * ninc + 2 * i + 1] = A * ny;
     i = fill[R]++;
     nbr[i] = L;
-    lgeo[4 * i] = rc[0] - dLR[0];
-    lgeo[4 * i + 1] = rc[1] - dLR[1];
-    lgeo[4 * i + 2] = -A * nx;
-    lgeo[4 * i + 3] = -A * ny;
+    lgeo[2 * i] = rc[0] - dLR[0];
+    lgeo[2 * i + 1] = rc[1] - dLR[1];
+    lgeo[2 * ninc + 2 * i] = -A * nx;
+    lgeo[2 * ninc + 2 * i + 1] = -A * ny;
   }
   // face ids per cell (same order as the global CSR)
   std::vector<int> cface(inc0[nc]), cside(inc0[nc]);
@@ -639,6 +644,7 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   fd->ncells = (int)nc;
   fd->nblocks = nblocks;
   fd->max_slots = max_slots;
+  fd->ninc = (int64_t)ninc;
   m->fld = fd;
   m->fl.nblocks = nblocks;
   m->ncells = nc;
