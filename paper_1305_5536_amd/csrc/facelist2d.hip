@@ -42,6 +42,8 @@ struct FLDev {
   void* slot_geo;     // [nslots][10] nx, ny, w, rL0x, rL0y, rL1x, rL1y, rR0x, rR0y, (rR1 = rR0 + rL1 - rL0)
   int* cell_inc0;     // [ncells+1] block-local CSR start (global index into cell_inc)
   int* cell_inc;      // slot_local*2 + side
+  void* inc_geo;      // [per cell_inc entry][5] signed weight (+-A/2), the two Gauss
+                      // points' offsets from the cell's own centroid
   void* cell_geo;     // [ncells][8] 1/V, Minv00, Minv01, Minv11, a1x, a1y, a2x, a2y
   int* lim_inc0;      // [ncells+1] global CSR for the limiter and the CFL bound
   int* lim_nbr;       // neighbour cell of each incidence
@@ -71,6 +73,7 @@ struct PF {
   const T* slot_geo;
   const int* cell_inc0;
   const int* cell_inc;
+  const T* inc_geo;
   const T* cell_geo;
   const int* lim_inc0;
   const int* lim_nbr;
@@ -221,20 +224,14 @@ __global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
     T rm[4] = {T(0), T(0), T(0), T(0)};
     T rx[4] = {T(0), T(0), T(0), T(0)};
     T ry[4] = {T(0), T(0), T(0), T(0)};
+    // the cell's incidences: the slot's fluxes from LDS, this side's weight and
+    // Gauss-point offsets from a record laid out in incidence order (the
+    // block's cells read one contiguous run of them)
     const int i0 = p.cell_inc0[e], i1 = p.cell_inc0[e + 1];
     for (int i = i0; i < i1; ++i) {
-      const int code = p.cell_inc[i];
-      const int ls = code >> 1, side = code & 1;
-      const T* g = p.slot_geo + 10 * (size_t)(s0 + ls);
-      const T w = side ? g[2] : -g[2];
-      T r0x, r0y, r1x, r1y;
-      if (side == 0) {
-        r0x = g[3]; r0y = g[4]; r1x = g[5]; r1y = g[6];
-      } else {
-        r0x = g[7]; r0y = g[8];
-        r1x = g[7] + (g[5] - g[3]);
-        r1y = g[8] + (g[6] - g[4]);
-      }
+      const int ls = p.cell_inc[i] >> 1;
+      const T* g = p.inc_geo + 5 * (size_t)i;
+      const T w = g[0], r0x = g[1], r0y = g[2], r1x = g[3], r1y = g[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const T f0 = sF[ls][v], f1 = sF[ls][4 + v];
@@ -363,6 +360,7 @@ PF<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.slot_geo = static_cast<const T*>(f.slot_geo);
   p.cell_inc0 = f.cell_inc0;
   p.cell_inc = f.cell_inc;
+  p.inc_geo = static_cast<const T*>(f.inc_geo);
   p.cell_geo = static_cast<const T*>(f.cell_geo);
   p.lim_inc0 = f.lim_inc0;
   p.lim_nbr = f.lim_nbr;
@@ -576,7 +574,7 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   // blocks of up to kBlock consecutive cells; a block is halved until its
   // distinct incident faces fit the LDS flux table
   std::vector<int> blk_cell0{0}, blk_slot0{0}, slot_cells, cell_inc0(nc + 1, 0), cell_inc;
-  std::vector<double> sgeo;
+  std::vector<double> sgeo, igeo;
   {
     std::vector<int64_t> mark(nf, -1);
     int64_t stamp = 0, e = 0;
@@ -627,6 +625,26 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
           sgeo.insert(sgeo.end(), g, g + 10);
         }
         cell_inc.push_back(slot_of_face[f] * 2 + cside[i]);
+        {
+          // this side's weight and Gauss-point offsets (R: rR1 = rR0 + (rL1 - rL0))
+          double rc[2], dLR[2];
+          offsets(f, rc, dLR);
+          const double A = d->face_area[f], nx = d->face_normal[2 * f],
+                       ny = d->face_normal[2 * f + 1];
+          const double o = A / (2.0 * std::sqrt(3.0));
+          const double t[2] = {-ny, nx};
+          const double rL0[2] = {rc[0] - o * t[0], rc[1] - o * t[1]};
+          const double rL1[2] = {rc[0] + o * t[0], rc[1] + o * t[1]};
+          if (cside[i] == 0) {
+            const double r[5] = {-0.5 * A, rL0[0], rL0[1], rL1[0], rL1[1]};
+            igeo.insert(igeo.end(), r, r + 5);
+          } else {
+            const double rR0[2] = {rL0[0] - dLR[0], rL0[1] - dLR[1]};
+            const double r[5] = {0.5 * A, rR0[0], rR0[1], rR0[0] + (rL1[0] - rL0[0]),
+                                 rR0[1] + (rL1[1] - rL0[1])};
+            igeo.insert(igeo.end(), r, r + 5);
+          }
+        }
       }
       cell_inc0[c + 1] = (int)cell_inc.size();
     }
@@ -660,6 +678,7 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
     return f64 ? upload<double>(h, dst) : upload<float>(h, dst);
   };
   if (err == hipSuccess) err = up(sgeo, &fd->slot_geo);
+  if (err == hipSuccess) err = up(igeo, &fd->inc_geo);
   if (err == hipSuccess) err = up(cgeo, &fd->cell_geo);
   if (err == hipSuccess) err = up(lgeo, &fd->lim_geo);
   if (err == hipSuccess) err = up(perim, &fd->cell_perim);
@@ -679,6 +698,7 @@ void facelist_destroy(dg_mesh* m) {
   (void)hipFree(f->slot_geo);
   (void)hipFree(f->cell_inc0);
   (void)hipFree(f->cell_inc);
+  (void)hipFree(f->inc_geo);
   (void)hipFree(f->cell_geo);
   (void)hipFree(f->lim_inc0);
   (void)hipFree(f->lim_nbr);
