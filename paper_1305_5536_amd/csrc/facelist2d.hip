@@ -14,8 +14,9 @@
 //   1. each thread solves the Riemann problems of some slots (HLL at both Gauss
 //      points) and writes the 2 x 4 fluxes to LDS;
 //   2. after one barrier each thread gathers its own cell's incidences from
-//      LDS (a segmented reduction, no atomics), adds the volume term, applies
-//      M^-1 and the RK combination.
+//      LDS (a segmented reduction, no atomics; each incidence's weight and
+//      Gauss-point offsets come from a record stored in incidence order), adds
+//      the volume term, applies M^-1 and the RK combination.
 // The limiter is a separate pass (k_fl_lim) into the workspace, as on 3D
 // meshes; stage 2 reuses Pi(U^n) from stage 1.
 #include <hip/hip_runtime.h>
