@@ -494,6 +494,17 @@ def bench_c1(a):
            "config": {"workload": f"2D Euler isentropic vortex, periodic Cartesian {n}x{n} on "
                                   "[0,10]^2, gamma 1.4, HLL, no limiter, SSP-RK2 CFL 0.3",
                       "cells": n * n, "note": "the state fits in L2: launch-latency bound"}}
+    # algorithmic bytes of both stages over the whole step (the stage kernels and the
+    # one-workgroup dt reduction are three short launches here)
+    elem = 8 if a.precision == "fp64" else 4
+    step_bytes = (STAGE_VALUES[1] + STAGE_VALUES[2]) * elem * n * n
+    achieved = step_bytes / (t / a.steps) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_cart2d stages 1 and 2 with the dt reduction (one step)",
+                       "bytes_per_step": step_bytes, "step_s": t / a.steps,
+                       "note": f"the {n}x{n} state fits in L2; the step time is launch "
+                               "latency, not bandwidth"}
     if not a.no_cpu:
         import oracle
         om = oracle.Mesh.cartesian((n, n), (0.0, 0.0), (10.0, 10.0))
