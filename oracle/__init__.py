@@ -82,6 +82,8 @@ def lib():
         L.or_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
         L.or_hll.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
         L.or_hlld.argtypes = [ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.or_signal_speed.restype = ctypes.c_double
+        L.or_signal_speed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.or_exact_riemann.restype = ctypes.c_int
         L.or_exact_riemann.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
                                        _dp]
@@ -339,6 +341,15 @@ def hlld(uL, uR, n, gamma: float) -> np.ndarray:
     out = np.zeros(8)
     lib().or_hlld(gamma, _p(uL), _p(uR), _p(n3), _p(out))
     return out
+
+
+def signal_speed(u, n, gamma: float, mhd: bool = False) -> float:
+    """Sound speed (Euler) or fast magnetosonic speed along the unit normal n
+    (MHD) of one conserved state."""
+    u = _f64(u)
+    n3 = _f64(list(n) + [0.0] * (3 - len(n)))
+    dim = 3 if mhd else len(n)
+    return lib().or_signal_speed(dim, int(mhd), gamma, _p(u), _p(n3))
 
 
 def exact_riemann(uL, uR, n, gamma: float):

@@ -29,7 +29,13 @@
 //
 // Parity pins live in tests/ (convergence on exact solutions, conservation,
 // free-stream preservation, FV reduction, Riemann-solver invariants, limiter
-// closed forms, Gram/mass-matrix closed forms, divergence-free basis).
+// closed forms, Gram/mass-matrix closed forms, divergence-free basis; a
+// face-by-face NumPy assembly of the weak form on tiny meshes; the CFL step's
+// closed forms on boxes; the signal speed as the largest eigenvalue of the flux
+// Jacobian; where HLLD's outer speeds switch to the upwind flux; the common
+// field alpha's 1D closed form).  One reading stays shared rather than pinned:
+// the switch of HLLD's star states to the outer values when its denominator is
+// degenerate (a tolerance of 1e-12 relative).
 
 #include <algorithm>
 #include <cmath>
@@ -1688,6 +1694,13 @@ void or_hll(int dim, int mhd, double gamma, const double* uL, const double* uR, 
 void or_hlld(double gamma, const double* uL, const double* uR, const double* n, double* F) {
   Phys P{3, 1, gamma};
   hlld(P, uL, uR, n, F);
+}
+// Signal speed of one state along the unit normal n: the sound speed
+// (Euler) or the fast magnetosonic speed (MHD), the speed the CFL bound and
+// the outer HLL/HLLD wave estimates use.
+double or_signal_speed(int dim, int mhd, double gamma, const double* u, const double* n) {
+  Phys P{dim, mhd, gamma};
+  return signal_speed(P, u, n);
 }
 // Exact Euler Riemann solver on single states: flux F, star = (p*, u*) and
 // the primitive state (rho, u_n, p) on the face.  Returns 0, or 1 on vacuum
