@@ -150,7 +150,11 @@ typedef struct {
 } dg_mesh_desc;
 
 /* Create a mesh handle: validates the descriptor and configuration, uploads
- * the geometry and allocates the workspace.  On failure *out is NULL. */
+ * the geometry and allocates the workspace.  On failure *out is NULL.  The
+ * kernels address coefficient k of cell e as k * ncells + e in 32 bits, so
+ * meshes with ncells * ncoef >= 2^31 (e.g. a 3D MHD box above ~69M cells) and
+ * face lists with 12 ncells >= 2^31 or 20 nfaces >= 2^31 return DG_EINVAL
+ * before any allocation. */
 dg_status dg_mesh_create(const dg_mesh_desc* desc, const dg_config* cfg, dg_mesh_t* out);
 
 /* Release the handle and its device memory (synchronises the device).
@@ -347,6 +351,57 @@ dg_status dg_mesh_geometry(dg_mesh_t mesh, double* generators, double* volume, d
  * other kinds. */
 dg_status dg_set_moving_timing(dg_mesh_t mesh, int on);
 dg_status dg_moving_timing(dg_mesh_t mesh, double* avg_ms, int* nsteps);
+
+/* ------------------------------------------------------------ batch handles
+ * Many independent periodic 2D Euler simulations of uneven sizes advanced
+ * together (the batched stepper).  A dg_batch_t is built from single meshes
+ * and owns one batch mesh (kind 2) whose state stores the instances one after
+ * another in the coefficient-major arrays (see "Batches" above); every call
+ * below forwards to the mesh-handle entry points on it, and dg_batch_mesh
+ * exposes that handle for the others (dg_rhs, dg_stage1/2, dg_cfl_dt,
+ * dg_check, ...).  Computes what the single meshes compute (Sec. 2.2-2.5),
+ * instance by instance, bit for bit. */
+typedef struct dg_batch* dg_batch_t;
+
+/* Build a batch from ninst single meshes: each meshes[i] a 2D Cartesian Euler
+ * mesh (kind 0), all with the same dg_config; instance i takes meshes[i]'s
+ * cells and box.  The meshes are only read (they stay valid and independent).
+ * autotune_cache: NULL for the library's default launch shape, or the path of
+ * a text file holding three integers "rows waves_per_group grid_waves" (the
+ * shape an autotuner chose for this batch: dg_set_tiling and dg_set_launch
+ * values).  DG_EUNSUPPORTED for other mesh kinds or physics; DG_EINVAL for
+ * mismatched configurations, an unreadable or malformed file, or a batch too
+ * large for 32-bit indexing.  On failure *out is NULL. */
+dg_status dg_batch_create(const dg_mesh_t* meshes, int ninst, const char* autotune_cache,
+                          dg_batch_t* out);
+
+/* The batch mesh handle (kind 2) of b, owned by b; NULL for a NULL batch. */
+dg_mesh_t dg_batch_mesh(dg_batch_t b);
+
+/* First cell of instance inst in the batch state (inst = ninst gives the total
+ * cell count), or -1 for a NULL batch or an index outside [0, ninst]. */
+int64_t dg_batch_offset(dg_batch_t b, int inst);
+
+/* Advance every instance nsteps SSP-RK2 steps in place (U, device, the batch
+ * state): the dg_run sequence with DG_RUN_GRAPH (captured once per argument
+ * set into a hipGraph and replayed).  cfl > 0: adaptive per-instance steps,
+ * dt_hist_dev receives (nsteps + 1) * ninst doubles (the step history, as in
+ * dg_run); cfl = 0: dt_hist_dev holds nsteps * ninst given step sizes.  One
+ * step (nsteps = 1) goes through the handle's staging buffer and a device
+ * copy. */
+dg_status dg_batch_run(dg_batch_t b, void* U, double cfl, double* dt_hist_dev, int nsteps,
+                       void* stream);
+
+/* Discrete adjoint of one batch step (dg_adjoint_step with V1 recomputed):
+ * lam_n = (d step(U_n) / d U_n)^T lam_np1 with the per-instance step sizes
+ * dt_dev[ninst] (device).  Same semantics, aliasing rules and workspaces as
+ * dg_adjoint_step. */
+dg_status dg_batch_adjoint_step(dg_batch_t b, const void* U_n, const double* dt_dev,
+                                const void* lam_np1, void* lam_n, void* stream);
+
+/* Release the batch and its batch mesh (synchronises the device).  NULL is
+ * ignored. */
+void dg_batch_destroy(dg_batch_t b);
 
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* dg_last_error(void);

@@ -140,3 +140,11 @@ def autotune_batch(solver, U, sizes, reps: int = 5, use_cache: bool = True) -> d
         db[key] = entry
         _store(db)
     return entry
+
+
+def write_launch_file(path: str, entry: dict) -> str:
+    """Write a batch launch shape (``autotune_batch``'s result) as the text file
+    ``dg_batch_create`` reads: "rows waves_per_group grid_waves"."""
+    with open(path, "w") as f:
+        f.write(f"{int(entry['rows'])} {int(entry['wpb'])} {int(entry['grid'])}\n")
+    return path

@@ -101,6 +101,15 @@ SYMBOLS = [
     ("dg_mesh_geometry", ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp,
                                         ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),
+    ("dg_batch_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                       ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("dg_batch_mesh", ctypes.c_void_p, [ctypes.c_void_p]),
+    ("dg_batch_offset", ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int]),
+    ("dg_batch_run", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    ("dg_batch_adjoint_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_batch_destroy", None, [ctypes.c_void_p]),
     ("dg_last_error", ctypes.c_char_p, []),
 ]
 

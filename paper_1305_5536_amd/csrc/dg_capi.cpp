@@ -268,16 +268,27 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     set_error("dg_mesh_create: face-list meshes are 2D only");
     return DG_EUNSUPPORTED;
   }
+  // face lists address 12 state arrays of ncells and, per face, at most two
+  // block slots of 10 geometry values (and two incidences of 5) in 32 bits
+  if (d->kind == 1 && (d->ncells * 12 >= ((int64_t)1 << 31) || d->nfaces * 20 >= ((int64_t)1 << 31)))
+    return einval("dg_mesh_create: face list too large for 32-bit indexing "
+                  "(needs 12 ncells < 2^31 and 20 nfaces < 2^31)");
   if (d->kind == 0) {
     if (d->dim != 2 && d->dim != 3) return einval("dg_mesh_create: dim must be 2 or 3");
     if (d->dim == 3 && cfg->physics != DG_MHD) {
       set_error("dg_mesh_create: 3D Cartesian meshes are built for MHD only");
       return DG_EUNSUPPORTED;
     }
+    int64_t cells = 1;
     for (int k = 0; k < d->dim; ++k) {
       if (d->n[k] < 1 || d->n[k] > (1 << 20)) return einval("dg_mesh_create: bad cell count");
       if (!(d->hi[k] > d->lo[k])) return einval("dg_mesh_create: hi must exceed lo");
+      cells *= d->n[k];
     }
+    // the kernels address coefficient k of cell e as k * ncells + e in 32 bits
+    const int64_t ncoef = d->dim == 3 ? 31 : (cfg->physics == DG_MHD ? 23 : 12);
+    if (cells * ncoef >= ((int64_t)1 << 31))
+      return einval("dg_mesh_create: mesh too large for 32-bit indexing (ncells * ncoef >= 2^31)");
   }
 
   dg_mesh* m = new (std::nothrow) dg_mesh();
@@ -295,14 +306,14 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     const bool mhd = cfg->physics == DG_MHD;
     m->ncoef = mhd ? 23 : 12;
     m->ncells = d->n[0] * d->n[1];
-    if (m->ncells * m->ncoef >= ((int64_t)1 << 31)) {
-      delete m;
-      return einval("dg_mesh_create: mesh too large for 32-bit indexing");
-    }
     m->c2.nx = (int)d->n[0];
     m->c2.ny = (int)d->n[1];
     m->c2.hx = (d->hi[0] - d->lo[0]) / d->n[0];
     m->c2.hy = (d->hi[1] - d->lo[1]) / d->n[1];
+    for (int k = 0; k < 2; ++k) {
+      m->c2.lo[k] = d->lo[k];
+      m->c2.hi[k] = d->hi[k];
+    }
     m->c2.tiles_x = (int)((d->n[0] + 59) / 60);  // 60 interior columns per wave
     m->c2.rows_per_tile =
         mhd ? default_rows_mhd2d(m->c2.tiles_x, d->n[1]) : default_rows(m->c2.tiles_x, d->n[1]);
@@ -860,6 +871,113 @@ dg_status dg_mesh_geometry(dg_mesh_t m, double* generators, double* volume, doub
   const int r = moving_read(m, generators, volume, centroid, ring, degree);
   if (r) return hip_fail((hipError_t)r, "dg_mesh_geometry: copy");
   return DG_OK;
+}
+
+// ------------------------------------------------------------------ batches
+// A dg_batch_t wraps one batch mesh (kind 2) built from single 2D Cartesian
+// Euler meshes; every call forwards to the mesh-handle entry points.
+
+dg_status dg_batch_create(const dg_mesh_t* meshes, int ninst, const char* autotune_cache,
+                          dg_batch_t* out) {
+  if (!out) return einval("dg_batch_create: out is NULL");
+  *out = nullptr;
+  if (!meshes || ninst < 1) return einval("dg_batch_create: needs ninst >= 1 meshes");
+  const dg_mesh* m0 = meshes[0];
+  if (!m0) return einval("dg_batch_create: NULL mesh");
+  std::vector<int32_t> inst_n(2 * (size_t)ninst);
+  std::vector<double> inst_box(4 * (size_t)ninst);
+  for (int i = 0; i < ninst; ++i) {
+    const dg_mesh* m = meshes[i];
+    if (!m) return einval("dg_batch_create: NULL mesh");
+    if (m->kind != 0 || m->dim != 2 || m->cfg.physics != DG_EULER) {
+      set_error("dg_batch_create: instances must be single 2D Cartesian Euler meshes");
+      return DG_EUNSUPPORTED;
+    }
+    if (m->cfg.precision != m0->cfg.precision || m->cfg.flux != m0->cfg.flux ||
+        m->cfg.limiter != m0->cfg.limiter || m->cfg.gamma != m0->cfg.gamma)
+      return einval("dg_batch_create: instances need identical dg_config");
+    inst_n[2 * i] = m->c2.nx;
+    inst_n[2 * i + 1] = m->c2.ny;
+    inst_box[4 * i] = m->c2.lo[0];
+    inst_box[4 * i + 1] = m->c2.lo[1];
+    inst_box[4 * i + 2] = m->c2.hi[0];
+    inst_box[4 * i + 3] = m->c2.hi[1];
+  }
+  int rows = 0, wpb = 0, grid = -1;
+  if (autotune_cache) {
+    FILE* f = std::fopen(autotune_cache, "r");
+    if (!f) return einval(std::string("dg_batch_create: cannot read ") + autotune_cache);
+    const int got = std::fscanf(f, "%d %d %d", &rows, &wpb, &grid);
+    std::fclose(f);
+    if (got != 3 || rows < 1 || grid < 0)
+      return einval("dg_batch_create: launch file needs 'rows waves_per_group grid_waves'");
+  }
+  dg_mesh_desc d{};
+  d.dim = 2;
+  d.kind = 2;
+  d.ninst = ninst;
+  d.inst_n = inst_n.data();
+  d.inst_box = inst_box.data();
+  dg_mesh_t bm = nullptr;
+  dg_status st = dg_mesh_create(&d, &m0->cfg, &bm);
+  if (st != DG_OK) return st;
+  if (autotune_cache) {
+    st = dg_set_tiling(bm, rows);
+    if (st == DG_OK) st = dg_set_launch(bm, wpb, grid);
+    if (st != DG_OK) {
+      dg_mesh_destroy(bm);
+      return st;
+    }
+  }
+  dg_batch* b = new (std::nothrow) dg_batch();
+  if (!b) {
+    dg_mesh_destroy(bm);
+    set_error("dg_batch_create: out of host memory");
+    return DG_ENOMEM;
+  }
+  b->mesh = bm;
+  *out = b;
+  return DG_OK;
+}
+
+dg_mesh_t dg_batch_mesh(dg_batch_t b) { return b ? b->mesh : nullptr; }
+
+int64_t dg_batch_offset(dg_batch_t b, int inst) {
+  if (!b || inst < 0 || inst > b->mesh->bt.ninst) return -1;
+  return b->mesh->bt.d.off[inst];
+}
+
+dg_status dg_batch_run(dg_batch_t b, void* U, double cfl, double* dt_hist_dev, int nsteps,
+                       void* stream) {
+  if (!b || !U || !dt_hist_dev) return einval("dg_batch_run: NULL argument");
+  if (nsteps < 1) return einval("dg_batch_run: nsteps must be >= 1");
+  dg_mesh* m = b->mesh;
+  if (nsteps >= 2)
+    return dg_run(m, U, U, nsteps, cfl, dt_hist_dev, 0, nullptr, nullptr, DG_RUN_GRAPH, stream);
+  // one step in place: through the handle's staging buffer
+  const size_t bytes = (size_t)m->ncoef * m->ncells * m->elem;
+  if (!m->tmp) {
+    hipError_t e = hipMalloc(&m->tmp, bytes);
+    if (e != hipSuccess) return hip_fail(e, "dg_batch_run: workspace allocation");
+  }
+  dg_status st = dg_run(m, U, m->tmp, 1, cfl, dt_hist_dev, 0, nullptr, nullptr, DG_RUN_GRAPH,
+                        stream);
+  if (st != DG_OK) return st;
+  hipError_t e = hipMemcpyAsync(U, m->tmp, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dg_batch_run: copy");
+  return DG_OK;
+}
+
+dg_status dg_batch_adjoint_step(dg_batch_t b, const void* U_n, const double* dt_dev,
+                                const void* lam_np1, void* lam_n, void* stream) {
+  if (!b || !dt_dev) return einval("dg_batch_adjoint_step: NULL argument");
+  return dg_adjoint_step(b->mesh, U_n, nullptr, 0.0, dt_dev, lam_np1, lam_n, stream);
+}
+
+void dg_batch_destroy(dg_batch_t b) {
+  if (!b) return;
+  dg_mesh_destroy(b->mesh);
+  delete b;
 }
 
 }  // extern "C"

@@ -25,6 +25,7 @@ enum StageMode : int {
 struct Cart2D {
   int nx, ny;
   double hx, hy;
+  double lo[2], hi[2];  // the box as given at create
   int rows_per_tile;  // rows marched by one wave
   int tiles_x, tiles_y;
 };
@@ -91,6 +92,10 @@ struct RunGraph {
 constexpr int kMaxRunGraphs = 32;
 
 }  // namespace dg
+
+struct dg_batch {
+  dg_mesh* mesh = nullptr;  // a batch mesh (kind 2) built from the instances
+};
 
 struct dg_mesh {
   dg_config cfg;

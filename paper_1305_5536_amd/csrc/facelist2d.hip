@@ -431,7 +431,7 @@ void facelist_destroy(dg_mesh* m);
 
 dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   const int64_t nc = d->ncells, nf = d->nfaces;
-  if (nc < 1 || nf < 1 || nc > (1 << 30) || nf > (1 << 30)) {
+  if (nc < 1 || nf < 1) {
     set_error("dg_mesh_create: face list needs ncells >= 1 and nfaces >= 1");
     return DG_EINVAL;
   }

@@ -19,10 +19,33 @@ def declared_functions():
     return names
 
 
+BOUNDARY = (
+    # mesh handles and the per-stage operators
+    "dg_mesh_create", "dg_mesh_destroy", "dg_state_len", "dg_rhs", "dg_limit", "dg_cfl_dt",
+    "dg_step", "dg_adjoint_step", "dg_check", "dg_last_error",
+    # batch handles
+    "dg_batch_create", "dg_batch_offset", "dg_batch_run", "dg_batch_adjoint_step",
+    "dg_batch_destroy",
+)
+
+
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ("dg_mesh_create", "dg_rhs", "dg_limit", "dg_step", "dg_cfl_dt", "dg_check"):
-        assert n in names
+    missing = [n for n in BOUNDARY if n not in names]
+    assert not missing, missing
+
+
+def test_batch_calls_validate_without_gpu():
+    from paper_1305_5536_amd import capi
+    lib = capi.lib()
+    out = ctypes.c_void_p(1)
+    assert lib.dg_batch_create(None, 1, None, ctypes.byref(out)) == capi.DG_EINVAL
+    assert not out.value
+    assert lib.dg_batch_offset(None, 0) == -1
+    assert lib.dg_batch_mesh(None) is None
+    assert lib.dg_batch_run(None, None, 0.3, None, 1, None) == capi.DG_EINVAL
+    assert lib.dg_batch_adjoint_step(None, None, None, None, None, None) == capi.DG_EINVAL
+    lib.dg_batch_destroy(None)
 
 
 def test_library_exports_every_declared_symbol():
@@ -48,3 +71,32 @@ def test_error_path_without_gpu():
     d.dim, d.kind = 2, 0
     assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
         capi.DG_EUNSUPPORTED
+
+
+def test_oversized_meshes_rejected_before_any_device_call():
+    """Meshes whose coefficient offsets would overflow the kernels' 32-bit
+    indexing are refused with DG_EINVAL during validation (no allocation, no
+    launch): a 512^3 MHD box (31 arrays of 134M cells) and a face list with
+    more faces than its slot tables can address."""
+    from paper_1305_5536_amd import capi
+    lib = capi.lib()
+    out = ctypes.c_void_p()
+    cfg = capi.dg_config(capi.DG_MHD, capi.DG_FP64, capi.DG_FLUX_HLLD, 1, 5.0 / 3.0)
+    d = capi.dg_mesh_desc()
+    d.dim, d.kind = 3, 0
+    for k in range(3):
+        d.n[k], d.lo[k], d.hi[k] = 512, 0.0, 1.0
+    assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
+        capi.DG_EINVAL
+    assert b"32-bit" in lib.dg_last_error()
+    assert not out.value
+    cfg = capi.dg_config(capi.DG_EULER, capi.DG_FP64, capi.DG_FLUX_HLL, 1, 5.0 / 3.0)
+    d = capi.dg_mesh_desc()
+    d.dim, d.kind = 2, 1
+    d.ncells, d.nfaces = 40_000_000, 120_000_000
+    assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
+        capi.DG_EINVAL
+    assert b"32-bit" in lib.dg_last_error()
+    d.ncells, d.nfaces = 200_000_000, 3
+    assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
+        capi.DG_EINVAL

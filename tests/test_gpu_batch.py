@@ -213,3 +213,64 @@ def test_batch_autotuner(torch_cuda, tmp_path, monkeypatch):
     b2 = _batch(sizes, precision="fp32")
     assert autotune.autotune_batch(b2, U, sizes)["rows"] == e["rows"]  # from the cache
     assert b2.launch == (e["wpb"], e["grid"])
+
+
+def test_batch_handle_entry_points(torch_cuda, tmp_path):
+    """dg_batch_create / offset / run / adjoint_step / destroy through the C ABI:
+    a batch built from single meshes computes exactly what a batch mesh
+    (kind 2) of the same instances computes, with and without a launch file."""
+    import ctypes
+    from paper_1305_5536_amd import capi as C
+    from paper_1305_5536_amd.solver import _stream
+    torch = torch_cuda
+    lib = C.lib()
+    sizes = [(64, 64), (61, 9), (100, 70), (17, 33), (3, 1)]
+    states = _states(sizes, seed0=700)
+    singles = [_single(n) for n in sizes]
+    ref = _batch(sizes)
+    hs = (ctypes.c_void_p * len(sizes))(*[s._h.value for s in singles])
+    launch = tmp_path / "launch.txt"
+    launch.write_text("8 2 2048\n")
+    for cache in (None, str(launch).encode()):
+        bh = ctypes.c_void_p()
+        assert lib.dg_batch_create(hs, len(sizes), cache, ctypes.byref(bh)) == C.DG_OK, \
+            C.last_error()
+        try:
+            assert lib.dg_batch_mesh(bh) is not None
+            for i in range(len(sizes) + 1):
+                assert lib.dg_batch_offset(bh, i) == ref.offsets[i]
+            assert lib.dg_batch_offset(bh, len(sizes) + 1) == -1
+            for nsteps in (1, 3):
+                U0 = ref.pack(states)
+                U = U0.clone()
+                hist = torch.empty((nsteps + 1) * len(sizes), dtype=torch.float64,
+                                   device=U.device)
+                assert lib.dg_batch_run(bh, U.data_ptr(), 0.3, hist.data_ptr(), nsteps,
+                                        _stream()) == C.DG_OK, C.last_error()
+                want, want_hist = ref.run(U0, nsteps, cfl=0.3)
+                torch.cuda.synchronize()
+                assert torch.equal(U, want), nsteps
+                assert torch.equal(hist, want_hist), nsteps
+            U = ref.pack(states)
+            dt = ref.cfl_dt(U, 0.3)
+            lam = torch.randn_like(U)
+            got = torch.empty_like(U)
+            assert lib.dg_batch_adjoint_step(bh, U.data_ptr(), dt.data_ptr(), lam.data_ptr(),
+                                             got.data_ptr(), _stream()) == C.DG_OK
+            assert torch.equal(got, ref.adjoint_step(U, dt, lam))
+            assert lib.dg_check(lib.dg_batch_mesh(bh)) == C.DG_OK
+        finally:
+            lib.dg_batch_destroy(bh)
+    # malformed launch file, mixed configurations, wrong mesh kinds
+    bad = tmp_path / "bad.txt"
+    bad.write_text("eight\n")
+    bh = ctypes.c_void_p()
+    assert lib.dg_batch_create(hs, len(sizes), str(bad).encode(), ctypes.byref(bh)) == C.DG_EINVAL
+    assert not bh.value
+    other = _single((8, 8), limiter=False)
+    mixed = (ctypes.c_void_p * 2)(singles[0]._h.value, other._h.value)
+    assert lib.dg_batch_create(mixed, 2, None, ctypes.byref(bh)) == C.DG_EINVAL
+    assert lib.dg_batch_create(hs, 0, None, ctypes.byref(bh)) == C.DG_EINVAL
+    for s in singles + [other]:
+        s.close()
+    ref.close()
