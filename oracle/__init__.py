@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dg_oracle.cpp")
-_LIB = os.path.join(_HERE, "libdgoracle.so")
+_PORTABLE = os.path.join(_HERE, "libdgoracle.so")
+_LIB = _PORTABLE  # the copy lib() loads
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -26,15 +27,36 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (no -march=native: the library travels)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+    if force or not os.path.exists(_PORTABLE) or os.path.getmtime(_PORTABLE) < os.path.getmtime(_SRC):
+        tmp = _PORTABLE + ".tmp"
         cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, _PORTABLE)
+    return _PORTABLE
 
 
 _lib = None
+BUILD_FLAGS = "-O2 -std=c++17 -fopenmp"
+
+
+def use_native_build(directory: str) -> bool:
+    """Compile the oracle for this host's CPU (g++ -O3 -march=native, the flags a
+    host timing of the oracle calls for) into ``directory`` and load that copy
+    instead of the portable one.  Must run before the first oracle call; returns
+    False (and keeps the portable build) if the compiler is unavailable."""
+    global _LIB, BUILD_FLAGS
+    if _lib is not None:
+        return False
+    path = os.path.join(directory, "libdgoracle_native.so")
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC,
+           "-o", path]
+    try:
+        subprocess.run(cmd, check=True, capture_output=True)
+    except (OSError, subprocess.CalledProcessError):
+        return False
+    _LIB = path
+    BUILD_FLAGS = "-O3 -march=native -std=c++17 -fopenmp"
+    return True
 
 
 def lib():
