@@ -311,6 +311,18 @@ dg_status dg_get_launch(dg_mesh_t mesh, int* waves_per_group, int* grid_waves);
  * n_f for MHD).  dt_dev is a device pointer to one double. */
 dg_status dg_cfl_dt(dg_mesh_t mesh, const void* U, double cfl, double* dt_dev, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dg_cfl_dt with its
+ * per-wave partial minima in a static device array of 4 MiB per GPU (held
+ * until the process ends) instead of the handle's workspace; the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Same result as dg_cfl_dt, bit for bit.  Built for single 2D Cartesian Euler
+ * meshes (kind 0; DG_EUNSUPPORTED otherwise) of at most 2^25 cells (DG_EINVAL
+ * above).  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (on different streams or from different host threads) race. */
+dg_status dg_cfl_dt_static(dg_mesh_t mesh, const void* U, double cfl, double* dt_dev,
+                           void* stream);
+
 /* Launch shape of the Cartesian stage kernels: the number of rows (2D, and
  * every instance of a batch) or z-planes (3D) one wave marches through.  0
  * restores the library default.

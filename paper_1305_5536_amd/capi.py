@@ -92,6 +92,8 @@ SYMBOLS = [
                                      ctypes.POINTER(ctypes.c_int)]),
     ("dg_cfl_dt", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_cfl_dt_static", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_set_tiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("dg_get_tiling", ctypes.c_int, [ctypes.c_void_p]),
     ("dg_check", ctypes.c_int, [ctypes.c_void_p]),

@@ -33,6 +33,8 @@
 //   d gy /dt  = 3 (sum_q Fy(q) - Sy- - Sy+)/hy^2 + sqrt(3) (Dx- - Dx+)/(hx hy)
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "dg_internal.h"
 #include "dg_math.h"
 #include "euler_exact.h"
@@ -1043,6 +1045,64 @@ hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt
                                hipStream_t s) {
   hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, part, n, cfl, dt);
   return hipGetLastError();
+}
+
+}  // namespace dg
+
+// ------------------------------------------- CFL step without allocation --
+// dg_cfl_dt_static keeps the per-wave partial minima in this file-scope
+// device array instead of the handle's workspace (each GPU holds its own copy
+// until the process ends).  In host code its name is not a device address:
+// the address comes from hipGetSymbolAddress, taken once per device at mesh
+// creation with that device current, and only that pointer reaches kernels.
+static __device__ __align__(256) double scratch[dg::kCflScratchParts];
+
+namespace dg {
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t cart2d_scratch_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[dev] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t cfl_static_t(const dg_mesh* m, double* part, const void* U, double cfl,
+                        double* dt_dev, hipStream_t s) {
+  P2<T> p = make_params<T>(m, U, nullptr, nullptr, nullptr, 0.0);
+  p.dtpart = part;
+  const int64_t nblk = (m->ncells + 255) / 256;
+  hipLaunchKernelGGL((k_cart2d_cfl<T>), dim3((unsigned)nblk), dim3(256), 0, s, p);
+  const int nparts = (int)((m->ncells + 63) / 64);
+  hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, part, nparts, cfl, dt_dev);
+  return hipGetLastError();
+}
+
+// Same kernels as launch_cart2d_cfl; every partial the finalisation reads is
+// written first by the CFL kernel of the same call, so nothing is cleared.
+hipError_t launch_cart2d_cfl_static(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                                    hipStream_t s) {
+  if (4 * ((m->ncells + 255) / 256) > kCflScratchParts) return hipErrorInvalidValue;
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (m->device >= 0 && m->device < kMaxScratchDevices) part = g_scratch[m->device];
+  }
+  if (!part) return hipErrorInvalidSymbol;
+  if (m->cfg.precision == DG_FP64) return cfl_static_t<double>(m, part, U, cfl, dt_dev, s);
+  return cfl_static_t<float>(m, part, U, cfl, dt_dev, s);
 }
 
 }  // namespace dg

@@ -320,6 +320,10 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
     if (cfg->physics == DG_EULER) {
+      // the static scratch of dg_cfl_dt_static on this device (the device
+      // that is current here is the mesh's); without its address only that
+      // entry point is unavailable (it then returns DG_EHIP)
+      if (cart2d_scratch_init() != hipSuccess) (void)hipGetLastError();
       BatchDesc one;
       one.ninst = 1;
       one.nx = {m->c2.nx};
@@ -570,6 +574,27 @@ dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void
   else
     e = launch_cart3d_cfl(m, U, cfl, dt_dev, s);
   if (e != hipSuccess) return hip_fail(e, "dg_cfl_dt launch");
+  return DG_OK;
+}
+
+dg_status dg_cfl_dt_static(dg_mesh_t m, const void* U, double cfl, double* dt_dev,
+                           void* stream) {
+  if (!m || !U || !dt_dev) return einval("dg_cfl_dt_static: NULL argument");
+  if (!(cfl > 0) || !std::isfinite(cfl)) return einval("dg_cfl_dt_static: cfl must be > 0");
+  if (m->kind != 0 || m->dim != 2 || m->cfg.physics != DG_EULER) {
+    set_error("dg_cfl_dt_static: built for single 2D Cartesian Euler meshes");
+    return DG_EUNSUPPORTED;
+  }
+  if (4 * ((m->ncells + 255) / 256) > kCflScratchParts)
+    return einval("dg_cfl_dt_static: mesh above the static scratch limit of " +
+                  std::to_string(kCflScratchParts * 64) + " cells");
+  m->ws_a_fresh = false;
+  hipError_t e = launch_cart2d_cfl_static(m, U, cfl, dt_dev, (hipStream_t)stream);
+  if (e == hipErrorInvalidSymbol) {
+    set_error("dg_cfl_dt_static: no static scratch address for this device");
+    return DG_EHIP;
+  }
+  if (e != hipSuccess) return hip_fail(e, "dg_cfl_dt_static launch");
   return DG_OK;
 }
 

@@ -141,6 +141,12 @@ dg_status hip_fail(hipError_t e, const char* what);
 hipError_t launch_cart2d(const dg_mesh* m, int mode, const void* in, const void* u0, void* out,
                          const double* dt_dev, double dt_host, double cfl, double* dt_next,
                          hipStream_t s);
+// dg_cfl_dt_static: partial minima in a static device array of this many
+// doubles per GPU (4 MiB); the stand-alone CFL kernel writes four per 256 cells.
+constexpr int64_t kCflScratchParts = (int64_t)1 << 19;
+hipError_t cart2d_scratch_init();  // once per device, with that device current
+hipError_t launch_cart2d_cfl_static(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
+                                    hipStream_t s);
 hipError_t launch_cart2d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
 hipError_t launch_cart2d_batch(const dg_mesh* m, int mode, const void* in, const void* u0,
