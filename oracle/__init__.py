@@ -87,6 +87,9 @@ def lib():
         L.or_step_jvp.restype = ctypes.c_int
         L.or_step_jvp.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   _dp, _dp, ctypes.c_double, _dp, _dp]
+        L.or_step_branches.restype = ctypes.c_int
+        L.or_step_branches.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp,
+                                       ctypes.c_double, _dp, ctypes.POINTER(ctypes.c_int)]
         L.or_step_mh.restype = ctypes.c_int
         L.or_step_mh.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  _dp, ctypes.c_double, _dp]
@@ -250,6 +253,23 @@ def step(mesh: Mesh, U, dt: float, gamma: float, limiter: bool, mhd: bool = Fals
     if rc and check:
         raise NonPhysical("non-physical state in step")
     return out
+
+
+def step_branches(mesh: Mesh, U, dt: float, gamma: float, limiter: bool = True):
+    """One SSP-RK2 step (2D Euler, box, HLL) and the branches it takes: int codes
+    [2 stages, ncells, 12] (the limiter of the four variables, then HLL at the
+    two Gauss points of the faces -x, +x, -y, +y).  Two steps took the same
+    branches everywhere exactly when their codes are equal."""
+    U = _state(mesh, U, False)
+    out = np.empty_like(U)
+    codes = np.zeros((2, mesh.ncells, 12), dtype=np.int32)
+    rc = lib().or_step_branches(mesh._h, int(bool(limiter)), gamma, _p(U), dt, _p(out),
+                                codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if rc == 2:
+        raise ValueError("step_branches: 2D Euler on a box only")
+    if rc:
+        raise NonPhysical("non-physical state in step_branches")
+    return out, codes
 
 
 def step_jvp(mesh: Mesh, U, dU, dt: float, gamma: float, limiter: bool, mhd: bool = False):

@@ -431,8 +431,11 @@ template <class T> T signal_speed(const Phys& P, const T* u, const double* n) {
 
 // HLL flux with Davis wave-speed estimates (the build's Euler Riemann solver;
 // the Riemann problem is posed along the face normal, Sec. 2.3).
+// code (optional): the branch taken, for finite-difference checks: 0 left of
+// the fan (F_L), 2 right of it (F_R); inside, 1 | 4 (S_L from the right
+// state) | 8 (S_R from the right state).
 template <class T>
-void hll(const Phys& P, const T* uL, const T* uR, const double* n, T* F) {
+void hll(const Phys& P, const T* uL, const T* uR, const double* n, T* F, int* code = nullptr) {
   int nv = P.nv(), nvel = P.nvel();
   T FL[8], FR[8];
   flux_n(P, uL, n, FL);
@@ -445,6 +448,9 @@ void hll(const Phys& P, const T* uL, const T* uR, const double* n, T* F) {
   T cL = signal_speed(P, uL, n), cR = signal_speed(P, uR, n);
   T SL = dmin(vnL - cL, vnR - cR);
   T SR = dmax(vnL + cL, vnR + cR);
+  if (code)
+    *code = SL >= T(0) ? 0 : SR <= T(0) ? 2
+          : 1 | ((vnR - cR) < (vnL - cL) ? 4 : 0) | ((vnR + cR) > (vnL + cL) ? 8 : 0);
   if (SL >= T(0)) {
     for (int k = 0; k < nv; ++k) F[k] = FL[k];
   } else if (SR <= T(0)) {
@@ -898,7 +904,13 @@ struct Ctx {
   const Mesh* mesh;
   Phys P;
   int limiter;
+  // Optional record of the branches a step takes (2D Euler on boxes, for
+  // finite-difference checks): per stage, per cell kBranchCodes ints: the
+  // limiter of the 4 variables, then HLL at the 2 Gauss points of the 4 faces.
+  int* br = nullptr;
+  int br_stage = 0;
 };
+constexpr int kBranchCodes = 12;
 
 // Semi-discrete right-hand side L(U) for one cell (Sec. 2.2): surface terms
 // over the cell's faces (Gauss points in order), then the volume term, then
@@ -968,8 +980,12 @@ bool rhs_cell(const Ctx& C, const T* U, T* dUdt, int64_t e, double half_dt = -1.
         hlld(P, uL, uR, fg.n, F);
       else if (P.riemann == 1) {
         if (!exact_riemann(P, uL, uR, fg.n, F)) ok = false;
-      } else
-        hll(P, uL, uR, fg.n, F);
+      } else {
+        int* code = nullptr;
+        if (C.br && m * fg.ng + p < kBranchCodes - 4)
+          code = C.br + ((int64_t)C.br_stage * nc + e) * kBranchCodes + 4 + m * fg.ng + p;
+        hll(P, uL, uR, fg.n, F, code);
+      }
       const double* r = sides[m] == 0 ? rL : rR;
       T sg = sides[m] == 0 ? T(-fg.wg[p]) : T(fg.wg[p]);
       for (int k = 0; k < nv; ++k) rmean[k] += sg * F[k];
@@ -1061,6 +1077,7 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
   // Neighbour means and face-centroid offsets from this cell's centroid.
   int nvar = P.mhd ? 8 : nh;
   T phimax[8], phimin[8];
+  int amax[8] = {0}, amin[8] = {0};  // arg-extremal: 0 the cell, m + 1 face m's neighbour
   for (int k = 0; k < nvar; ++k) phimax[k] = phimin[k] = q.m[k];
   double rf[64][3];
   for (int m = 0; m < nfc; ++m) {
@@ -1070,6 +1087,8 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
     Poly<T> qn;
     load_poly(P, U, nc, nb, qn);
     for (int k = 0; k < nvar; ++k) {
+      if (qn.m[k] > phimax[k]) amax[k] = m + 1;
+      if (qn.m[k] < phimin[k]) amin[k] = m + 1;
       phimax[k] = dmax(phimax[k], qn.m[k]);
       phimin[k] = dmin(phimin[k], qn.m[k]);
     }
@@ -1078,8 +1097,11 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
       rf[m][d] = d < dim ? fg.rc[d] - off : 0.0;
     }
   }
-  auto alpha_of = [&](int k, const T* grad) {
+  // code (recorded on request): 0 for alpha = 1, else the face that sets alpha
+  // (m + 1), the bound's arg-extremal neighbour << 4 and its side (max) << 8
+  auto alpha_of = [&](int k, const T* grad, int* code = nullptr) {
     T alpha = T(1);
+    int c = 0;
     for (int m = 0; m < nfc; ++m) {
       T dphi = T(0);
       for (int d = 0; d < dim; ++d) dphi += grad[d] * T(rf[m][d]);
@@ -1090,12 +1112,17 @@ void limit_cell(const Ctx& C, const T* U, T* Ul, int64_t e) {
         psi = (phimin[k] - q.m[k]) / dphi;
       else
         psi = T(1);
+      if (psi < alpha)
+        c = (m + 1) | ((dphi > T(0) ? amax[k] : amin[k]) << 4) | (dphi > T(0) ? 256 : 0);
       alpha = dmin(alpha, psi);
     }
+    if (code) *code = c;
     return alpha;
   };
   for (int v = 0; v < nh; ++v) {
-    T alpha = alpha_of(v, q.g[v]);
+    int* code = nullptr;
+    if (C.br && v < 4) code = C.br + ((int64_t)C.br_stage * nc + e) * kBranchCodes + v;
+    T alpha = alpha_of(v, q.g[v], code);
     for (int d = 0; d < dim; ++d) q.g[v][d] = alpha * q.g[v][d];
   }
   if (P.mhd) {
@@ -1238,7 +1265,10 @@ template <class T> void limit_all(const Ctx& C, const T* U, T* Ul) {
 // One SSP-RK2 step with the limiter at the start of each stage:
 //   Ua = Pi(U);  V1 = Ua + dt L(Ua);  Ub = Pi(V1);
 //   U_next = Ua/2 + (Ub + dt L(Ub))/2.
-template <class T> int step_all(const Ctx& C, const T* U, double dt, T* Un) {
+template <class T> int step_all(const Ctx& C0, const T* U, double dt, T* Un) {
+  Ctx C = C0, C2 = C0;  // the branch record's stage index
+  C.br_stage = 0;
+  C2.br_stage = 1;
   int64_t len = (int64_t)C.P.ncoef() * C.mesh->nc;
   std::vector<T> Ua(len), V1(len), L(len);
   if (C.limiter)
@@ -1249,12 +1279,12 @@ template <class T> int step_all(const Ctx& C, const T* U, double dt, T* Un) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < len; ++i) V1[i] = Ua[i] + T(dt) * L[i];
   std::vector<T>& Ub = L;  // reuse storage
-  if (C.limiter)
-    limit_all(C, V1.data(), Ub.data());
+  if (C2.limiter)
+    limit_all(C2, V1.data(), Ub.data());
   else
     std::copy(V1.begin(), V1.end(), Ub.begin());
   std::vector<T>& L2 = V1;
-  bad |= rhs_all(C, Ub.data(), L2.data());
+  bad |= rhs_all(C2, Ub.data(), L2.data());
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < len; ++i) Un[i] = T(0.5) * Ua[i] + T(0.5) * (Ub[i] + T(dt) * L2[i]);
   return bad;
@@ -1616,6 +1646,21 @@ int or_step(void* h, int mhd, int riemann, int limiter, double gamma, const doub
 }
 
 // MUSCL-Hancock step and operator (Euler only; 5 = non-physical, 4 = MHD).
+// One SSP-RK2 step (2D Euler on a box, HLL) that also records the branches it
+// takes: codes[2][ncells][12] (per stage and cell: the limiter of the four
+// variables, then HLL at the two Gauss points of the four faces, in the
+// cell's face order -x, +x, -y, +y).  Returns 1 on a non-physical state, 2 if
+// the mesh or physics is not a 2D box with Euler.
+int or_step_branches(void* h, int limiter, double gamma, const double* U, double dt, double* Un,
+                     int* codes) {
+  Mesh* M = as_mesh(h);
+  if (M->kind != 0 || M->dim != 2) return 2;
+  Ctx C{M, Phys{2, 0, gamma}, limiter};
+  C.br = codes;
+  std::fill(codes, codes + 2 * M->nc * kBranchCodes, 0);
+  return step_all(C, U, dt, Un);
+}
+
 int or_step_mh(void* h, int riemann, int limiter, double gamma, const double* U, double dt,
                double* Un) {
   Ctx C{as_mesh(h), Phys{as_mesh(h)->dim, 0, gamma, riemann}, limiter};
