@@ -591,8 +591,12 @@ def bench_c4(a):
                    "cells": n, "rk_stages_per_step": 2, "parallelism": "single GPU",
                    "input_generation_s": tgen},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage 1 (k_fl_lim + k_fl_rhs)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (pmc_traffic("k_fl_step_c4_1M_fp64.md", "k_fl_step<double, 1, true>",
+                                             f"{n} cells", (f"{CSRC}/facelist2d.hip",
+                                                            f"{CSRC}/dg_math.h"))
+                                 if a.precision == "fp64" and n == 1_000_000 else None),
+                     "kernel": "k_fl_step<1> (stage 1: limiter, RHS and update in one launch)",
                      "bytes_per_launch": per * n, "avg_launch_s": r["stage1_s"]},
         "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3},
         "wall_s": r["wall_s"],

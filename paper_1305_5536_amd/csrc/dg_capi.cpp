@@ -89,10 +89,10 @@ static int default_rows_mhd2d(int64_t ntiles_x, int64_t nrows) {
   return (int)std::min<int64_t>(rows, nrows);
 }
 
-// Meshes that keep Pi(U) of stage 1 in ws_a for stage 2 (3D MHD and face
-// lists limit in passes of their own into ws_a / ws_b; 2D MHD limits on read
-// and its stage 1 writes Pi(U) to ws_a); the 2D Euler kernels limit inside
-// the stage kernel and recompute Pi(U^n) in stage 2.
+// Meshes that keep Pi(U) of stage 1 in ws_a for stage 2 (3D MHD limits in
+// passes of its own into ws_a / ws_b; 2D MHD and face lists limit on read and
+// their stage 1 writes Pi(U) to ws_a); the 2D Euler Cartesian kernels limit
+// inside the stage kernel and recompute Pi(U^n) in stage 2.
 static bool limiter_pass(const dg_mesh* m) {
   return m->dim == 3 || m->kind == 1 || m->cfg.physics == DG_MHD;
 }
@@ -413,7 +413,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   const bool separate_limiter = limiter_pass(m);
   if (e == hipSuccess && separate_limiter) e = hipMalloc(&m->ws_a, bytes);
   // (2D MHD limits on read: its stage kernels need only ws_a, for Pi(U^n))
-  if (e == hipSuccess && (m->dim == 3 || m->kind == 1)) e = hipMalloc(&m->ws_b, bytes);
+  if (e == hipSuccess && m->dim == 3) e = hipMalloc(&m->ws_b, bytes);
   if (e == hipSuccess) e = hipMalloc(&m->status, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of

@@ -8,17 +8,27 @@
 //
 // Work decomposition.  Cells are split into blocks of up to 256 consecutive
 // indices (a space-filling-curve numbering makes a block compact).  The host
-// lists, per block, every face incident to one of its cells ("slots": faces
-// on the block boundary appear in both blocks) and a block-local CSR from each
-// cell to its (slot, side) incidences.  One workgroup per block:
-//   1. each thread solves the Riemann problems of some slots (HLL at both Gauss
-//      points) and writes the 2 x 4 fluxes to LDS;
-//   2. after one barrier each thread gathers its own cell's incidences from
-//      LDS (a segmented reduction, no atomics; each incidence's weight and
-//      Gauss-point offsets come from a record stored in incidence order), adds
-//      the volume term, applies M^-1 and the RK combination.
-// The limiter is a separate pass (k_fl_lim) into the workspace, as on 3D
-// meshes; stage 2 reuses Pi(U^n) from stage 1.
+// lists, per block, its "halo" (the outside cells that share a face with it)
+// and every face incident to one of its cells ("slots": faces on the block
+// boundary appear in both blocks), each slot with its two cells' block-local
+// indices and one geometry record (unit normal, length, face-centroid offset
+// from L's centroid, offset from L's centroid to R's periodic image), and per
+// cell its incidences (slot, side) with the face-centroid offset from the
+// cell's own centroid.  One workgroup per block, limit on read:
+//   0. the raw coefficients of the block's cells and of its halo go to LDS;
+//   1. each cell of the block is limited from its neighbours' means in LDS and
+//      its incidences' face-centroid offsets; each halo cell from the global
+//      face lists (its neighbours' means gathered); the limited gradients
+//      replace the raw ones in LDS;
+//   2. the slots' Riemann problems (HLL at both Gauss points, which sit at the
+//      face centroid -+ A/(2 sqrt 3) along the tangent) go to an LDS table as
+//      the weighted sum and half-difference of the two fluxes and A n, half
+//      the slots at a time;
+//   3. each cell gathers its incidences from that table (a segmented
+//      reduction, no atomics);
+//   4. the volume term, M^-1 and the RK combination (stage 2 limits U^n of its
+//      own cell for the combination from the neighbours' means in HBM).
+// A stand-alone limiter kernel (k_fl_lim) serves dg_limit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,14 +49,16 @@ struct FLDev {
   int64_t ninc;       // incidences of the global CSR (2 x faces)
   int* blk_cell0;     // [nblocks+1] first cell of each block
   int* blk_slot0;     // [nblocks+1] first slot of each block
-  int* slot_cells;    // [2*nslots] global L, R
-  void* slot_geo;     // [nslots][10] nx, ny, w, rL0x, rL0y, rL1x, rL1y, rR0x, rR0y, (rR1 = rR0 + rL1 - rL0)
+  int* blk_halo0;     // [nblocks+1] first halo entry of each block
+  int* halo_cell;     // global index of each halo cell
+  int* slot_lr;       // [nslots] block-local L | R << 16 (own cell i: i; halo h: nown + h)
+  void* slot_geo;     // [nslots][8] nx, ny, A, x_f - c_L (2), c_R' - c_L (2), 0
   int* cell_inc0;     // [ncells+1] block-local CSR start (global index into cell_inc)
-  int* cell_inc;      // slot_local*2 + side
-  void* inc_geo;      // [per cell_inc entry][5] signed weight (+-A/2), the two Gauss
-                      // points' offsets from the cell's own centroid
-  void* cell_geo;     // [ncells][8] 1/V, Minv00, Minv01, Minv11, a1x, a1y, a2x, a2y
-  int* lim_inc0;      // [ncells+1] global CSR for the limiter and the CFL bound
+  int* cell_inc;      // slot_local*2 + side | neighbour's block-local index << 16,
+                      // each cell's incidences by slot
+  void* inc_rf;       // [per cell_inc entry][2] face centroid - the cell's own centroid
+  void* cell_geo;     // [ncells][8] 1/V, V Minv00, V Minv01, V Minv11, a1x, a1y, a2x, a2y
+  int* lim_inc0;      // [ncells+1] global CSR for k_fl_lim, halo cells and the CFL bound
   int* lim_nbr;       // neighbour cell of each incidence
   void* lim_geo;      // [ninc][2] face-centroid offsets, then [ninc][2] A n outward
   void* cell_perim;   // [ncells] sum of face lengths
@@ -54,14 +66,18 @@ struct FLDev {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kMaxSlots = 1024;  // LDS table: 64 KB of fluxes in FP64
+constexpr int kBlock = 256;      // cells of a block at most (one thread each)
+constexpr int kMaxSlots = 1024;  // distinct faces of a block
+constexpr int kMaxHalo = 128;    // outside neighbours of a block
+constexpr int kHalf = 512;       // slots per pass of the LDS flux table
+constexpr int kLocal = kBlock + kMaxHalo;
 
 template <typename T>
 struct PF {
   const T* __restrict__ in;
   const T* __restrict__ ua;
   T* __restrict__ out;
+  T* __restrict__ lim_out;  // stage 1: Pi(in) of each cell (NULL: not kept)
   const double* dt_dev;
   double dt_host;
   int* status;
@@ -70,11 +86,13 @@ struct PF {
   T gamma;
   const int* blk_cell0;
   const int* blk_slot0;
-  const int* slot_cells;
+  const int* blk_halo0;
+  const int* halo_cell;
+  const int* slot_lr;
   const T* slot_geo;
   const int* cell_inc0;
   const int* cell_inc;
-  const T* inc_geo;
+  const T* inc_rf;
   const T* cell_geo;
   const int* lim_inc0;
   const int* lim_nbr;
@@ -176,76 +194,269 @@ __global__ __launch_bounds__(256) void k_fl_lim(PF<T> p) {
   }
 }
 
-// ------------------------------------------------------------------ RHS --
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
-  __shared__ T sF[kMaxSlots][8];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int c0 = p.blk_cell0[b], c1 = p.blk_cell0[b + 1];
-  const int s0 = p.blk_slot0[b], s1 = p.blk_slot0[b + 1];
-  const int nc = p.nc;
-  bool bad = false;
-  // 1. face fluxes into LDS
-  for (int s = s0 + (int)threadIdx.x; s < s1; s += kBlock) {
-    const int L = p.slot_cells[2 * s], R = p.slot_cells[2 * s + 1];
-    const T* g = p.slot_geo + 10 * (size_t)s;
-    const T nx = g[0], ny = g[1];
-    const T rL0x = g[3], rL0y = g[4], rL1x = g[5], rL1y = g[6], rR0x = g[7], rR0y = g[8];
-    const T rR1x = rR0x + (rL1x - rL0x), rR1y = rR0y + (rL1y - rL0y);
-    T qL[12], qR[12];
-    load12(p.in, nc, L, qL);
-    load12(p.in, nc, R, qR);
-    T uL[4], uR[4], F0[4], F1[4];
+// ------------------------------------------------------------ stage --
+// alpha = min(1, min_f psi_f) of one conserved variable (Sec. 2.5): psi from
+// the face-centroid increment d = g . (x_f - c) and the bounds hi, lo of the
+// means of the cell and its face neighbours.
+template <typename T>
+__device__ __forceinline__ T psi_of(T d, T phi, T hi, T lo) {
+  const T num = d > T(0) ? hi - phi : lo - phi;
+  return d > T(0) ? div_small(num, d) : (d < T(0) ? div_small(-num, -d) : T(1));
+}
+
+// Limit the gradients of q (12 coefficients, means untouched) of a block cell
+// whose incidences are [i0, i1) of the block-local CSR, from the block-local
+// means m[v][local] in LDS.  Incidences are taken kInc at a time with all
+// their loads in flight; padding entries repeat the cell itself (no change to
+// a bound, psi = 1).
+constexpr int kInc = 4;
+template <typename T>
+__device__ __forceinline__ void limit_block_cell(const PF<T>& p, int i0, int i1, int self,
+                                                 const T (*m)[kLocal], T* q) {
+  T hi[4], lo[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      uL[v] = fma(qL[3 * v + 1], rL0x, fma(qL[3 * v + 2], rL0y, qL[3 * v]));
-      uR[v] = fma(qR[3 * v + 1], rR0x, fma(qR[3 * v + 2], rR0y, qR[3 * v]));
-    }
-    hll_n(uL, uR, nx, ny, p.gamma, F0, bad);
+  for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
+  T alpha[4] = {T(1), T(1), T(1), T(1)};
+  for (int b0 = i0; b0 < i1; b0 += kInc) {
+    int nb[kInc];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      uL[v] = fma(qL[3 * v + 1], rL1x, fma(qL[3 * v + 2], rL1y, qL[3 * v]));
-      uR[v] = fma(qR[3 * v + 1], rR1x, fma(qR[3 * v + 2], rR1y, qR[3 * v]));
-    }
-    hll_n(uL, uR, nx, ny, p.gamma, F1, bad);
-    const int ls = s - s0;
+    for (int u = 0; u < kInc; ++u) nb[u] = b0 + u < i1 ? (p.cell_inc[b0 + u] >> 16) : self;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      sF[ls][v] = F0[v];
-      sF[ls][4 + v] = F1[v];
-    }
-  }
-  __syncthreads();
-  // 2. per cell: gather incident faces, volume term, M^-1, RK combination
-  const int e = c0 + (int)threadIdx.x;
-  double dtmin = 1e300;
-  if (e < c1) {
-    T q[12];
-    load12(p.in, nc, e, q);
-    T rm[4] = {T(0), T(0), T(0), T(0)};
-    T rx[4] = {T(0), T(0), T(0), T(0)};
-    T ry[4] = {T(0), T(0), T(0), T(0)};
-    // the cell's incidences: the slot's fluxes from LDS, this side's weight and
-    // Gauss-point offsets from a record laid out in incidence order (the
-    // block's cells read one contiguous run of them)
-    const int i0 = p.cell_inc0[e], i1 = p.cell_inc0[e + 1];
-    for (int i = i0; i < i1; ++i) {
-      const int ls = p.cell_inc[i] >> 1;
-      const T* g = p.inc_geo + 5 * (size_t)i;
-      const T w = g[0], r0x = g[1], r0y = g[2], r1x = g[3], r1y = g[4];
+    for (int u = 0; u < kInc; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const T f0 = sF[ls][v], f1 = sF[ls][4 + v];
-        rm[v] = fma(w, f0 + f1, rm[v]);
-        rx[v] = fma(w, fma(f0, r0x, f1 * r1x), rx[v]);
-        ry[v] = fma(w, fma(f0, r0y, f1 * r1y), ry[v]);
+        const T mm = m[3 * v][nb[u]];
+        hi[v] = fmax(hi[v], mm);
+        lo[v] = fmin(lo[v], mm);
+      }
+  }
+  for (int b0 = i0; b0 < i1; b0 += kInc) {
+    T rx[kInc], ry[kInc];
+#pragma unroll
+    for (int u = 0; u < kInc; ++u) {
+      const int i = b0 + u < i1 ? b0 + u : b0;
+      rx[u] = p.inc_rf[2 * (size_t)i];
+      ry[u] = p.inc_rf[2 * (size_t)i + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kInc; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        alpha[v] = fmin(alpha[v], psi_of(q[3 * v + 1] * rx[u] + q[3 * v + 2] * ry[u], q[3 * v],
+                                         hi[v], lo[v]));
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    q[3 * v + 1] *= alpha[v];
+    q[3 * v + 2] *= alpha[v];
+  }
+}
+
+// The same limiter for a cell outside the block (a halo cell) from the global
+// face lists: neighbour means gathered from `U`, eight incidences at a time
+// with all their loads in flight (padding repeats the cell itself).
+template <typename T>
+__device__ __forceinline__ void limit_global_cell(const PF<T>& p, const T* __restrict__ U, int e,
+                                                  T* q) {
+  constexpr int kB = 8;
+  T hi[4], lo[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
+  const int i0 = p.lim_inc0[e], i1 = p.lim_inc0[e + 1];
+  for (int b0 = i0; b0 < i1; b0 += kB) {
+    int nb[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) nb[u] = b0 + u < i1 ? p.lim_nbr[b0 + u] : e;
+    T m[kB][4];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) m[u][v] = U[(3 * v) * p.nc + nb[u]];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        hi[v] = fmax(hi[v], m[u][v]);
+        lo[v] = fmin(lo[v], m[u][v]);
+      }
+  }
+  T alpha[4] = {T(1), T(1), T(1), T(1)};
+  for (int b0 = i0; b0 < i1; b0 += kB) {
+    T rx[kB], ry[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int i = b0 + u < i1 ? b0 + u : b0;
+      rx[u] = p.lim_geo[2 * i];
+      ry[u] = p.lim_geo[2 * i + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        alpha[v] = fmin(alpha[v], psi_of(q[3 * v + 1] * rx[u] + q[3 * v + 2] * ry[u], q[3 * v],
+                                         hi[v], lo[v]));
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    q[3 * v + 1] *= alpha[v];
+    q[3 * v + 2] *= alpha[v];
+  }
+}
+
+// One stage (MODE kRhs, kStage1, kStage2) of a block of cells; LIM: limit on
+// read (Pi of `in`, and in stage 2 Pi of `ua` for the combination).
+template <typename T, int MODE, bool LIM>
+__global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
+  __shared__ T cU[12][kLocal];  // coefficients of the block's and the halo's cells
+  __shared__ T sF[10][kHalf];   // per slot: w (F0 + F1), w (F1 - F0)/2, A n
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int c0 = p.blk_cell0[b], nown = p.blk_cell0[b + 1] - c0;
+  const int h0 = p.blk_halo0[b], nhalo = p.blk_halo0[b + 1] - h0;
+  const int s0 = p.blk_slot0[b], nslot = p.blk_slot0[b + 1] - s0;
+  const int nc = p.nc;
+  bool bad = false;
+  // 0. raw coefficients of the block's cells and its halo
+  for (int i = tid; i < nown + nhalo; i += kBlock) {
+    const int g = i < nown ? c0 + i : p.halo_cell[h0 + i - nown];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) cU[k][i] = p.in[k * nc + g];
+  }
+  __syncthreads();
+  // 1. limit on read (the limiter reads only means; only gradients change)
+  const int e = c0 + tid;
+  T q[12];
+  int i0 = 0, i1 = 0;
+  if (tid < nown) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = cU[k][tid];
+    i0 = p.cell_inc0[e];
+    i1 = p.cell_inc0[e + 1];
+  }
+  if (LIM) {
+    T qh[12];
+    if (tid < nhalo) {
+      const int g = p.halo_cell[h0 + tid];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) qh[k] = cU[k][nown + tid];
+      limit_global_cell(p, p.in, g, qh);
+    }
+    if (tid < nown) {
+      limit_block_cell(p, i0, i1, tid, cU, q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cU[3 * v + 1][tid] = q[3 * v + 1];
+        cU[3 * v + 2][tid] = q[3 * v + 2];
+      }
+      // stage 1 hands Pi(U^n) of its cells to stage 2's combination
+      if (MODE == kStage1 && p.lim_out) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p.lim_out[k * nc + e] = q[k];
       }
     }
+    if (tid < nhalo) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cU[3 * v + 1][nown + tid] = qh[3 * v + 1];
+        cU[3 * v + 2][nown + tid] = qh[3 * v + 2];
+      }
+    }
+    __syncthreads();
+  }
+  // 2-3. slot fluxes into LDS, half the slots at a time; each cell gathers its
+  // incidences of the half (they are sorted by slot)
+  T rm[4] = {T(0), T(0), T(0), T(0)};
+  T rx[4] = {T(0), T(0), T(0), T(0)};
+  T ry[4] = {T(0), T(0), T(0), T(0)};
+  const T is3 = T(0.57735026918962576451);  // 1/sqrt(3)
+  int ii = i0;
+  for (int sa = 0; sa < nslot; sa += kHalf) {
+    const int sb = min(nslot, sa + kHalf);
+    for (int sl = sa + tid; sl < sb; sl += kBlock) {
+      const int lr = p.slot_lr[s0 + sl];
+      const int L = lr & 0xffff, R = lr >> 16;
+      const T* g = p.slot_geo + 8 * (size_t)(s0 + sl);
+      const T nx = g[0], ny = g[1], A = g[2], fx = g[3], fy = g[4], dx = g[5], dy = g[6];
+      // Gauss points x_f -+ A/(2 sqrt 3) t, t = (-n_y, n_x), from L's centroid
+      const T o = T(0.5) * A * is3;
+      const T tx = -ny * o, ty = nx * o;
+      T uL[4], uR[4], F0[4], F1[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T gLx = cU[3 * v + 1][L], gLy = cU[3 * v + 2][L];
+        const T gRx = cU[3 * v + 1][R], gRy = cU[3 * v + 2][R];
+        uL[v] = cU[3 * v][L] + gLx * (fx - tx) + gLy * (fy - ty);
+        uR[v] = cU[3 * v][R] + gRx * (fx - tx - dx) + gRy * (fy - ty - dy);
+      }
+      hll_n(uL, uR, nx, ny, p.gamma, F0, bad);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T gLx = cU[3 * v + 1][L], gLy = cU[3 * v + 2][L];
+        const T gRx = cU[3 * v + 1][R], gRy = cU[3 * v + 2][R];
+        uL[v] = cU[3 * v][L] + gLx * (fx + tx) + gLy * (fy + ty);
+        uR[v] = cU[3 * v][R] + gRx * (fx + tx - dx) + gRy * (fy + ty - dy);
+      }
+      hll_n(uL, uR, nx, ny, p.gamma, F1, bad);
+      const T w = T(0.5) * A;
+      const int ls = sl - sa;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sF[v][ls] = w * (F0[v] + F1[v]);
+        sF[4 + v][ls] = T(0.5) * w * (F1[v] - F0[v]);
+      }
+      sF[8][ls] = A * nx;
+      sF[9][ls] = A * ny;
+    }
+    __syncthreads();
+    if (tid < nown) {
+      // side 0 (L) takes -flux, side 1 (R) +flux; the Gauss-point offsets
+      // from the cell's centroid are r_f -+ delta/2, delta = (A/sqrt3) t.
+      // The half's incidences (sorted by slot) kInc at a time, loads first;
+      // the first incidence of a later half ends the pass.
+      bool stop = false;
+      while (!stop && ii < i1) {
+        int inc[kInc];
+        T fx[kInc], fy[kInc];
+#pragma unroll
+        for (int u = 0; u < kInc; ++u) {
+          const int i = ii + u < i1 ? ii + u : ii;
+          inc[u] = p.cell_inc[i];
+          fx[u] = p.inc_rf[2 * (size_t)i];
+          fy[u] = p.inc_rf[2 * (size_t)i + 1];
+        }
+        int done = 0;
+#pragma unroll
+        for (int u = 0; u < kInc; ++u) {
+          const int ls = ((inc[u] & 0xffff) >> 1) - sa;
+          if (stop || ii + u >= i1 || ls >= kHalf) {
+            stop = true;
+            continue;
+          }
+          const T sg = (inc[u] & 1) ? T(1) : T(-1);
+          const T Anx = sF[8][ls], Any = sF[9][ls];
+          const T ddx = -Any * is3, ddy = Anx * is3;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T G = sg * sF[v][ls], K = sg * sF[4 + v][ls];
+            rm[v] += G;
+            rx[v] += fma(G, fx[u], K * ddx);
+            ry[v] += fma(G, fy[u], K * ddy);
+          }
+          ++done;
+        }
+        ii += done;
+      }
+    }
+    if (sb < nslot) __syncthreads();  // the next half overwrites the table
+  }
+  // 4. volume term, M^-1, RK combination
+  double dtmin = 1e300;
+  if (tid < nown) {
     const T* cg = p.cell_geo + 8 * (size_t)e;
     const T iV = cg[0];
     const T m00 = cg[1], m01 = cg[2], m11 = cg[3];
     // volume term: 4 principal-axis points, weights V/4 (the 1/V of the
-    // inverse mass matrix is folded in: rx, ry are per unit volume below)
+    // inverse mass matrix is folded in)
     T vx[4] = {T(0), T(0), T(0), T(0)}, vy[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -271,8 +482,6 @@ __global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
     T d[12];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // surface terms carry V implicitly through the face lengths; the volume
-      // sums need the factor V/4
       const T gx = rx[v] * iV + T(0.25) * vx[v];
       const T gy = ry[v] * iV + T(0.25) * vy[v];
       d[3 * v] = rm[v] * iV;
@@ -288,6 +497,8 @@ __global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) o[k] = fma(dt, d[k], q[k]);
       if (MODE == kStage2) {
+        // ua: Pi(U^n) (written by stage 1 of the same U^n, or by the
+        // stand-alone limiter), U^n itself without a limiter
         T a[12];
         load12(p.ua, nc, e, a);
 #pragma unroll
@@ -311,9 +522,9 @@ __global__ __launch_bounds__(kBlock) void k_fl_rhs(PF<T> p) {
   if (MODE == kStage2 && p.dtpart) {
     dtmin = wave_min(dtmin);
     __shared__ double sd[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) sd[threadIdx.x >> 6] = dtmin;
+    if ((tid & 63) == 0) sd[tid >> 6] = dtmin;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double m = sd[0];
       for (int w = 1; w < kBlock / 64; ++w) m = fmin(m, sd[w]);
       p.dtpart[b] = m;
@@ -348,6 +559,7 @@ PF<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.in = static_cast<const T*>(in);
   p.ua = static_cast<const T*>(ua);
   p.out = static_cast<T*>(out);
+  p.lim_out = nullptr;
   p.dt_dev = dt_dev;
   p.dt_host = dt_host;
   p.status = m->status;
@@ -357,11 +569,13 @@ PF<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.gamma = (T)m->cfg.gamma;
   p.blk_cell0 = f.blk_cell0;
   p.blk_slot0 = f.blk_slot0;
-  p.slot_cells = f.slot_cells;
+  p.blk_halo0 = f.blk_halo0;
+  p.halo_cell = f.halo_cell;
+  p.slot_lr = f.slot_lr;
   p.slot_geo = static_cast<const T*>(f.slot_geo);
   p.cell_inc0 = f.cell_inc0;
   p.cell_inc = f.cell_inc;
-  p.inc_geo = static_cast<const T*>(f.inc_geo);
+  p.inc_rf = static_cast<const T*>(f.inc_rf);
   p.cell_geo = static_cast<const T*>(f.cell_geo);
   p.lim_inc0 = f.lim_inc0;
   p.lim_nbr = f.lim_nbr;
@@ -379,20 +593,29 @@ hipError_t lim_t(const dg_mesh* m, const void* in, void* out, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t rhs_t(const dg_mesh* m, int mode, const void* in, const void* ua, void* out,
-                 const double* dt_dev, double dt_host, bool want_dt, hipStream_t s) {
+hipError_t step_t(const dg_mesh* m, int mode, const void* in, const void* ua, void* out,
+                  void* lim_out, const double* dt_dev, double dt_host, bool want_dt,
+                  hipStream_t s) {
   PF<T> p = make_params<T>(m, in, ua, out, dt_dev, dt_host);
+  p.lim_out = static_cast<T*>(lim_out);
   if (want_dt) p.dtpart = m->dtpart;
   const dim3 g(m->fld->nblocks), b(kBlock);
+  const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
   switch (mode) {
     case kRhs:
-      hipLaunchKernelGGL((k_fl_rhs<T, kRhs>), g, b, 0, s, p);
+      hipLaunchKernelGGL((k_fl_step<T, kRhs, false>), g, b, 0, s, p);
       break;
     case kStage1:
-      hipLaunchKernelGGL((k_fl_rhs<T, kStage1>), g, b, 0, s, p);
+      if (lim)
+        hipLaunchKernelGGL((k_fl_step<T, kStage1, true>), g, b, 0, s, p);
+      else
+        hipLaunchKernelGGL((k_fl_step<T, kStage1, false>), g, b, 0, s, p);
       break;
     case kStage2:
-      hipLaunchKernelGGL((k_fl_rhs<T, kStage2>), g, b, 0, s, p);
+      if (lim)
+        hipLaunchKernelGGL((k_fl_step<T, kStage2, true>), g, b, 0, s, p);
+      else
+        hipLaunchKernelGGL((k_fl_step<T, kStage2, false>), g, b, 0, s, p);
       break;
     default:
       return hipErrorInvalidValue;
@@ -573,24 +796,31 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
     }
   }
   // blocks of up to kBlock consecutive cells; a block is halved until its
-  // distinct incident faces fit the LDS flux table
-  std::vector<int> blk_cell0{0}, blk_slot0{0}, slot_cells, cell_inc0(nc + 1, 0), cell_inc;
-  std::vector<double> sgeo, igeo;
+  // distinct incident faces fit the slot table and its outside neighbours the
+  // halo table
+  std::vector<int> blk_cell0{0};
   {
-    std::vector<int64_t> mark(nf, -1);
+    std::vector<int64_t> fmark(nf, -1), cmark(nc, -1);
     int64_t stamp = 0, e = 0;
     while (e < nc) {
       int64_t e1 = std::min<int64_t>(e + kBlock, nc);
       for (;;) {
         ++stamp;
-        int ns = 0;
+        int ns = 0, nh = 0;
         for (int64_t c = e; c < e1; ++c)
-          for (int i = inc0[c]; i < inc0[c + 1]; ++i)
-            if (mark[cface[i]] != stamp) {
-              mark[cface[i]] = stamp;
+          for (int i = inc0[c]; i < inc0[c + 1]; ++i) {
+            const int f = cface[i];
+            if (fmark[f] != stamp) {
+              fmark[f] = stamp;
               ++ns;
             }
-        if (ns <= kMaxSlots || e1 - e <= 1) break;
+            const int o = cside[i] ? d->face_cells[2 * f] : d->face_cells[2 * f + 1];
+            if ((o < e || o >= e1) && cmark[o] != stamp) {
+              cmark[o] = stamp;
+              ++nh;
+            }
+          }
+        if ((ns <= kMaxSlots && nh <= kMaxHalo) || e1 - e <= 1) break;
         e1 = e + (e1 - e) / 2;
       }
       blk_cell0.push_back((int)e1);
@@ -598,65 +828,72 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
     }
   }
   const int nblocks = (int)blk_cell0.size() - 1;
-  std::vector<int> slot_of_face(nf, -1);
+  std::vector<int> blk_slot0{0}, blk_halo0{0}, halo_cell, slot_lr, cell_inc0(nc + 1, 0), cell_inc;
+  std::vector<double> sgeo, irf;
+  std::vector<int> slot_of_face(nf, -1), local_of(nc, -1);
   int max_slots = 0;
   for (int b = 0; b < nblocks; ++b) {
-    const int ca = blk_cell0[b], cb = blk_cell0[b + 1];
-    const int first = (int)slot_cells.size() / 2;
+    const int ca = blk_cell0[b], cb = blk_cell0[b + 1], nown = cb - ca;
+    // block-local indices: own cells first, then the halo in first-seen order
+    std::vector<int> halo;
+    for (int c = ca; c < cb; ++c) local_of[c] = c - ca;
+    for (int c = ca; c < cb; ++c)
+      for (int i = inc0[c]; i < inc0[c + 1]; ++i) {
+        const int f = cface[i];
+        const int o = cside[i] ? d->face_cells[2 * f] : d->face_cells[2 * f + 1];
+        if (local_of[o] < 0) {
+          local_of[o] = nown + (int)halo.size();
+          halo.push_back(o);
+        }
+      }
+    if ((int)halo.size() > kMaxHalo) {
+      set_error("dg_mesh_create: a cell block has too many outside neighbours");
+      return DG_EINVAL;
+    }
+    // slots in first-seen order; each cell's incidences sorted by slot
     std::vector<int> touched;
+    int ns = 0;
     for (int c = ca; c < cb; ++c) {
+      std::vector<std::pair<int, int>> mine;  // (slot, incidence index in the global CSR)
       for (int i = inc0[c]; i < inc0[c + 1]; ++i) {
         const int f = cface[i];
         if (slot_of_face[f] < 0) {
-          slot_of_face[f] = (int)slot_cells.size() / 2 - first;
+          slot_of_face[f] = ns++;
           touched.push_back(f);
           const int L = d->face_cells[2 * f], R = d->face_cells[2 * f + 1];
-          slot_cells.push_back(L);
-          slot_cells.push_back(R);
+          slot_lr.push_back(local_of[L] | (local_of[R] << 16));
           double rc[2], dLR[2];
           offsets(f, rc, dLR);
-          const double A = d->face_area[f], nx = d->face_normal[2 * f],
-                       ny = d->face_normal[2 * f + 1];
-          const double o = A / (2.0 * std::sqrt(3.0));
-          const double t[2] = {-ny, nx};
-          const double rL0[2] = {rc[0] - o * t[0], rc[1] - o * t[1]};
-          const double rL1[2] = {rc[0] + o * t[0], rc[1] + o * t[1]};
-          const double g[10] = {nx, ny, 0.5 * A, rL0[0], rL0[1], rL1[0], rL1[1],
-                                rL0[0] - dLR[0], rL0[1] - dLR[1], 0.0};
-          sgeo.insert(sgeo.end(), g, g + 10);
+          const double g[8] = {d->face_normal[2 * f], d->face_normal[2 * f + 1], d->face_area[f],
+                               rc[0], rc[1], dLR[0], dLR[1], 0.0};
+          sgeo.insert(sgeo.end(), g, g + 8);
         }
-        cell_inc.push_back(slot_of_face[f] * 2 + cside[i]);
-        {
-          // this side's weight and Gauss-point offsets (R: rR1 = rR0 + (rL1 - rL0))
-          double rc[2], dLR[2];
-          offsets(f, rc, dLR);
-          const double A = d->face_area[f], nx = d->face_normal[2 * f],
-                       ny = d->face_normal[2 * f + 1];
-          const double o = A / (2.0 * std::sqrt(3.0));
-          const double t[2] = {-ny, nx};
-          const double rL0[2] = {rc[0] - o * t[0], rc[1] - o * t[1]};
-          const double rL1[2] = {rc[0] + o * t[0], rc[1] + o * t[1]};
-          if (cside[i] == 0) {
-            const double r[5] = {-0.5 * A, rL0[0], rL0[1], rL1[0], rL1[1]};
-            igeo.insert(igeo.end(), r, r + 5);
-          } else {
-            const double rR0[2] = {rL0[0] - dLR[0], rL0[1] - dLR[1]};
-            const double r[5] = {0.5 * A, rR0[0], rR0[1], rR0[0] + (rL1[0] - rL0[0]),
-                                 rR0[1] + (rL1[1] - rL0[1])};
-            igeo.insert(igeo.end(), r, r + 5);
-          }
-        }
+        mine.emplace_back(slot_of_face[f], i);
+      }
+      std::sort(mine.begin(), mine.end());
+      for (const auto& si : mine) {
+        const int i = si.second, f = cface[i];
+        const int o = cside[i] ? d->face_cells[2 * f] : d->face_cells[2 * f + 1];
+        cell_inc.push_back((si.first * 2 + cside[i]) | (local_of[o] << 16));
+        double rc[2], dLR[2];
+        offsets(f, rc, dLR);
+        // face centroid from this side's centroid (R: its image next to L)
+        irf.push_back(cside[i] ? rc[0] - dLR[0] : rc[0]);
+        irf.push_back(cside[i] ? rc[1] - dLR[1] : rc[1]);
       }
       cell_inc0[c + 1] = (int)cell_inc.size();
     }
     for (int f : touched) slot_of_face[f] = -1;
-    const int ns = (int)slot_cells.size() / 2 - first;
+    for (int c = ca; c < cb; ++c) local_of[c] = -1;
+    for (int o : halo) local_of[o] = -1;
     if (ns > kMaxSlots) {
       set_error("dg_mesh_create: a cell block has too many incident faces");
       return DG_EINVAL;
     }
     max_slots = std::max(max_slots, ns);
-    blk_slot0.push_back((int)slot_cells.size() / 2);
+    blk_slot0.push_back(blk_slot0.back() + ns);
+    halo_cell.insert(halo_cell.end(), halo.begin(), halo.end());
+    blk_halo0.push_back((int)halo_cell.size());
   }
   FLDev* fd = new FLDev();
   std::memset(fd, 0, sizeof(FLDev));
@@ -670,7 +907,9 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   const bool f64 = m->cfg.precision == DG_FP64;
   hipError_t err = upload_i(blk_cell0, &fd->blk_cell0);
   if (err == hipSuccess) err = upload_i(blk_slot0, &fd->blk_slot0);
-  if (err == hipSuccess) err = upload_i(slot_cells, &fd->slot_cells);
+  if (err == hipSuccess) err = upload_i(blk_halo0, &fd->blk_halo0);
+  if (err == hipSuccess) err = upload_i(halo_cell, &fd->halo_cell);
+  if (err == hipSuccess) err = upload_i(slot_lr, &fd->slot_lr);
   if (err == hipSuccess) err = upload_i(cell_inc0, &fd->cell_inc0);
   if (err == hipSuccess) err = upload_i(cell_inc, &fd->cell_inc);
   if (err == hipSuccess) err = upload_i(inc0, &fd->lim_inc0);
@@ -679,7 +918,7 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
     return f64 ? upload<double>(h, dst) : upload<float>(h, dst);
   };
   if (err == hipSuccess) err = up(sgeo, &fd->slot_geo);
-  if (err == hipSuccess) err = up(igeo, &fd->inc_geo);
+  if (err == hipSuccess) err = up(irf, &fd->inc_rf);
   if (err == hipSuccess) err = up(cgeo, &fd->cell_geo);
   if (err == hipSuccess) err = up(lgeo, &fd->lim_geo);
   if (err == hipSuccess) err = up(perim, &fd->cell_perim);
@@ -695,11 +934,13 @@ void facelist_destroy(dg_mesh* m) {
   if (!f) return;
   (void)hipFree(f->blk_cell0);
   (void)hipFree(f->blk_slot0);
-  (void)hipFree(f->slot_cells);
+  (void)hipFree(f->blk_halo0);
+  (void)hipFree(f->halo_cell);
+  (void)hipFree(f->slot_lr);
   (void)hipFree(f->slot_geo);
   (void)hipFree(f->cell_inc0);
   (void)hipFree(f->cell_inc);
-  (void)hipFree(f->inc_geo);
+  (void)hipFree(f->inc_rf);
   (void)hipFree(f->cell_geo);
   (void)hipFree(f->lim_inc0);
   (void)hipFree(f->lim_nbr);
@@ -719,36 +960,28 @@ hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const voi
   auto limit = [&](const void* a, void* b) {
     return f64 ? lim_t<double>(m, a, b, s) : lim_t<float>(m, a, b, s);
   };
-  auto rhs = [&](int md, const void* a, const void* ua, void* o, bool want_dt) {
-    return f64 ? rhs_t<double>(m, md, a, ua, o, dt_dev, dt_host, want_dt, s)
-               : rhs_t<float>(m, md, a, ua, o, dt_dev, dt_host, want_dt, s);
+  auto step = [&](int md, const void* ua, void* lim_out, bool want_dt) {
+    return f64 ? step_t<double>(m, md, in, ua, out, lim_out, dt_dev, dt_host, want_dt, s)
+               : step_t<float>(m, md, in, ua, out, lim_out, dt_dev, dt_host, want_dt, s);
   };
   hipError_t e = hipSuccess;
   switch (mode) {
     case kLimit:
       return limit(in, out);
     case kRhs:
-      return rhs(kRhs, in, nullptr, out, false);
-    case kStage1: {
-      const void* a = in;
-      if (lim) {
-        e = limit(in, m->ws_a);
-        a = m->ws_a;
-      }
-      if (e == hipSuccess) e = rhs(kStage1, a, nullptr, out, false);
-      return e;
-    }
+      return step(kRhs, nullptr, nullptr, false);
+    case kStage1:
+      // keeps Pi(U) of every cell in ws_a for the stage 2 of the same U
+      return step(kStage1, nullptr, lim ? m->ws_a : nullptr, false);
     case kStage2: {
       const void* ua = u0;
-      const void* b = in;
       if (lim) {
         if (!(m->ws_a_fresh && m->ws_a_src == u0)) e = limit(u0, m->ws_a);
         ua = m->ws_a;
-        if (e == hipSuccess) e = limit(in, m->ws_b);
-        b = m->ws_b;
       }
-      if (e == hipSuccess) e = rhs(kStage2, b, ua, out, dt_next != nullptr);
-      if (e == hipSuccess && dt_next) e = launch_min_finalize(m->dtpart, m->fld->nblocks, cfl, dt_next, s);
+      if (e == hipSuccess) e = step(kStage2, ua, nullptr, dt_next != nullptr);
+      if (e == hipSuccess && dt_next)
+        e = launch_min_finalize(m->dtpart, m->fld->nblocks, cfl, dt_next, s);
       return e;
     }
     default:

@@ -128,8 +128,37 @@ def _c5_like(torch, precision, sizes, nsteps, k, seed0=2005, limiter=True):
     return s, states, targets
 
 
+def _flips(oracle, N, U0, v, eps, dts):
+    """Branch switches inside U0 +- eps v over the step schedule dts, on one
+    N x N instance, from the oracle's branch record: (kinks, near-ties).
+    Kinks: limiter decisions (alpha = 1 or the face, neighbour and side that
+    set it) and HLL regions (left, fan, right).  Near-ties: which state gives
+    S_L or S_R inside the fan; in smooth flow the two estimates nearly
+    coincide, and the flux's derivative jumps only by a term proportional to
+    the jump between the two face states."""
+    m = oracle.Mesh.cartesian((N, N), *BOX)
+
+    def path(U):
+        codes = []
+        for dt in dts:
+            U, c = oracle.step_branches(m, U, dt, G53, True)
+            codes.append(c)
+        return codes
+
+    base = path(U0)
+    kinks = ties = 0
+    for sgn in (1.0, -1.0):
+        for c0, c1 in zip(base, path(U0 + sgn * eps * v)):
+            kinks += int((c0[:, :, :4] != c1[:, :, :4]).sum())
+            h0, h1 = c0[:, :, 4:], c1[:, :, 4:]
+            region = (h0 & 3) != (h1 & 3)
+            kinks += int(region.sum())
+            ties += int(((h0 != h1) & ~region).sum())
+    return kinks, ties
+
+
 @pytest.mark.parametrize("limiter,tol", [(False, 1e-7), (True, 2e-2)])
-def test_central_difference_fp64(torch_cuda, limiter, tol):
+def test_central_difference_fp64(oracle, torch_cuda, limiter, tol):
     """dL/dU0 along a random direction against a central difference (eps 1e-6)
     of the FP64 loss through the GPU forward, on the recorded step schedule,
     for two instances of the batched recipe (40 steps, k = 20).  Without the
@@ -161,9 +190,77 @@ def test_central_difference_fp64(torch_cuda, limiter, tol):
         Lp = float(loss(s.run(U0 + eps * v, nsteps, dt_hist=dth[:nsteps * s.ninst].clone())[0]))
         Lm = float(loss(s.run(U0 - eps * v, nsteps, dt_hist=dth[:nsteps * s.ninst].clone())[0]))
     fd = (Lp - Lm) / (2 * eps)
+    kinks = ties = 0
+    if limiter:
+        # how many limiter / wave-speed decisions switch branch inside +-eps v
+        vh = v.cpu().numpy().reshape(12, -1)
+        dth_h = dth.cpu().numpy()
+        for i, n in enumerate(sizes):
+            sl = slice(s.offsets[i], s.offsets[i + 1])
+            k, t = _flips(oracle, n[0], states[i], vh[:, sl].reshape(-1), eps,
+                          dth_h[i:nsteps * s.ninst:s.ninst])
+            kinks += k
+            ties += t
     print(f"limiter {limiter}: central difference {fd:.12e} vs adjoint {g:.12e}, "
-          f"rel {abs(fd - g) / abs(g):.3e}")
+          f"rel {abs(fd - g) / abs(g):.3e}; branch switches inside +-eps v over {nsteps} "
+          f"steps: {kinks} kinks, {ties} wave-speed near-ties")
     assert abs(fd - g) <= tol * abs(g)
+
+
+def test_central_difference_limited_branch_free(oracle, torch_cuda):
+    """The limited map at the 1e-6 bar: central differences (eps 1e-6, FP64)
+    along directions on which no limiter decision and no HLL region switches
+    inside +-eps v (the oracle's branch record over the same step schedule)
+    match the adjoint to 1e-6.  Directions are seeded random perturbations of
+    a 6 x 6 patch of cells of the first instance over 4 steps; at least three
+    kink-free ones must be found among 24 seeds."""
+    torch = torch_cuda
+    from paper_1305_5536_amd.rollout import rollout
+    sizes, nsteps, eps = [(64, 64), (96, 96)], 4, 1e-6
+    s, states, targets = _c5_like(torch, "fp64", sizes, nsteps, 2, limiter=True)
+    U0 = s.pack(states)
+    tgt = torch.cat([torch.as_tensor(t) for t in targets]).to(s.device)
+    vol = torch.cat([torch.full((n[0] * n[1],), 1.0 / (n[0] * n[1]), dtype=torch.float64)
+                     for n in sizes]).to(s.device)
+
+    def loss(out):
+        return 0.5 * (vol * (out[:s.ncells] - tgt) ** 2).sum()
+
+    U = U0.clone().requires_grad_(True)
+    out, dth = rollout(s, U, nsteps, k=2)
+    loss(out).backward()
+    grad = U.grad.detach()
+    dts0 = dth.cpu().numpy()[0:nsteps * s.ninst:s.ninst]
+    N = sizes[0][0]
+    U0h = states[0].reshape(12, N, N)
+    passed, tried = [], []
+    for seed in range(4005, 4029):
+        rng = np.random.default_rng(seed)
+        i0, j0 = rng.integers(0, N - 6, 2)
+        vloc = np.zeros((12, N, N))
+        vloc[:, j0:j0 + 6, i0:i0 + 6] = rng.standard_normal((12, 6, 6))
+        vloc *= np.abs(U0h)
+        kinks, ties = _flips(oracle, N, states[0], vloc.reshape(-1), eps, dts0)
+        tried.append((seed, kinks, ties))
+        if kinks:
+            continue
+        vfull = np.zeros((12, s.ncells))
+        vfull[:, :N * N] = vloc.reshape(12, -1)
+        v = s.to_device(vfull.reshape(-1))
+        g = float((grad * v).sum())
+        with torch.no_grad():
+            Lp = float(loss(s.run(U0 + eps * v, nsteps, dt_hist=dth[:nsteps * s.ninst].clone())[0]))
+            Lm = float(loss(s.run(U0 - eps * v, nsteps, dt_hist=dth[:nsteps * s.ninst].clone())[0]))
+        fd = (Lp - Lm) / (2 * eps)
+        rel = abs(fd - g) / abs(g)
+        print(f"seed {seed}: no kinks ({ties} wave-speed near-ties); central difference "
+              f"{fd:.12e} vs adjoint {g:.12e}, rel {rel:.3e}")
+        assert rel <= 1e-6, (seed, rel)
+        passed.append(seed)
+        if len(passed) == 3:
+            break
+    print(f"directions tried (seed, kinks, near-ties): {tried}")
+    assert len(passed) == 3, tried
 
 
 @pytest.mark.parametrize("limiter", [False, True])
