@@ -34,6 +34,17 @@ FP32_VALU_PEAK_TFLOPS = 157.3
 # stage 1 reads U and writes V1 (24 values); stage 2 reads V1 and U and writes
 # U_next (36 values).  Limiter and CFL minima add no algorithmic traffic.
 STAGE_VALUES = {1: 24, 2: 36}
+# The fused step of 2D Euler (both SSP-RK2 stages in one kernel) reads U and
+# writes U_next: 24 values per cell-step.
+STEP_VALUES = 24
+# Algorithmic flops of one 2D Euler cell-step of the fused kernel, counted from
+# the formulation (an FMA is 2, a division or square root 1): per stage, the
+# cell's -x and -y faces (two Gauss points each: states 40, two HLL solves of
+# 72, sums 8: 192 per face), the 2x2 volume rule (42 per point), the limiter
+# (17 per variable), the row update through the inverse mass matrix (68) and
+# the stage's dt update (24): 712; two stages, the convex combination (24)
+# and the CFL bound of the new mean (19).
+EULER2D_FLOPS_PER_CELL_STEP = 2 * 712 + 24 + 19
 # Algorithmic FP64/FP32 flops of one 3D MHD cell-stage (12 HLLD solves at 2x2
 # Gauss points of 3 faces, 8 volume points, accumulation, inverse mass matrix
 # and the RK combination; counted from the kernel's formulation).
@@ -184,6 +195,47 @@ def run_gpu(U0, mesh, physics, gamma, precision, steps, warmup, cfl=0.3, flux=No
     med["repeats_ms_per_step"] = [r["event_s"] / steps * 1e3 for r in regions]
     med["warmup_steps"] = warm
     med["dt_last"] = dt.item()
+    s.close()
+    return med
+
+
+def run_gpu_step(U0, mesh, gamma, precision, steps, warmup, cfl=0.3, limiter=True,
+                 repeats=REPEATS):
+    """SSP-RK2 steps through dg_step_cfl (on 2D Euler one fused kernel for both
+    stages, plus the one-workgroup dt reduction) on the device step size, timed
+    as run_gpu: max(warmup, 10) untimed steps, then ``repeats`` regions of
+    ``steps`` steps with HIP events around every step; the median region."""
+    import torch
+
+    from paper_1305_5536_amd.solver import Solver
+    s = Solver(mesh, physics="euler", precision=precision, limiter=limiter, gamma=gamma)
+    U = s.to_device(U0)
+    Un = s.empty()
+    dt = s.cfl_dt(U, cfl)
+    warm = max(warmup, WARMUP_MIN)
+    for _ in range(warm):
+        s.step(U, dt, out=Un, cfl=cfl, dt_next=dt)
+        U, Un = Un, U
+    s.check()
+    stream = torch.cuda.current_stream()
+    regions = []
+    for _ in range(repeats):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for k in range(steps):
+            s.step(U, dt, out=Un, cfl=cfl, dt_next=dt)
+            ev[k + 1].record(stream)
+            U, Un = Un, U
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tev = ev[0].elapsed_time(ev[-1]) * 1e-3
+        regions.append({"wall_s": wall, "event_s": tev, "step_s": tev / steps})
+    s.check()
+    med = dict(sorted(regions, key=lambda r: r["event_s"])[len(regions) // 2])
+    med["repeats_ms_per_step"] = [r["event_s"] / steps * 1e3 for r in regions]
+    med["warmup_steps"] = warm
     s.close()
     return med
 
@@ -355,45 +407,109 @@ def bench_c2(a):
     log("timing the GPU steps")
     elem = 8 if a.precision == "fp64" else 4
     mesh = cartesian((n, n), (0.0, 0.0), (1.0, 1.0))
+    ncells = n * n
+    copy_gbs = copy_bandwidth()
+    # the two stage kernels (the per-stage path, also what the adjoint's
+    # forward sweeps and other meshes run)
     r = run_gpu(U0, mesh, "euler", 5.0 / 3.0, a.precision, a.steps, a.warmup, flux=a.flux,
                 limiter=limiter)
-    ncells = n * n
-    value = ncells * 2 * a.steps / r["event_s"]
     stage2_bytes = STAGE_VALUES[2] * elem * ncells
-    achieved = stage2_bytes / r["stage2_s"] / 1e9
-    copy_gbs = copy_bandwidth()
-    out = {
-        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": r["warmup_steps"], "ms_per_step": r["event_s"] / a.steps * 1e3,
-        "timing": {"repeats": REPEATS, "reported": "median repeat",
-                   "repeats_ms_per_step": r["repeats_ms_per_step"],
-                   "warmup_requested": a.warmup, "warmup_run": r["warmup_steps"]},
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
-        "config": {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
-                               f"P1 Taylor DG, {flux}, {limname}, SSP-RK2 CFL 0.3",
-                   "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+    st_gbs = stage2_bytes / r["stage2_s"] / 1e9
+    stages = {
+        "ms_per_step": r["event_s"] / a.steps * 1e3,
+        "value": ncells * 2 * a.steps / r["event_s"],
+        "repeats_ms_per_step": r["repeats_ms_per_step"],
+        "stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
+        "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9,
+        "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": st_gbs / HBM_PEAK_GBS,
                      "traffic": (pmc_traffic("k_cart2d_c2_2048.md", "k_cart2d<double, 2, 1, 0>",
                                              "2048x2048", (f"{CSRC}/cart2d.hip", f"{CSRC}/dg_math.h"))
                                  if n == 2048 and a.precision == "fp64" and a.flux == "hll"
                                  and a.limiter == "arepo" else None),
                      "kernel": "k_cart2d stage 2 (+ dt reduction)",
-                     "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"]},
-        # the same achieved rate against a measured 1 GiB device copy (read + write)
-        "copy_reference": {"copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
-        "kernels": {"stage1_avg_ms": r["stage1_s"] * 1e3, "stage2_avg_ms": r["stage2_s"] * 1e3,
-                    "stage1_GBs": STAGE_VALUES[1] * elem * ncells / r["stage1_s"] / 1e9},
-        "wall_s": r["wall_s"],
+                     "bytes_per_launch": stage2_bytes, "avg_launch_s": r["stage2_s"],
+                     "frac_of_copy": st_gbs / copy_gbs},
     }
+    config = {"workload": f"2D Euler shear layer, periodic Cartesian {n}x{n}, gamma 5/3, "
+                          f"P1 Taylor DG, {flux}, {limname}, SSP-RK2 CFL 0.3",
+              "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU"}
+    fused = a.flux == "hll" and a.limiter == "arepo"
+    f = None
+    if fused:
+        # dg_step: both stages in one kernel; the line reports whichever path
+        # (fused step or two stage kernels) ran faster in this run, the other
+        # beside it
+        f = run_gpu_step(U0, mesh, 5.0 / 3.0, a.precision, a.steps, a.warmup)
+        fused = f["event_s"] < r["event_s"]
+    fused_step = None
+    if f is not None:
+        fused_step = {"ms_per_step": f["step_s"] * 1e3, "value": ncells * 2 * a.steps / f["event_s"],
+                      "repeats_ms_per_step": f["repeats_ms_per_step"],
+                      "kernel": "k_cart2d_step (both SSP-RK2 stages) + dt reduction",
+                      "TFLOPs": EULER2D_FLOPS_PER_CELL_STEP * ncells / f["step_s"] / 1e12,
+                      "GBs": STEP_VALUES * elem * ncells / f["step_s"] / 1e9}
+    if fused:
+        flops = EULER2D_FLOPS_PER_CELL_STEP * ncells
+        peak = FP64_VALU_PEAK_TFLOPS if a.precision == "fp64" else FP32_VALU_PEAK_TFLOPS
+        tflops = flops / f["step_s"] / 1e12
+        step_bytes = STEP_VALUES * elem * ncells
+        kern = f"k_cart2d_step<{'double' if a.precision == 'fp64' else 'float'}, 1>"
+        out = {
+            "metric": METRIC, "value": ncells * 2 * a.steps / f["event_s"],
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": f["warmup_steps"],
+            "ms_per_step": f["step_s"] * 1e3,
+            "timing": {"repeats": REPEATS, "reported": "median repeat",
+                       "repeats_ms_per_step": f["repeats_ms_per_step"],
+                       "warmup_requested": a.warmup, "warmup_run": f["warmup_steps"]},
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+            "config": config,
+            # both stages in one pass move 24 values per cell-step, so the step is
+            # bound by its arithmetic: the FP64 VALU roof with the algorithmic flops
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                         "frac": tflops / peak,
+                         "traffic": (pmc_traffic("k_cart2d_step_c2_2048.md", kern, "2048x2048",
+                                                 (f"{CSRC}/cart2d.hip", f"{CSRC}/dg_math.h"))
+                                     if n == 2048 else None),
+                         "kernel": f"{kern} (both SSP-RK2 stages; + dt reduction)",
+                         "flops_per_launch": flops, "avg_launch_s": f["step_s"]},
+            "hbm": {"bytes_per_launch": step_bytes,
+                    "achieved_GBs": step_bytes / f["step_s"] / 1e9,
+                    "frac": step_bytes / f["step_s"] / 1e9 / HBM_PEAK_GBS},
+            "copy_reference": {"copy_GBs": copy_gbs},
+            "two_stage_kernels": stages,
+            "wall_s": f["wall_s"],
+        }
+    else:
+        out = {
+            "metric": METRIC, "value": stages["value"], "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": r["warmup_steps"], "ms_per_step": stages["ms_per_step"],
+            "timing": {"repeats": REPEATS, "reported": "median repeat",
+                       "repeats_ms_per_step": r["repeats_ms_per_step"],
+                       "warmup_requested": a.warmup, "warmup_run": r["warmup_steps"]},
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if a.precision == "fp64" else "f32", "data": "synthetic",
+            "config": config, "roofline": stages.pop("roofline"),
+            "copy_reference": {"copy_GBs": copy_gbs},
+            "kernels": stages, "wall_s": r["wall_s"],
+        }
+        if fused_step:
+            out["fused_step"] = fused_step
     if a.also_fp32 and a.precision == "fp64":
         r32 = run_gpu(U0, mesh, "euler", 5.0 / 3.0, "fp32", a.steps, a.warmup, flux=a.flux,
                       limiter=limiter)
         out["fp32"] = {"value": ncells * 2 * a.steps / r32["event_s"],
-                       "ms_per_step": r32["event_s"] / a.steps * 1e3,
+                       "ms_per_step": r32["event_s"] / a.steps * 1e3, "path": "two stage kernels",
                        "stage2_GBs": STAGE_VALUES[2] * 4 * ncells / r32["stage2_s"] / 1e9,
                        "stage1_GBs": STAGE_VALUES[1] * 4 * ncells / r32["stage1_s"] / 1e9}
+        if f is not None:
+            f32 = run_gpu_step(U0, mesh, 5.0 / 3.0, "fp32", a.steps, a.warmup)
+            if f32["event_s"] < r32["event_s"]:
+                out["fp32"] = {"value": ncells * 2 * a.steps / f32["event_s"],
+                               "ms_per_step": f32["step_s"] * 1e3, "path": "fused step",
+                               "two_stage_ms_per_step": r32["event_s"] / a.steps * 1e3,
+                               "TFLOPs": EULER2D_FLOPS_PER_CELL_STEP * ncells / f32["step_s"] / 1e12}
     if not a.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(U0, n, a.cpu_steps, label="the same shear-layer state",

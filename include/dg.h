@@ -189,7 +189,10 @@ dg_status dg_limit(dg_mesh_t mesh, const void* U, void* U_lim, void* stream);
  *   Ua = Pi(U); V1 = Ua + dt L(Ua); Ub = Pi(V1); U_next = Ua/2 + (Ub + dt L(Ub))/2.
  * U_next is stored unlimited; the next step limits it first.  U_next may
  * equal U (the library then stages the result in its workspace and copies it
- * back: one extra state copy). */
+ * back: one extra state copy).  2D Euler on a Cartesian mesh with HLL and the
+ * limiter off or DG_LIMITER_MINMOD runs both stages in one kernel (V1 never
+ * reaches device memory; the result equals the two-stage sequence below);
+ * other meshes run dg_stage1 and dg_stage2. */
 dg_status dg_step(dg_mesh_t mesh, const void* U, void* U_next, double dt, void* stream);
 
 /* The two stages of dg_step as separate launches:
@@ -214,6 +217,16 @@ dg_status dg_stage2(dg_mesh_t mesh, const void* U, const void* V1, void* U_next,
  * double), so a step can follow dg_cfl_dt without a host synchronisation. */
 dg_status dg_step_devdt(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,
                         void* stream);
+
+/* dg_step_devdt that also writes the CFL step of U_next, when dt_next_dev is
+ * not NULL: *dt_next_dev = cfl * min_e (CFL bound of U_next's cell means), the
+ * formula of dg_cfl_dt, from per-wave minima taken inside the step kernel plus
+ * one single-workgroup reduction (it may equal dt_dev).  A stepping loop with
+ * no host synchronisation: dg_cfl_dt once, then dg_step_cfl per step.
+ * DG_EINVAL for NULL U, U_next or dt_dev, or cfl <= 0 with dt_next_dev;
+ * DG_EUNSUPPORTED on moving meshes (dg_step_mh). */
+dg_status dg_step_cfl(dg_mesh_t mesh, const void* U, void* U_next, const double* dt_dev,
+                      double cfl, double* dt_next_dev, void* stream);
 
 /* One MUSCL-Hancock step, the paper's own integrator (Sec. 2.4):
  *   Ua = Pi(U);  U_next = Ua + dt L_MH(Ua; dt/2),
@@ -267,7 +280,8 @@ dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double 
 #define DG_RUN_GRAPH 1
 #define DG_RUN_MUSCL_HANCOCK 2
 
-/* nsteps SSP-RK2 steps (the dg_stage1/dg_stage2 pair of each step) from U_in
+/* nsteps SSP-RK2 steps (dg_step's kernels: the fused step, or the
+ * dg_stage1/dg_stage2 pair when v1_keep asks for the stage-1 outputs) from U_in
  * to U_out, with per-step (per-instance) step sizes in the device array
  * dt_hist, nd = dg_ninst doubles per step:
  *   cfl > 0: adaptive.  dt_hist[0..nd) = the CFL step of U_in (dg_cfl_dt) and

@@ -75,6 +75,9 @@ SYMBOLS = [
                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     ("dg_step_devdt", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    ("dg_step_cfl", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
     ("dg_adjoint_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),

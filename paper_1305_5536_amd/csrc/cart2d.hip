@@ -619,6 +619,187 @@ void k_cart2d_w2(P2<T> p) {
   cart2d_tile<T, MODE, LIM, RS>(p, wave, lane);
 }
 
+// ------------------------------------------------------------- fused step --
+// Both SSP-RK2 stages of a step (Sec. 2.2 with the limiter of Sec. 2.5 at the
+// start of each stage) in one pass.  A wave marches the rows of its strip
+// twice over, the second march trailing the first: the stage-1 march turns
+// the U^n window into V1 = Pi(U) + dt L(Pi(U)) one row at a time, and each V1
+// row goes straight (in registers) into the window of the stage-2 march, which
+// finalises U^{n+1} = (Pi(U) + Pi(V1) + dt L(Pi(V1)))/2 two rows behind.  The
+// limited U^n rows wait for that combination in a per-wave LDS ring of three
+// rows.  HBM traffic per step is one read of U^n and one write of U^{n+1} (24
+// values per cell instead of 60 for the two stage launches); the price is a
+// halo of two lanes on each side per stage (56 output columns per 64-lane
+// wave) and four extra stage-1 rows per strip.  Results equal the two stage
+// launches: the same row arithmetic, in the same order.
+
+// Time derivative (Sec. 2.2) of the row a wave finalises, from the row's
+// limited polynomial ev: its -x face (left neighbour by lane exchange) and +x
+// face (the -x face of lane+1), the volume term, and the sums and differences
+// of the fluxes at the Gauss points of the y-face below (ySm, yDm) and above
+// (Sy, Dy), through the folded inverse mass matrix.  The row update of
+// cart2d_tile, written out again so the tuned stage kernels keep their code.
+template <typename T>
+__device__ __forceinline__ void row_rates(const Cell<T>& ev, const T* ySm, const T* yDm,
+                                          const T* Sy, const T* Dy, const P2<T>& p, bool& bad,
+                                          Cell<T>& d) {
+  Cell<T> left;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    left.m[v] = lane_up(ev.m[v]);
+    left.gx[v] = lane_up(ev.gx[v]);
+    left.gy[v] = lane_up(ev.gy[v]);
+  }
+  T Sm[4], Dm[4], sx[4], sy[4];
+  xface<T>(left, ev, p, Sm, Dm, bad);
+  volume<T>(ev, p, sx, sy, bad);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    T Sp = lane_down(Sm[v]);
+    T Dp = lane_down(Dm[v]);
+    d.m[v] = (Sm[v] - Sp) * p.cmx + (ySm[v] - Sy[v]) * p.cmy;
+    d.gx[v] = (sx[v] - Sm[v] - Sp) * p.cgx + (yDm[v] - Dy[v]) * p.ccr;
+    d.gy[v] = (sy[v] - ySm[v] - Sy[v]) * p.cgy + (Dm[v] - Dp) * p.ccr;
+  }
+}
+
+constexpr int kStepCols = 56;
+constexpr int kStepRing = 3;
+
+template <typename T, int LIM>
+__device__ __forceinline__ void cart2d_step_tile(const P2<T>& p, int wave, int lane,
+                                                 T (*ring)[12][kLanes]) {
+  const int tx = wave % p.tiles_x, ty = wave / p.tiles_x;
+  const int colu = tx * kStepCols + lane - 4;
+  // stage 1 is exact on lanes 2..61 (its limiter needs lane -+1, its faces the
+  // limited lane -+1), stage 2 on lanes 4..59
+  const bool liveA = lane >= 2 && lane < 62;
+  const bool liveB = lane >= 4 && lane < 4 + kStepCols;
+  const bool own = liveB && colu < p.nx;
+  int col = colu % p.nx;
+  if (col < 0) col += p.nx;
+  const int nx = p.nx, ny = p.ny, nc = p.nc;
+  const int y0 = ty * p.rows;
+  const int y1 = min(y0 + p.rows, ny);
+  // stage 2 outputs rows [y0, y1) and reads V1 rows [y0 - 2, y1 + 2), which
+  // stage 1 computes from U^n rows [y0 - 4, y1 + 4)
+  const int a0 = y0 - 2, a1 = y1 + 2;
+  auto wrap = [ny](int r) {
+    r %= ny;
+    return r < 0 ? r + ny : r;
+  };
+  auto next = [ny](int r) { return r + 1 == ny ? 0 : r + 1; };
+  bool badA = false, badB = false;
+  double dtmin = 1e300;
+  const T dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
+
+  // stage-1 window over U^n: prev = row j-1 (limited), cur = row j, nx1 = j+1
+  Cell<T> prev, cur, nx1;
+  load_means(p.in, nc, wrap(a0 - 2) * nx + col, prev.m);
+  int r = wrap(a0 - 1);
+  load_cell(p.in, nc, r * nx + col, cur);
+  r = next(r);
+  load_cell(p.in, nc, r * nx + col, nx1);
+  int r2 = next(r);
+  T ySm[4], yDm[4];
+  // stage-2 window over V1: pB = row f-2 (limited), cB = row f-1, nB = row f
+  Cell<T> pB, cB, nB;
+  T ySmB[4], yDmB[4];
+
+  for (int j = a0 - 1; j <= a1; ++j) {
+    Cell<T> nx2;
+    if (j + 2 <= a1)
+      load_cell(p.in, nc, r2 * nx + col, nx2);
+    else if (j + 2 == a1 + 1)
+      load_means(p.in, nc, r2 * nx + col, nx2.m);
+    r2 = next(r2);
+
+    if (LIM != 0) limit_any<T, 1>(cur, prev.m, nx1.m, p);
+    T Sy[4], Dy[4];
+    if (j >= a0) yface<T>(prev, cur, p, Sy, Dy, badA);
+    if (j >= a0 + 1) {
+      // stage 1 of row f = j - 1
+      const int f = j - 1;
+      Cell<T> o;
+      row_rates<T>(prev, ySm, yDm, Sy, Dy, p, badA, o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        o.m[v] = fma(dt, o.m[v], prev.m[v]);
+        o.gx[v] = fma(dt, o.gx[v], prev.gx[v]);
+        o.gy[v] = fma(dt, o.gy[v], prev.gy[v]);
+      }
+      // stage 2 takes V1 row f
+      pB = cB;
+      cB = nB;
+      nB = o;
+      if (LIM != 0 && f >= y0) limit_any<T, 1>(cB, pB.m, nB.m, p);
+      T SyB[4], DyB[4];
+      if (f - 1 >= y0) yface<T>(pB, cB, p, SyB, DyB, badB);
+      if (f - 2 >= y0) {
+        // finalise row g = f - 2 (held in pB); Pi(U^n) of row g from the ring
+        const int g = f - 2;
+        Cell<T> o2;
+        row_rates<T>(pB, ySmB, yDmB, SyB, DyB, p, badB, o2);
+        const int slot = (g - y0) % kStepRing;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          o2.m[v] = T(0.5) * (ring[slot][3 * v][lane] + fma(dt, o2.m[v], pB.m[v]));
+          o2.gx[v] = T(0.5) * (ring[slot][3 * v + 1][lane] + fma(dt, o2.gx[v], pB.gx[v]));
+          o2.gy[v] = T(0.5) * (ring[slot][3 * v + 2][lane] + fma(dt, o2.gy[v], pB.gy[v]));
+        }
+        if (own) {
+          store_cell(p.out, nc, wrap(g) * nx + col, o2);
+          if (p.dt_next) dtmin = fmin(dtmin, cell_dt(o2.m, p));
+        }
+      }
+      if (f - 1 >= y0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          ySmB[v] = SyB[v];
+          yDmB[v] = DyB[v];
+        }
+      }
+    }
+    // Pi(U^n) of row j for the combination three rows later (its slot held
+    // row j - 3, which stage 2 read above; LDS operations of a wave run in
+    // order)
+    if (j >= y0 && j < y1) {
+      const int slot = (j - y0) % kStepRing;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ring[slot][3 * v][lane] = cur.m[v];
+        ring[slot][3 * v + 1][lane] = cur.gx[v];
+        ring[slot][3 * v + 2][lane] = cur.gy[v];
+      }
+    }
+    if (j >= a0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ySm[v] = Sy[v];
+        yDm[v] = Dy[v];
+      }
+    }
+    prev = cur;
+    cur = nx1;
+    nx1 = nx2;
+  }
+  if ((badA && liveA) || (badB && liveB)) atomicOr(p.status, 1);
+  if (p.dt_next) {
+    dtmin = wave_min(dtmin);
+    if (lane == 0) p.dtpart[wave] = dtmin;
+  }
+}
+
+template <typename T, int LIM>
+__global__ __launch_bounds__(256) void k_cart2d_step(P2<T> p) {
+  __shared__ T ring[4][kStepRing][12][kLanes];
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int w = threadIdx.x >> 6;
+  const int wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+  if (wave >= p.ntiles) return;
+  cart2d_step_tile<T, LIM>(p, wave, lane, ring[w]);
+}
+
 // ---------------------------------------------------------------- batches --
 // A batch of independent meshes stored one after another in the same
 // coefficient-major arrays (stride nc = total cells of the batch).  Tile t
@@ -819,7 +1000,7 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
   P2<T> p = make_params<T>(m, in, u0, out, dt_dev, dt_host);
   const int nblocks = (p.ntiles + 3) / 4;
   const int lim = m->cfg.limiter;  // 0 none, 1 Arepo, 2 WENO
-  if (mode == kStage2 || mode == kMH) {
+  if (mode == kStage2 || mode == kMH || mode == kStep) {
     p.dt_next = dt_next;
     p.cfl = cfl;
   }
@@ -848,6 +1029,22 @@ hipError_t launch_t(const dg_mesh* m, int mode, const void* in, const void* u0, 
         hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
                            dt_next);
       break;
+    case kStep: {
+      // HLL and the limiter off or of Sec. 2.5 (the caller checks)
+      if (RS != 0 || lim == 2 || m->cfg.physics != DG_EULER) return hipErrorInvalidValue;
+      p.rows = m->c2.step_rows;
+      p.tiles_x = m->c2.step_tiles_x;
+      p.ntiles = m->c2.step_tiles_x * m->c2.step_tiles_y;
+      const int nb = (p.ntiles + 3) / 4;
+      if (lim == 1)
+        hipLaunchKernelGGL((k_cart2d_step<T, 1>), dim3(nb), dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_cart2d_step<T, 0>), dim3(nb), dim3(256), 0, s, p);
+      if (dt_next)
+        hipLaunchKernelGGL(k_min_finalize, dim3(1), dim3(1024), 0, s, m->dtpart, p.ntiles, cfl,
+                           dt_next);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }

@@ -80,6 +80,16 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
+// Rows per wave of the fused 2D Euler step: about 4096 waves over the mesh,
+// 8 to 64 rows (each wave computes four stage-1 rows beyond its own);
+// DG_STEP_ROWS overrides.
+static int default_step_rows(int64_t ntiles_x, int64_t nrows) {
+  const char* env = std::getenv("DG_STEP_ROWS");
+  int64_t rows = env ? std::atoi(env) : 0;
+  if (rows <= 0) rows = std::max<int64_t>(8, std::min<int64_t>(64, (ntiles_x * nrows + 4095) / 4096));
+  return (int)std::min<int64_t>(rows, nrows);
+}
+
 // Rows per wave of the 2D MHD stage kernel: about 8192 waves over the mesh,
 // 2 to 16 rows (each wave solves one extra y-face row; measured on 512^2 and
 // 2048^2 meshes).
@@ -319,6 +329,9 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
         mhd ? default_rows_mhd2d(m->c2.tiles_x, d->n[1]) : default_rows(m->c2.tiles_x, d->n[1]);
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
+    m->c2.step_tiles_x = (int)((d->n[0] + 55) / 56);  // 56 output columns per wave
+    m->c2.step_rows = default_step_rows(m->c2.step_tiles_x, d->n[1]);
+    m->c2.step_tiles_y = (int)((d->n[1] + m->c2.step_rows - 1) / m->c2.step_rows);
     if (cfg->physics == DG_EULER) {
       // the static scratch of dg_cfl_dt_static on this device (the device
       // that is current here is the mesh's); without its address only that
@@ -418,9 +431,10 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
   // the stand-alone CFL kernel (whole 256-thread blocks write)
-  // (the finest tiling, one row per wave, has at most ncells/60 + rows waves)
+  // (the finest tiling, one row per wave, has at most ncells/60 + rows waves;
+  // ncells/56 + rows for the fused 2D step)
   if (m->kind == 0)
-    nwaves = std::max<int64_t>(nwaves, (m->ncells + 59) / 60 +
+    nwaves = std::max<int64_t>(nwaves, (m->ncells + 55) / 56 +
                                            (m->dim == 2 ? m->c2.ny : m->c3.ny * m->c3.nz));
   m->ndtpart = (int)std::max<int64_t>(nwaves, 4 * ((m->ncells + 255) / 256));
   if (e == hipSuccess) e = hipMalloc(&m->dtpart, sizeof(double) * m->ndtpart);
@@ -493,8 +507,18 @@ dg_status dg_limit(dg_mesh_t m, const void* U, void* Ul, void* stream) {
   return dispatch(m, kLimit, U, nullptr, Ul, nullptr, 0.0, (hipStream_t)stream);
 }
 
+// Meshes whose SSP-RK2 step runs as one fused kernel (both stages in one pass
+// over the rows): 2D Euler on a single Cartesian mesh with HLL and the limiter
+// off or that of Sec. 2.5.
+static bool fused_step(const dg_mesh* m) {
+  return m->kind == 0 && m->dim == 2 && m->cfg.physics == DG_EULER &&
+         m->cfg.flux == DG_FLUX_HLL && m->cfg.limiter != DG_LIMITER_WENO;
+}
+
 static dg_status step_impl(dg_mesh_t m, const void* U, void* Un, const double* dt_dev,
-                           double dt_host, hipStream_t s) {
+                           double dt_host, hipStream_t s, double cfl = 0.0,
+                           double* dt_next = nullptr) {
+  m->ws_a_fresh = false;
   void* target = Un;
   if (U == Un) {
     if (!m->tmp) {
@@ -503,13 +527,18 @@ static dg_status step_impl(dg_mesh_t m, const void* U, void* Un, const double* d
     }
     target = m->tmp;
   }
-  dg_status st = dispatch(m, kStage1, U, nullptr, m->v1, dt_dev, dt_host, s);
-  if (st != DG_OK) return st;
-  // a separate limiter pass keeps Pi(U) of stage 1 for the stage-2 combination
-  m->ws_a_fresh = true;
-  m->ws_a_src = U;
-  st = dispatch(m, kStage2, m->v1, U, target, dt_dev, dt_host, s);
-  m->ws_a_fresh = false;
+  dg_status st;
+  if (fused_step(m)) {
+    st = dispatch(m, kStep, U, nullptr, target, dt_dev, dt_host, s, cfl, dt_next);
+  } else {
+    st = dispatch(m, kStage1, U, nullptr, m->v1, dt_dev, dt_host, s);
+    if (st != DG_OK) return st;
+    // a separate limiter pass keeps Pi(U) of stage 1 for the stage-2 combination
+    m->ws_a_fresh = true;
+    m->ws_a_src = U;
+    st = dispatch(m, kStage2, m->v1, U, target, dt_dev, dt_host, s, cfl, dt_next);
+    m->ws_a_fresh = false;
+  }
   if (st != DG_OK) return st;
   if (target != Un) {
     hipError_t e = hipMemcpyAsync(Un, target, (size_t)m->ncoef * m->ncells * m->elem,
@@ -553,6 +582,17 @@ dg_status dg_step_devdt(dg_mesh_t m, const void* U, void* Un, const double* dt_d
                         void* stream) {
   if (!m || !U || !Un || !dt_dev) return einval("dg_step_devdt: NULL argument");
   return step_impl(m, U, Un, dt_dev, 0.0, (hipStream_t)stream);
+}
+
+dg_status dg_step_cfl(dg_mesh_t m, const void* U, void* Un, const double* dt_dev, double cfl,
+                      double* dt_next_dev, void* stream) {
+  if (!m || !U || !Un || !dt_dev) return einval("dg_step_cfl: NULL argument");
+  if (dt_next_dev && !(cfl > 0 && std::isfinite(cfl))) return einval("dg_step_cfl: cfl must be > 0");
+  if (m->kind == 3) {
+    set_error("dg_step_cfl: moving Voronoi meshes step with dg_step_mh");
+    return DG_EUNSUPPORTED;
+  }
+  return step_impl(m, U, Un, dt_dev, 0.0, (hipStream_t)stream, cfl, dt_next_dev);
 }
 
 dg_status dg_cfl_dt(dg_mesh_t m, const void* U, double cfl, double* dt_dev, void* stream) {
@@ -702,6 +742,13 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
         cur = out;
         continue;
       }
+      if (!v1_keep && fused_step(m)) {
+        dg_status st = dispatch(m, kStep, cur, nullptr, out, dtn, 0.0, q, cfl,
+                                cfl > 0 ? dt_hist + (int64_t)(n + 1) * nd : nullptr);
+        if (st != DG_OK) return st;
+        cur = out;
+        continue;
+      }
       dg_status st = dispatch(m, kStage1, cur, nullptr, V1, dtn, 0.0, q);
       if (st != DG_OK) return st;
       m->ws_a_fresh = true;
@@ -817,6 +864,9 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
                                              : default_rows(m->c2.tiles_x, m->c2.ny));
     m->c2.rows_per_tile = r;
     m->c2.tiles_y = (m->c2.ny + r - 1) / r;
+    const int rs = rows ? std::min(rows, m->c2.ny) : default_step_rows(m->c2.step_tiles_x, m->c2.ny);
+    m->c2.step_rows = rs;
+    m->c2.step_tiles_y = (m->c2.ny + rs - 1) / rs;
   } else {
     int r = rows ? std::min(rows, m->c3.nz)
                  : default_rows((int64_t)m->c3.tiles_x * m->c3.tiles_y, m->c3.nz);

@@ -18,7 +18,8 @@ enum StageMode : int {
   kStage1 = 1,  // out = Pi(in) + dt L(Pi(in))
   kStage2 = 2,  // out = Pi(u0)/2 + (Pi(in) + dt L(Pi(in)))/2
   kLimit = 3,   // out = Pi(in)
-  kMH = 4       // out = Pi(in) + dt L_MH(Pi(in); dt/2): one MUSCL-Hancock step
+  kMH = 4,      // out = Pi(in) + dt L_MH(Pi(in); dt/2): one MUSCL-Hancock step
+  kStep = 5     // out = one SSP-RK2 step of in (both stages in one pass)
 };
 
 // Geometry and launch shape of a periodic 2D Cartesian mesh.
@@ -28,6 +29,8 @@ struct Cart2D {
   double lo[2], hi[2];  // the box as given at create
   int rows_per_tile;  // rows marched by one wave
   int tiles_x, tiles_y;
+  // the fused SSP-RK2 step (2D Euler): 56 output columns per wave
+  int step_rows, step_tiles_x, step_tiles_y;
 };
 
 struct Cart3D {

@@ -174,12 +174,21 @@ class Solver:
         C.check(C.lib().dg_limit(self._h, _ptr(U), _ptr(out), _stream()), "dg_limit")
         return out
 
-    def step(self, U: torch.Tensor, dt, out: torch.Tensor | None = None) -> torch.Tensor:
-        """One SSP-RK2 step; ``dt`` is a float or a device float64 tensor of one element."""
+    def step(self, U: torch.Tensor, dt, out: torch.Tensor | None = None, cfl: float = 0.0,
+             dt_next: torch.Tensor | None = None) -> torch.Tensor:
+        """One SSP-RK2 step; ``dt`` is a float or a device float64 tensor of one
+        element; with a device ``dt``, optionally dt_next = CFL step of the result."""
         self._check_state(U)
         out = self.empty() if out is None else out
         self._check_state(out, "out")
-        if isinstance(dt, torch.Tensor):
+        if dt_next is not None:
+            if not isinstance(dt, torch.Tensor):
+                raise ValueError("dt_next needs the step size as a device tensor")
+            self._check_dt(dt)
+            self._check_dt(dt_next)
+            st = C.lib().dg_step_cfl(self._h, _ptr(U), _ptr(out), _ptr(dt), float(cfl),
+                                     _ptr(dt_next), _stream())
+        elif isinstance(dt, torch.Tensor):
             self._check_dt(dt)
             st = C.lib().dg_step_devdt(self._h, _ptr(U), _ptr(out), _ptr(dt), _stream())
         else:

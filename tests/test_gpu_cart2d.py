@@ -225,8 +225,9 @@ def test_bad_arguments_are_rejected(torch_cuda):
 
 
 def test_stages_with_device_dt_and_fused_cfl(oracle, torch_cuda):
-    """dg_stage1 + dg_stage2 equal dg_step; the fused CFL minimum of stage 2
-    equals dg_cfl_dt of the new state (and the oracle's)."""
+    """dg_stage1 + dg_stage2 equal dg_step (the fused step kernel) to rounding;
+    the fused CFL minimum of stage 2 equals dg_cfl_dt of the new state (and the
+    oracle's)."""
     n, lo, hi = (150, 90), (0.0, 0.0), (1.0, 1.0)
     U0 = W.random_p1_state(n, lo, hi, G53, seed=13, amp=0.3)
     s = _solver(n, lo, hi, G53)
@@ -238,7 +239,7 @@ def test_stages_with_device_dt_and_fused_cfl(oracle, torch_cuda):
     s.stage1(U, dt, V1)
     s.stage2(U, V1, dt, Un, cfl=0.3, dt_next=dt_next)
     ref = s.step(U, dt.item())
-    assert torch_cuda.equal(Un, ref)
+    assert field_errors(Un.cpu().numpy(), ref.cpu().numpy(), n, lo, hi).max() < 1e-14
     assert dt_next.item() == s.cfl_dt(Un, 0.3).item()
     o = oracle.cfl_dt(oracle.Mesh.cartesian(n, lo, hi), Un.cpu().numpy(), G53, 0.3)
     assert abs(dt_next.item() - o) <= 1e-14 * o
@@ -301,3 +302,103 @@ def test_autotuner_picks_a_candidate(tmp_path, monkeypatch, torch_cuda):
     s.tiling = 0
     r2 = autotune(s, U, n, candidates=(4, 8, 16), reps=3)
     assert r2["rows"] == r["rows"] and s.tiling == r["rows"]
+
+
+FUSED_SHAPES = [(1, 5), (3, 1), (2, 3), (61, 9), (57, 13), (113, 40), (130, 77), (224, 20)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("limiter", [False, True])
+@pytest.mark.parametrize("n", FUSED_SHAPES)
+def test_fused_step_equals_two_stages(torch_cuda, n, limiter, precision):
+    """On 2D Euler dg_step runs both stages in one kernel (stage-1 rows pass to
+    stage 2 in registers; 56 output columns per wave; four extra stage-1 rows
+    per strip).  It equals dg_stage1 + dg_stage2 to rounding (the same
+    arithmetic; the compiler may contract the row update's products into FMAs
+    differently: 1e-14 of the field scale in FP64, 1e-5 in FP32, where the
+    face sums cancel to a few tens of ulps of the field scale), on meshes
+    narrower than a wave, ragged strips and single rows, and dg_step_cfl's CFL
+    step equals stage 2's to the same bound; in place it gives the same bits."""
+    lo, hi = (0.0, 0.0), (1.0, 1.3)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=n[0] * 1000 + n[1], amp=0.3)
+    s = _solver(n, lo, hi, G53, limiter=limiter, precision=precision)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    V1, ref, got = s.empty(), s.empty(), s.empty()
+    f64 = dict(dtype=torch_cuda.float64, device="cuda")
+    d_ref, d_got = torch_cuda.empty(1, **f64), torch_cuda.empty(1, **f64)
+    s.stage1(U, dt, V1)
+    s.stage2(U, V1, dt, ref, cfl=0.3, dt_next=d_ref)
+    s.step(U, dt, out=got, cfl=0.3, dt_next=d_got)
+    s.check()
+    tol = 1e-14 if precision == "fp64" else 1e-5
+    errs = field_errors(got.double().cpu().numpy(), ref.double().cpu().numpy(), n, lo, hi)
+    assert errs.max() < tol, errs
+    assert abs(d_got.item() - d_ref.item()) <= tol * d_ref.item()
+    # in place, with the next step size written over the current one
+    s.step(U, dt, out=U, cfl=0.3, dt_next=dt)
+    assert torch_cuda.equal(U, got) and dt.item() == d_got.item()
+
+
+def test_fused_step_matches_oracle_over_strips_and_rows(oracle, torch_cuda):
+    """A mesh of several 56-column strips with a ragged last strip and rows per
+    wave that leave a short last tile: 20 fused steps against the oracle."""
+    n, lo, hi = (150, 47), (0.0, 0.0), (1.5, 0.47)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=31, amp=0.3)
+    om = oracle.Mesh.cartesian(n, lo, hi)
+    ref, dts = oracle.run(om, U0, 20, G53, 0.3, True)
+    s = _solver(n, lo, hi, G53, limiter=True)
+    s.tiling = 10
+    U = s.to_device(U0)
+    dt = torch_cuda.tensor([dts[0]], dtype=torch_cuda.float64, device="cuda")
+    V = s.empty()
+    for k in range(20):
+        # the kernel's own CFL step drives the run; it must agree with the oracle's
+        assert abs(dt.item() - dts[k]) <= 1e-13 * dts[k]
+        dt.fill_(dts[k])
+        s.step(U, dt, out=V, cfl=0.3, dt_next=dt)
+        U, V = V, U
+    s.check()
+    errs = field_errors(U.cpu().numpy(), ref, n, lo, hi)
+    assert errs.max() < 1e-12, errs
+
+
+def test_fused_step_reports_nonphysical_state(torch_cuda):
+    from paper_1305_5536_amd.capi import NonPhysicalState
+    n, lo, hi = (70, 20), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G14, seed=2, amp=0.1).reshape(12, -1)
+    s = _solver(n, lo, hi, G14, limiter=False)
+    s.step(s.to_device(U0.reshape(-1)), 1e-4)
+    s.check()  # a physical state raises nothing (halo lanes are masked)
+    U0[9, 12 * 70 + 69] = -1.0  # negative energy in the last column of row 12
+    s.step(s.to_device(U0.reshape(-1)), 1e-4)
+    with pytest.raises(NonPhysicalState):
+        s.check()
+
+
+def test_run_uses_the_fused_step(torch_cuda):
+    """dg_run on a 2D Euler mesh steps with the fused kernel (graph-captured,
+    replayed twice) and equals dg_step_cfl one call at a time bit for bit, and
+    the two-stage path that keeps the stage-1 outputs to rounding."""
+    n, lo, hi = (90, 40), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=33, amp=0.3)
+    s = _solver(n, lo, hi, G53)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    A, B = U.clone(), s.empty()
+    for _ in range(6):
+        s.step(A, dt, out=B, cfl=0.3, dt_next=dt)
+        A, B = B, A
+    v1 = [s.empty() for _ in range(6)]
+    two, hist2 = s.run(U, 6, cfl=0.3, v1_keep=v1, graph=False)
+    out = s.empty()
+    hist = torch_cuda.empty(7, dtype=torch_cuda.float64, device="cuda")
+    for rep in range(3):  # capture, then two replays of the cached graph
+        out.zero_()
+        s.run(U, 6, cfl=0.3, out=out, dt_hist=hist, graph=True)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(out, A), rep
+        assert hist[6].item() == dt.item(), rep
+        assert field_errors(out.cpu().numpy(), two.cpu().numpy(), n, lo, hi).max() < 1e-13
+        assert torch_cuda.allclose(hist, hist2, rtol=1e-13, atol=0)
+    s.check()

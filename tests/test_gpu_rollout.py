@@ -96,6 +96,10 @@ def test_checkpoint_interval_and_graph_do_not_change_gradient(torch_cuda):
 
 
 def test_batched_gradient_equals_single_instances(torch_cuda):
+    """A batch's rollout and gradient equal each instance's own.  The single
+    mesh's forward steps run the fused step kernel, the batch's its stage
+    kernels: the same arithmetic, equal to rounding (step sizes and states to
+    1e-13, gradients to 1e-12)."""
     torch = torch_cuda
     from paper_1305_5536_amd.rollout import rollout
     from paper_1305_5536_amd.solver import Solver, batch, cartesian
@@ -112,12 +116,14 @@ def test_batched_gradient_equals_single_instances(torch_cuda):
         s = Solver(cartesian(n, *BOX), gamma=G53)
         u = s.to_device(states[i]).requires_grad_(True)
         o, d = rollout(s, u, 21, k=10)
-        assert torch.equal(d, dth[i::len(sizes)])
-        assert np.array_equal(o.detach().cpu().numpy(), outs[i])
+        assert torch.allclose(d, dth[i::len(sizes)], rtol=1e-13, atol=0)
+        ob = outs[i]
+        assert np.abs(o.detach().cpu().numpy() - ob).max() <= 1e-13 * np.abs(ob).max()
         wi = s.to_device(np.concatenate([wb.cpu().numpy().reshape(12, -1)[
             :, sb.offsets[i]:sb.offsets[i + 1]]], axis=1))
         (o * wi).sum().backward()
-        assert np.array_equal(u.grad.cpu().numpy(), gb[i]), n
+        g = u.grad.cpu().numpy()
+        assert np.abs(g - gb[i]).max() <= 1e-12 * np.abs(gb[i]).max(), n
 
 
 def _c5_like(torch, precision, sizes, nsteps, k, seed0=2005, limiter=True):
