@@ -80,13 +80,34 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
-// Rows per wave of the fused 2D Euler step: about 4096 waves over the mesh,
-// 8 to 64 rows (each wave computes four stage-1 rows beyond its own);
-// DG_STEP_ROWS overrides.
-static int default_step_rows(int64_t ntiles_x, int64_t nrows) {
+// Rows per wave of the fused 2D Euler step (DG_STEP_ROWS overrides).  A wave
+// of R rows costs about R + 1.85 stage-2 row times (its four extra stage-1
+// rows are a little cheaper than stage-2 rows), and the waves run in rounds of
+// one per SIMD (FP64: one wave per SIMD by registers; FP32: two), so R in
+// [8, 64] minimises rounds x (R + 1.85): the last round should be nearly full.
+static int default_step_rows(int64_t ntiles_x, int64_t nrows, bool f64) {
   const char* env = std::getenv("DG_STEP_ROWS");
   int64_t rows = env ? std::atoi(env) : 0;
-  if (rows <= 0) rows = std::max<int64_t>(8, std::min<int64_t>(64, (ntiles_x * nrows + 4095) / 4096));
+  if (rows <= 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+      (void)hipGetLastError();
+      cus = 256;
+    }
+    const int64_t slots = (int64_t)cus * 4 * (f64 ? 1 : 2);
+    double best = 1e300;
+    for (int64_t r = 8; r <= 64; ++r) {
+      const int64_t rr = std::min(r, nrows);
+      const int64_t waves = ntiles_x * ((nrows + rr - 1) / rr);
+      const double cost = (double)((waves + slots - 1) / slots) * ((double)rr + 1.85);
+      if (cost < best - 1e-9) {
+        best = cost;
+        rows = rr;
+      }
+    }
+  }
   return (int)std::min<int64_t>(rows, nrows);
 }
 
@@ -330,7 +351,8 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
     m->c2.step_tiles_x = (int)((d->n[0] + 55) / 56);  // 56 output columns per wave
-    m->c2.step_rows = default_step_rows(m->c2.step_tiles_x, d->n[1]);
+    m->c2.step_rows =
+        default_step_rows(m->c2.step_tiles_x, d->n[1], cfg->precision == DG_FP64);
     m->c2.step_tiles_y = (int)((d->n[1] + m->c2.step_rows - 1) / m->c2.step_rows);
     if (cfg->physics == DG_EULER) {
       // the static scratch of dg_cfl_dt_static on this device (the device
@@ -864,7 +886,9 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
                                              : default_rows(m->c2.tiles_x, m->c2.ny));
     m->c2.rows_per_tile = r;
     m->c2.tiles_y = (m->c2.ny + r - 1) / r;
-    const int rs = rows ? std::min(rows, m->c2.ny) : default_step_rows(m->c2.step_tiles_x, m->c2.ny);
+    const int rs = rows ? std::min(rows, m->c2.ny)
+                        : default_step_rows(m->c2.step_tiles_x, m->c2.ny,
+                                            m->cfg.precision == DG_FP64);
     m->c2.step_rows = rs;
     m->c2.step_tiles_y = (m->c2.ny + rs - 1) / rs;
   } else {
