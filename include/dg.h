@@ -264,14 +264,18 @@ dg_status dg_step_mh(dg_mesh_t mesh, const void* U, void* U_next, double dt, con
  *   lam_n = (d step(U, dt) / d U)^T lam_np1
  * through both stages, both limiter applications (the branch the forward step
  * takes: alpha = 1, or alpha = D/dm with its arg-max/arg-min neighbour) and
- * the HLL flux (the active wave-speed estimates).  Ties follow the first
+ * the face flux (HLL: the active wave-speed estimates; HLLD: the active region
+ * of the fan).  Ties follow the first
  * argument in the order self, -x, +x, -y, +y.  The step size is *dt_dev (one
  * per instance on a batch) when dt_dev is not NULL, else dt.  V1 is the
  * stage-1 output of the forward step from U (dg_stage1 with the same step
  * size), or NULL to recompute it.  Built for 2D Euler on Cartesian meshes and
- * batches (DG_EUNSUPPORTED otherwise).  lam_n must not alias U, V1 or
- * lam_np1.  Allocates two state-sized workspaces on the first call (kept by
- * the handle). */
+ * batches (HLL; limiter off or DG_LIMITER_MINMOD) and for 2D ideal MHD on
+ * Cartesian meshes (HLLD on the face-averaged normal field, the 23-coefficient
+ * basis of Sec. 2.2; limiter off or DG_LIMITER_MINMOD with one alpha for B,
+ * ties in the same order; dt frozen); DG_EUNSUPPORTED otherwise.  lam_n must
+ * not alias U, V1 or lam_np1.  Allocates two state-sized workspaces on the
+ * first call (kept by the handle). */
 dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double dt,
                           const double* dt_dev, const void* lam_np1, void* lam_n, void* stream);
 

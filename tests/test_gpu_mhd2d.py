@@ -247,5 +247,3 @@ def test_unsupported_entry_points(torch_cuda):
     U = s.to_device(_state((8, 8), seed=1))
     with pytest.raises(DGError):
         s.step_mh(U, 1e-3)
-    with pytest.raises(DGError):
-        s.adjoint_step(U, 1e-3, s.to_device(np.ones(U.numel())))
