@@ -269,8 +269,10 @@ dg_status dg_step_mh(dg_mesh_t mesh, const void* U, void* U_next, double dt, con
  * argument in the order self, -x, +x, -y, +y.  The step size is *dt_dev (one
  * per instance on a batch) when dt_dev is not NULL, else dt.  V1 is the
  * stage-1 output of the forward step from U (dg_stage1 with the same step
- * size), or NULL to recompute it.  Built for 2D Euler on Cartesian meshes and
- * batches (HLL; limiter off or DG_LIMITER_MINMOD) and for 2D ideal MHD on
+ * size), or NULL to recompute it.  Built for 2D Euler on Cartesian meshes,
+ * batches and static face-list meshes (HLL; limiter off or DG_LIMITER_MINMOD;
+ * on a face list the bounds and alpha run over the cell's faces in the mesh's
+ * incidence order) and for 2D ideal MHD on
  * Cartesian meshes (HLLD on the face-averaged normal field, the 23-coefficient
  * basis of Sec. 2.2; limiter off or DG_LIMITER_MINMOD with one alpha for B,
  * ties in the same order; dt frozen); DG_EUNSUPPORTED otherwise.  lam_n must

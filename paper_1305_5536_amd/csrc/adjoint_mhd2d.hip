@@ -33,6 +33,7 @@
 
 #include "dg_internal.h"
 #include "dg_math.h"
+#include "dual.h"
 #include "mhd_hlld.h"
 
 namespace dg {
@@ -42,51 +43,6 @@ hipError_t launch_mhd2d(const dg_mesh* m, int mode, const void* in, const void* 
                         hipStream_t s);
 
 namespace {
-
-// Forward-mode dual number: value and one tangent.  The arithmetic the HLLD
-// solver and the limiter use is defined as hidden friends, so it is found by
-// argument-dependent lookup only and hides nothing of the plain overloads.
-template <typename T>
-struct Dual {
-  T v, d;
-  __device__ __forceinline__ Dual() : v(T(0)), d(T(0)) {}
-  __device__ __forceinline__ Dual(double a) : v(T(a)), d(T(0)) {}
-  __device__ __forceinline__ Dual(T a, T b) : v(a), d(b) {}
-
-  friend __device__ __forceinline__ Dual operator+(Dual a, Dual b) {
-    return Dual(a.v + b.v, a.d + b.d);
-  }
-  friend __device__ __forceinline__ Dual operator-(Dual a, Dual b) {
-    return Dual(a.v - b.v, a.d - b.d);
-  }
-  friend __device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-  friend __device__ __forceinline__ Dual operator*(Dual a, Dual b) {
-    return Dual(a.v * b.v, a.d * b.v + a.v * b.d);
-  }
-  friend __device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
-  friend __device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
-  friend __device__ __forceinline__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
-  friend __device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
-  friend __device__ __forceinline__ Dual fma(Dual a, Dual b, Dual c) {
-    return Dual(fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d);
-  }
-  // min / max return the first argument on ties
-  friend __device__ __forceinline__ Dual fmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
-  friend __device__ __forceinline__ Dual fmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
-  friend __device__ __forceinline__ Dual fabs(Dual a) { return a.v < T(0) ? -a : a; }
-  friend __device__ __forceinline__ Dual rcp(Dual a) {
-    const T r = rcp(a.v);
-    return Dual(r, -a.d * r * r);
-  }
-  friend __device__ __forceinline__ Dual sqrt_pos(Dual a) {
-    const T s = sqrt_pos(a.v);
-    return Dual(s, a.d * T(0.5) * rcp(s));
-  }
-  friend __device__ __forceinline__ Dual div_small(Dual a, Dual b) {
-    const T q = div_small(a.v, b.v);
-    return Dual(q, div_small(a.d - q * b.d, b.v));
-  }
-};
 
 // Coefficient layout of a cell (23 values): 3v, 3v+1, 3v+2 the mean and x, y
 // gradient of rho, mx, my, mz, E (v = 0..4); 15..17 the means of Bx, By, Bz;
@@ -223,21 +179,26 @@ template <typename T, int D>
 __device__ void face_adjoint(const T* ce, const AccBar<T>& ae, const T* cn, const AccBar<T>& an,
                              int side, const PJ<T>& p, T* g) {
   constexpr int t = 1 - D;
-  const T* cL = side == 0 ? ce : cn;
-  const T* cR = side == 0 ? cn : ce;
-  const AccBar<T>& aL = side == 0 ? ae : an;
-  const AccBar<T>& aR = side == 0 ? an : ae;
+  // e's side of the face: normal offset +h_D/2 as L, -h_D/2 as R; the residual
+  // sign sigma -1 as L, +1 as R (values are selected element by element: an
+  // array picked through a pointer would leave the registers)
+  const T he = side == 0 ? p.half[D] : -p.half[D];
+  const T sge = side == 0 ? T(-1) : T(1);
 #pragma unroll 1
   for (int gp = 0; gp < 2; ++gp) {
     const T s = gp ? T(1) : T(-1);
     const T ht = s * p.q[t];
-    T uL[8], uR[8], Fb[8];
-    point_state<T, D>(cL, p.half[D], ht, uL);
-    point_state<T, D>(cR, -p.half[D], ht, uR);
+    T ue[8], un[8], uL[8], uR[8], Fb[8];
+    point_state<T, D>(ce, he, ht, ue);
+    point_state<T, D>(cn, -he, ht, un);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) Fb[k] = T(0);
-    flux_bar<T, D>(aL, s, T(-1), p, Fb);
-    flux_bar<T, D>(aR, s, T(1), p, Fb);
+    for (int k = 0; k < 8; ++k) {
+      uL[k] = side == 0 ? ue[k] : un[k];
+      uR[k] = side == 0 ? un[k] : ue[k];
+      Fb[k] = T(0);
+    }
+    flux_bar<T, D>(ae, s, sge, p, Fb);
+    flux_bar<T, D>(an, s, -sge, p, Fb);
     // the Jacobian of the flux on this cell's side, one direction at a time;
     // the normal field enters through the average of both sides
     T ub[8];
@@ -259,7 +220,7 @@ __device__ void face_adjoint(const T* ce, const AccBar<T>& ae, const T* cn, cons
       for (int j = 0; j < 8; ++j) acc = fma(Fb[j], F[j].d, acc);
       ub[k] = acc;
     }
-    point_state_bar<T, D>(ub, side == 0 ? p.half[D] : -p.half[D], ht, g);
+    point_state_bar<T, D>(ub, he, ht, g);
   }
 }
 

@@ -28,7 +28,9 @@
 //      reduction, no atomics);
 //   4. the volume term, M^-1 and the RK combination (stage 2 limits U^n of its
 //      own cell for the combination from the neighbours' means in HBM).
-// A stand-alone limiter kernel (k_fl_lim) serves dg_limit.
+// A stand-alone limiter kernel (k_fl_lim) serves dg_limit.  The discrete
+// adjoint of a step (k_adjfl_L, k_adjfl_lim) gathers over the global incidence
+// lists, one thread per cell.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +41,7 @@
 
 #include "dg_internal.h"
 #include "dg_math.h"
+#include "dual.h"
 
 namespace dg {
 
@@ -62,6 +65,10 @@ struct FLDev {
   int* lim_nbr;       // neighbour cell of each incidence
   void* lim_geo;      // [ninc][2] face-centroid offsets, then [ninc][2] A n outward
   void* cell_perim;   // [ncells] sum of face lengths
+  // the discrete adjoint (gathers over the global CSR)
+  int* inc_face;      // [ninc] face id << 1 | side (0: the cell is L) of each incidence
+  int* face_lr;       // [nfaces][2] L, R
+  void* face_geo;     // [nfaces][8] nx, ny, A, x_f - c_L (2), c_R' - c_L (2), 0
 };
 
 namespace {
@@ -631,6 +638,305 @@ hipError_t cfl_t(const dg_mesh* m, const void* U, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- discrete adjoint --
+// Adjoint of a stage (as for the Cartesian meshes):
+//   out = Pi_P^T lamW,   lamW = c_id lam + c_L (dL/dW)^T lam + c_extra extra,
+// W = Pi(P), the branch the forward step takes (dt frozen).  k_adjfl_L gathers
+// lamW of a cell over its incidences and its volume points; k_adjfl_lim the
+// limiter transpose.  One thread per cell, no atomics; the flux and limiter
+// Jacobians come from forward-mode dual numbers through hll_n and the
+// limiter arithmetic, the linear parts (Gauss-point extrapolation, the
+// residual weights, M^-1) are transposed by hand.
+template <typename T>
+struct PFA {
+  const T* W;      // Pi(P)
+  const T* P;      // the stage input (k_adjfl_lim)
+  const T* lam;    // adjoint of the stage output (k_adjfl_L)
+  const T* extra;  // added to lamW with weight c_extra (may be NULL)
+  const T* lamW;   // k_adjfl_lim input
+  T* out;
+  const double* dt_dev;
+  double dt_host;
+  double c_id, c_L_over_dt, c_extra;
+  int nc;
+  T gamma;
+  const int* inc0;
+  const int* nbr;
+  const int* inc_face;
+  const int* face_lr;
+  const T* face_geo;
+  const T* lim_geo;
+  const T* cell_geo;
+};
+
+// Cotangents of a cell's residual sums from the adjoint of its time
+// derivative: d mean = rm / V, d grad = (V M^-1) (r / V + vol / 4), with r the
+// face moments sum_g w F_g (x_g - c) and vol the sums of the volume fluxes.
+template <typename T>
+struct Cot {
+  T rm[4], rx[4], ry[4], vx[4], vy[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void cotangents(const T* lam, const T* cg, Cot<T>& c) {
+  const T iV = cg[0], m00 = cg[1], m01 = cg[2], m11 = cg[3];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const T gx = fma(m00, lam[3 * v + 1], m01 * lam[3 * v + 2]);
+    const T gy = fma(m01, lam[3 * v + 1], m11 * lam[3 * v + 2]);
+    c.rm[v] = iV * lam[3 * v];
+    c.rx[v] = iV * gx;
+    c.ry[v] = iV * gy;
+    c.vx[v] = T(0.25) * gx;
+    c.vy[v] = T(0.25) * gy;
+  }
+}
+
+// Both Cartesian Euler fluxes at one state (the volume term's point flux).
+template <typename S>
+__device__ __forceinline__ void euler_xy(const S* u, S gamma, S* Fx, S* Fy) {
+  const S ir = rcp(u[0]);
+  const S ux = u[1] * ir, uy = u[2] * ir;
+  const S pr = (gamma - S(1)) * (u[3] - S(0.5) * (u[1] * ux + u[2] * uy));
+  Fx[0] = u[1];
+  Fx[1] = u[1] * ux + pr;
+  Fx[2] = u[2] * ux;
+  Fx[3] = (u[3] + pr) * ux;
+  Fy[0] = u[2];
+  Fy[1] = u[1] * uy;
+  Fy[2] = u[2] * uy + pr;
+  Fy[3] = (u[3] + pr) * uy;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjfl_L(PFA<T> p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.nc) return;
+  const T is3 = T(0.57735026918962576451);  // 1/sqrt(3)
+  T we[12], le[12], g[12];
+  load12(p.W, p.nc, e, we);
+  load12(p.lam, p.nc, e, le);
+  const T* cge = p.cell_geo + 8 * (size_t)e;
+  Cot<T> ce;
+  cotangents(le, cge, ce);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) g[k] = T(0);
+  const Dual<T> dgam(p.gamma, T(0));
+  for (int i = p.inc0[e]; i < p.inc0[e + 1]; ++i) {
+    const int fs = p.inc_face[i], f = fs >> 1, side = fs & 1;
+    const int nb = side ? p.face_lr[2 * f] : p.face_lr[2 * f + 1];
+    const T* fg = p.face_geo + 8 * (size_t)f;
+    const T nx = fg[0], ny = fg[1], A = fg[2], fx = fg[3], fy = fg[4], dx = fg[5], dy = fg[6];
+    T wn[12], ln[12];
+    load12(p.W, p.nc, nb, wn);
+    load12(p.lam, p.nc, nb, ln);
+    Cot<T> cn;
+    cotangents(ln, p.cell_geo + 8 * (size_t)nb, cn);
+    // Gauss points x_f -+ A/(2 sqrt 3) t, t = (-n_y, n_x); weights A/2; the L
+    // cell takes -w F, the R cell +w F (mean and the moments about its
+    // centroid).  Values of e and nb are selected element by element (an
+    // array picked through a pointer would leave the registers).
+    const T w = T(0.5) * A, o = T(0.5) * A * is3;
+    const T tx = -ny * o, ty = nx * o;
+    const T se = side ? T(1) : T(-1);
+#pragma unroll 1
+    for (int gp = 0; gp < 2; ++gp) {
+      const T sg = gp ? T(1) : T(-1);
+      const T rLx = fma(sg, tx, fx), rLy = fma(sg, ty, fy);
+      const T rRx = rLx - dx, rRy = rLy - dy;
+      const T rex = side ? rRx : rLx, rey = side ? rRy : rLy;
+      const T rnx = side ? rLx : rRx, rny = side ? rLy : rRy;
+      T uL[4], uR[4], Fb[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T ue = we[3 * v] + we[3 * v + 1] * rex + we[3 * v + 2] * rey;
+        const T un = wn[3 * v] + wn[3 * v + 1] * rnx + wn[3 * v + 2] * rny;
+        uL[v] = side ? un : ue;
+        uR[v] = side ? ue : un;
+        Fb[v] = w * se * ((ce.rm[v] + ce.rx[v] * rex + ce.ry[v] * rey) -
+                          (cn.rm[v] + cn.rx[v] * rnx + cn.ry[v] * rny));
+      }
+      T ub[4];
+#pragma unroll 1
+      for (int k = 0; k < 4; ++k) {
+        Dual<T> dL[4], dR[4], F[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          dL[j] = Dual<T>(uL[j], T(side == 0 && j == k ? 1 : 0));
+          dR[j] = Dual<T>(uR[j], T(side == 1 && j == k ? 1 : 0));
+        }
+        bool bad = false;
+        hll_n(dL, dR, Dual<T>(nx, T(0)), Dual<T>(ny, T(0)), dgam, F, bad);
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = fma(Fb[j], F[j].d, acc);
+        ub[k] = acc;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        g[3 * v] += ub[v];
+        g[3 * v + 1] = fma(rex, ub[v], g[3 * v + 1]);
+        g[3 * v + 2] = fma(rey, ub[v], g[3 * v + 2]);
+      }
+    }
+  }
+  // volume term: the 4 principal-axis points c -+ a_k
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const T sgn = (q & 1) ? T(1) : T(-1);
+    const T ox = sgn * ((q & 2) ? cge[6] : cge[4]);
+    const T oy = sgn * ((q & 2) ? cge[7] : cge[5]);
+    T u[4], ub[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = fma(we[3 * v + 1], ox, fma(we[3 * v + 2], oy, we[3 * v]));
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      Dual<T> du[4], Fx[4], Fy[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) du[j] = Dual<T>(u[j], T(j == k ? 1 : 0));
+      euler_xy(du, dgam, Fx, Fy);
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc = fma(ce.vx[j], Fx[j].d, fma(ce.vy[j], Fy[j].d, acc));
+      ub[k] = acc;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      g[3 * v] += ub[v];
+      g[3 * v + 1] = fma(ox, ub[v], g[3 * v + 1]);
+      g[3 * v + 2] = fma(oy, ub[v], g[3 * v + 2]);
+    }
+  }
+  const double dt = p.dt_dev ? *p.dt_dev : p.dt_host;
+  const T cid = (T)p.c_id, cL = (T)(p.c_L_over_dt * dt), cx = (T)p.c_extra;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    T o = fma(cL, g[k], cid * le[k]);
+    if (p.extra) o = fma(cx, p.extra[(size_t)k * p.nc + e], o);
+    p.out[(size_t)k * p.nc + e] = o;
+  }
+}
+
+// out_e = sum over the cells n whose limiter reads P_e (e itself and its face
+// neighbours, each counted once) of (d Pi_n / d P_e)^T lamW_n: the limiter of
+// k_fl_lim (bounds over the cell and its neighbours in the incidence order,
+// alpha = min over the incidences of psi at the face centroid) in dual numbers.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjfl_lim(PFA<T> p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.nc) return;
+  T out[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[k] = T(0);
+  const int e0 = p.inc0[e], e1 = p.inc0[e + 1];
+  for (int ci = e0 - 1; ci < e1; ++ci) {
+    const int n = ci < e0 ? e : p.nbr[ci];
+    bool seen = ci >= e0 && n == e;
+    for (int cj = e0; cj < ci && !seen; ++cj) seen = p.nbr[cj] == n;
+    if (seen) continue;
+    const int n0 = p.inc0[n], n1 = p.inc0[n + 1];
+    bool reads_e = n == e;
+    for (int i = n0; i < n1; ++i) reads_e |= p.nbr[i] == e;
+    if (!reads_e) continue;
+    T pn[12], lw[12];
+    load12(p.P, p.nc, n, pn);
+    load12(p.lamW, p.nc, n, lw);
+#pragma unroll 1
+    for (int k = 0; k < 12; ++k) {
+      // the mean slot of coefficient k (-1: a gradient, read by the own limiter only)
+      const int ks = k % 3 == 0 ? k / 3 : -1;
+      if (n != e && ks < 0) continue;
+      Dual<T> q[12], hi[4], lo[4], al[4];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) q[j] = Dual<T>(pn[j], T(n == e && j == k ? 1 : 0));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        hi[v] = lo[v] = q[3 * v];
+        al[v] = Dual<T>(1.0);
+      }
+      for (int i = n0; i < n1; ++i) {
+        const int m = p.nbr[i];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const Dual<T> mv(p.P[(size_t)(3 * v) * p.nc + m], T(m == e && v == ks ? 1 : 0));
+          hi[v] = fmax(hi[v], mv);
+          lo[v] = fmin(lo[v], mv);
+        }
+      }
+      for (int i = n0; i < n1; ++i) {
+        const Dual<T> rx(p.lim_geo[2 * (size_t)i], T(0)), ry(p.lim_geo[2 * (size_t)i + 1], T(0));
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          al[v] = fmin(al[v], psi_of(q[3 * v + 1] * rx + q[3 * v + 2] * ry, q[3 * v], hi[v], lo[v]));
+      }
+      T acc = T(0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc = fma(lw[3 * v], q[3 * v].d, acc);
+        acc = fma(lw[3 * v + 1], (al[v] * q[3 * v + 1]).d, acc);
+        acc = fma(lw[3 * v + 2], (al[v] * q[3 * v + 2]).d, acc);
+      }
+      out[k] += acc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p.out[(size_t)k * p.nc + e] = out[k];
+}
+
+template <typename T>
+hipError_t adjoint_t(const dg_mesh* m, const void* U, const void* V1, const double* dt_dev,
+                     double dt, const void* lam_np1, void* lam_n, void* ws1, void* ws2,
+                     hipStream_t s) {
+  const FLDev& f = *m->fld;
+  const bool lim = m->cfg.limiter == DG_LIMITER_MINMOD;
+  const dim3 grid((unsigned)((f.ncells + 255) / 256)), block(256);
+  PFA<T> p{};
+  p.dt_dev = dt_dev;
+  p.dt_host = dt;
+  p.nc = f.ncells;
+  p.gamma = (T)m->cfg.gamma;
+  p.inc0 = f.lim_inc0;
+  p.nbr = f.lim_nbr;
+  p.inc_face = f.inc_face;
+  p.face_lr = f.face_lr;
+  p.face_geo = static_cast<const T*>(f.face_geo);
+  p.lim_geo = static_cast<const T*>(f.lim_geo);
+  p.cell_geo = static_cast<const T*>(f.cell_geo);
+  auto adj_stage = [&](const void* P, const void* lam, const void* extra, double c_id,
+                       double c_L_over_dt, double c_extra, void* out) -> hipError_t {
+    // W = Pi(P) into ws1; lamW into ws2 (or straight into out without a
+    // limiter); out = Pi_P^T lamW
+    const void* W = P;
+    if (lim) {
+      hipError_t r = lim_t<T>(m, P, ws1, s);
+      if (r != hipSuccess) return r;
+      W = ws1;
+    }
+    PFA<T> a = p;
+    a.W = static_cast<const T*>(W);
+    a.lam = static_cast<const T*>(lam);
+    a.extra = static_cast<const T*>(extra);
+    a.c_id = c_id;
+    a.c_L_over_dt = c_L_over_dt;
+    a.c_extra = c_extra;
+    a.out = static_cast<T*>(lim ? ws2 : out);
+    hipLaunchKernelGGL((k_adjfl_L<T>), grid, block, 0, s, a);
+    if (!lim) return hipGetLastError();
+    PFA<T> b = p;
+    b.P = static_cast<const T*>(P);
+    b.lamW = static_cast<const T*>(ws2);
+    b.out = static_cast<T*>(out);
+    hipLaunchKernelGGL((k_adjfl_lim<T>), grid, block, 0, s, b);
+    return hipGetLastError();
+  };
+  // stage 2: lam_V1 = Pi_V1^T [lam'/2 + (dt/2) L^T lam'] (in lam_n with the
+  // limiter, else in ws2); stage 1: lam_n = Pi_U^T [lam_V1 + dt L^T lam_V1 + lam'/2]
+  void* lam_v1 = lim ? lam_n : ws2;
+  hipError_t e = adj_stage(V1, lam_np1, nullptr, 0.5, 0.5, 0.0, lam_v1);
+  if (e != hipSuccess) return e;
+  return adj_stage(U, lam_v1, lam_np1, 1.0, 1.0, 0.5, lam_n);
+}
+
 // ------------------------------------------------------------ host setup --
 template <typename T>
 hipError_t upload(const std::vector<double>& h, void** d) {
@@ -795,6 +1101,23 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
       cside[i] = 1;
     }
   }
+  // the adjoint's incidence codes and global face records
+  std::vector<int> inc_face(inc0[nc]), face_lr(2 * nf);
+  std::vector<double> fgeo(8 * nf, 0.0);
+  for (int64_t i = 0; i < (int64_t)inc0[nc]; ++i) inc_face[i] = (cface[i] << 1) | cside[i];
+  for (int64_t f = 0; f < nf; ++f) {
+    double rc[2], dLR[2];
+    offsets(f, rc, dLR);
+    face_lr[2 * f] = d->face_cells[2 * f];
+    face_lr[2 * f + 1] = d->face_cells[2 * f + 1];
+    fgeo[8 * f] = d->face_normal[2 * f];
+    fgeo[8 * f + 1] = d->face_normal[2 * f + 1];
+    fgeo[8 * f + 2] = d->face_area[f];
+    fgeo[8 * f + 3] = rc[0];
+    fgeo[8 * f + 4] = rc[1];
+    fgeo[8 * f + 5] = dLR[0];
+    fgeo[8 * f + 6] = dLR[1];
+  }
   // blocks of up to kBlock consecutive cells; a block is halved until its
   // distinct incident faces fit the slot table and its outside neighbours the
   // halo table
@@ -922,6 +1245,9 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
   if (err == hipSuccess) err = up(cgeo, &fd->cell_geo);
   if (err == hipSuccess) err = up(lgeo, &fd->lim_geo);
   if (err == hipSuccess) err = up(perim, &fd->cell_perim);
+  if (err == hipSuccess) err = upload_i(inc_face, &fd->inc_face);
+  if (err == hipSuccess) err = upload_i(face_lr, &fd->face_lr);
+  if (err == hipSuccess) err = up(fgeo, &fd->face_geo);
   if (err != hipSuccess) {
     facelist_destroy(m);
     return hip_fail(err, "dg_mesh_create: face-list upload");
@@ -946,6 +1272,9 @@ void facelist_destroy(dg_mesh* m) {
   (void)hipFree(f->lim_nbr);
   (void)hipFree(f->lim_geo);
   (void)hipFree(f->cell_perim);
+  (void)hipFree(f->inc_face);
+  (void)hipFree(f->face_lr);
+  (void)hipFree(f->face_geo);
   delete f;
   m->fld = nullptr;
 }
@@ -987,6 +1316,14 @@ hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const voi
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_adjoint_facelist(const dg_mesh* m, const void* U, const void* V1,
+                                   const double* dt_dev, double dt, const void* lam_np1,
+                                   void* lam_n, void* ws1, void* ws2, hipStream_t s) {
+  if (m->cfg.precision == DG_FP64)
+    return adjoint_t<double>(m, U, V1, dt_dev, dt, lam_np1, lam_n, ws1, ws2, s);
+  return adjoint_t<float>(m, U, V1, dt_dev, dt, lam_np1, lam_n, ws1, ws2, s);
 }
 
 hipError_t launch_facelist_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
