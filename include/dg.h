@@ -272,10 +272,11 @@ dg_status dg_step_mh(dg_mesh_t mesh, const void* U, void* U_next, double dt, con
  * size), or NULL to recompute it.  Built for 2D Euler on Cartesian meshes,
  * batches and static face-list meshes (HLL; limiter off or DG_LIMITER_MINMOD;
  * on a face list the bounds and alpha run over the cell's faces in the mesh's
- * incidence order) and for 2D ideal MHD on
- * Cartesian meshes (HLLD on the face-averaged normal field, the 23-coefficient
- * basis of Sec. 2.2; limiter off or DG_LIMITER_MINMOD with one alpha for B,
- * ties in the same order; dt frozen); DG_EUNSUPPORTED otherwise.  lam_n must
+ * incidence order) and for 2D and 3D ideal MHD on Cartesian meshes (HLLD on
+ * the face-averaged normal field, the divergence-free field bases of Sec. 2.2;
+ * limiter off or DG_LIMITER_MINMOD with one alpha for B, ties in the same
+ * order, then -z, +z); DG_EUNSUPPORTED otherwise (the exact Riemann solver,
+ * the WENO-type limiter, moving meshes).  lam_n must
  * not alias U, V1 or lam_np1.  Allocates two state-sized workspaces on the
  * first call (kept by the handle). */
 dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double dt,

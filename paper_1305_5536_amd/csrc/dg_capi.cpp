@@ -51,6 +51,9 @@ hipError_t launch_facelist(const dg_mesh* m, int mode, const void* in, const voi
                            hipStream_t s);
 hipError_t launch_facelist_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                                hipStream_t s);
+hipError_t launch_adjoint_mhd3d(const dg_mesh* m, const void* U, const void* V1,
+                                const double* dt_dev, double dt, const void* lam_np1,
+                                void* lam_n, void* ws1, void* ws2, hipStream_t s);
 hipError_t launch_adjoint_facelist(const dg_mesh* m, const void* U, const void* V1,
                                    const double* dt_dev, double dt, const void* lam_np1,
                                    void* lam_n, void* ws1, void* ws2, hipStream_t s);
@@ -673,14 +676,15 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
   // 2D ideal MHD on a single Cartesian mesh (HLLD, limiter of Sec. 2.5 or none)
   const bool mhd2 = m->kind == 0 && m->dim == 2 && m->cfg.physics == DG_MHD &&
                     m->cfg.limiter != DG_LIMITER_WENO;
+  const bool mhd3 = m->kind == 0 && m->dim == 3 && m->cfg.limiter != DG_LIMITER_WENO;
   // 2D Euler on a static face-list mesh (HLL, limiter of Sec. 2.5 or none)
   const bool flist = m->kind == 1 && m->cfg.physics == DG_EULER &&
                      m->cfg.flux == DG_FLUX_HLL && m->cfg.limiter != DG_LIMITER_WENO;
-  if (!mhd2 && !flist &&
+  if (!mhd2 && !mhd3 && !flist &&
       (!m->adj_inst || m->cfg.flux != DG_FLUX_HLL || m->cfg.limiter == DG_LIMITER_WENO)) {
     set_error("dg_adjoint_step: built for 2D Euler Cartesian meshes, batches and static "
-              "face-list meshes with HLL and the Arepo limiter, and 2D MHD Cartesian meshes "
-              "with HLLD");
+              "face-list meshes with HLL and the Arepo limiter, and 2D and 3D MHD Cartesian "
+              "meshes with HLLD");
     return DG_EUNSUPPORTED;
   }
   if (!dt_dev && (!std::isfinite(dt) || dt < 0))
@@ -698,11 +702,13 @@ dg_status dg_adjoint_step(dg_mesh_t m, const void* U, const void* V1, double dt,
     if (st != DG_OK) return st;
     V1 = m->v1;
   }
-  if (mhd2 || flist) {
-    e = mhd2 ? launch_adjoint_mhd2d(m, U, V1, dt_dev, dt, lam_np1, lam_n, m->adj_ws1,
-                                    m->adj_ws2, s)
-             : launch_adjoint_facelist(m, U, V1, dt_dev, dt, lam_np1, lam_n, m->adj_ws1,
-                                       m->adj_ws2, s);
+  if (mhd2 || mhd3 || flist) {
+    e = mhd2   ? launch_adjoint_mhd2d(m, U, V1, dt_dev, dt, lam_np1, lam_n, m->adj_ws1,
+                                      m->adj_ws2, s)
+        : mhd3 ? launch_adjoint_mhd3d(m, U, V1, dt_dev, dt, lam_np1, lam_n, m->adj_ws1,
+                                      m->adj_ws2, s)
+               : launch_adjoint_facelist(m, U, V1, dt_dev, dt, lam_np1, lam_n, m->adj_ws1,
+                                         m->adj_ws2, s);
     if (e != hipSuccess) return hip_fail(e, "dg_adjoint_step launch");
     return DG_OK;
   }
