@@ -298,3 +298,47 @@ def test_fp32_gradient_error_stated(torch_cuda, limiter):
     print(f"limiter {limiter}: FP32 vs FP64 rollout gradient (40 steps): relative L2 means "
           f"{l2m:.3e}, gradients {l2g:.3e}; max entry {mx:.3e}")
     assert max(l2m, l2g) < (1e-4 if not limiter else 1e-2)
+
+
+@pytest.mark.parametrize("kind", ["mhd2d", "voronoi", "mhd3d"])
+def test_rollout_gradient_on_other_meshes(oracle, torch_cuda, kind):
+    """The differentiable rollout on 2D MHD, static Voronoi and 3D MHD meshes
+    (the limiter on, 12 steps on the oracle's dt schedule, checkpoints every
+    5): the gradient of <w, U_N> along random directions equals the oracle's
+    dual-number derivative chained step by step."""
+    torch = torch_cuda
+    from paper_1305_5536_amd.rollout import rollout
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    nsteps, mhd = 12, kind != "voronoi"
+    if kind == "mhd2d":
+        n = (10, 8)
+        om = oracle.Mesh.cartesian(n, *BOX)
+        U0 = W.random_p1_state(n, *BOX, G53, seed=91, amp=0.3, mhd=True, bamp=0.05)
+        s = Solver(cartesian(n, *BOX), physics="mhd", gamma=G53)
+    elif kind == "mhd3d":
+        n, lo, hi = (5, 4, 3), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+        om = oracle.Mesh.cartesian(n, lo, hi)
+        U0 = W.random_p1_state(n, lo, hi, G53, seed=92, amp=0.2, mhd=True)
+        s = Solver(cartesian(n, lo, hi), physics="mhd", gamma=G53)
+    else:
+        from workloads.voronoi import periodic_voronoi, random_voronoi_state
+        m = periodic_voronoi(60, seed=93)
+        om = oracle.Mesh.facelist(m)
+        U0 = random_voronoi_state(m, G53, seed=94, amp=0.2)
+        s = Solver(m, gamma=G53)
+    _, dts = oracle.run(om, U0, nsteps, G53, 0.3, True, mhd=mhd)
+    rng = np.random.default_rng(95)
+    w = rng.standard_normal(U0.size)
+    U = s.to_device(U0).requires_grad_(True)
+    out, _ = rollout(s, U, nsteps, k=5, dt_hist=torch.tensor(dts, dtype=torch.float64,
+                                                             device=s.device))
+    (out * torch.as_tensor(w, device=s.device)).sum().backward()
+    grad = U.grad.cpu().numpy()
+    for _ in range(3):
+        v = rng.standard_normal(U0.size)
+        u, du = U0.copy(), v.copy()
+        for dt in dts:
+            u, du = oracle.step_jvp(om, u, du, dt, G53, True, mhd=mhd)
+        ref, got = du @ w, grad @ v
+        print(f"{kind} rollout: oracle {ref:.12e} GPU {got:.12e}")
+        assert abs(got - ref) <= 1e-10 * np.abs(du * w).sum(), (got, ref)
