@@ -535,6 +535,12 @@ def bench_c3(a):
     # stage 1 = limiter pass + RHS kernel; report the whole stage against the
     # VALU peak (the RHS kernel dominates it; rocprof splits the two)
     achieved = MHD_FLOPS_PER_CELL_STAGE * ncells / r["stage1_s"] / 1e12
+    traffic = None
+    if a.precision == "fp64":
+        traffic = pmc_traffic("k_rhs3d_c3_256_fp64.md", "stage 1 (k_lim3d + k_rhs3d)", f"{n}^3",
+                              ("paper_1305_5536_amd/csrc/cart3d.hip",
+                               "paper_1305_5536_amd/csrc/mhd_hlld.h",
+                               "paper_1305_5536_amd/csrc/dg_math.h"))
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["event_s"] / a.steps * 1e3,
@@ -545,7 +551,7 @@ def bench_c3(a):
                    "cells": ncells, "rk_stages_per_step": 2, "parallelism": "single GPU",
                    "input_generation_s": tgen},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "stage 1 (k_lim3d + k_rhs3d)",
                      "flops_per_launch": MHD_FLOPS_PER_CELL_STAGE * ncells,
                      "avg_launch_s": r["stage1_s"]},

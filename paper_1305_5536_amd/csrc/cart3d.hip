@@ -9,16 +9,20 @@
 // B); slope limiter of Sec. 2.5 with one alpha for the three B components.
 //
 // Kernels.
-//   k_lim3d  : Pi(U) -> out, one thread per cell (memory bound).
-//   k_rhs3d  : L(Ulim) combined into an SSP-RK2 stage.  One wave owns a pencil
-//              of up to 62 x-columns (lanes 0 and 63 are halo columns) of one
-//              y-row and marches through a range of z-planes.  x-faces: each
-//              lane solves its -x face and passes it left by shuffle.
-//              z-faces: solved once per plane pair; the upper plane's share is
-//              carried in registers.  y-faces: solved by both adjacent rows
-//              (bitwise-identical arithmetic), which keeps waves independent.
+//   k_lim3d  : Pi(U) -> out, four row-waves per workgroup marching in z, each
+//              cell read once (memory bound).
+//   k_rhs3d  : L(Ulim) combined into an SSP-RK2 stage.  A workgroup of four
+//              row-waves owns a pencil of up to 62 x-columns (lanes 0 and 63
+//              are halo columns) of four consecutive y-rows and marches
+//              through a range of z-planes.  x-faces: each lane solves its -x
+//              face and passes it left by shuffle.  z-faces: solved once per
+//              plane pair, the upper plane's share carried in LDS.  y-faces:
+//              solved once, by the upper row's wave, and handed to the wave
+//              below through LDS; the group's top face is split by Gauss point
+//              over the four waves.
 //   k_cfl3d  : per-block minima of the CFL bound (fast magnetosonic speeds).
-// The kernel is FP64/FP32 VALU-bound: 12 HLLD solves per cell and stage.
+// The kernel is FP64/FP32 VALU-bound: 12 HLLD solves per cell and stage, 13
+// per cell as executed (the top face of each group of rows is solved twice).
 //
 // Residual algebra per face of axis D (tangential axes t1, t2), Gauss points
 // at tangential signs (s1, s2), S = sum F, T1 = sum s1 F, T2 = sum s2 F, cell on
@@ -33,6 +37,9 @@
 // ra10 = P[x][x] - P[y][y], ra11 = P[x][x] - P[z][z], and a = (M_B/V)^-1 ra
 // with M_B the Gram matrix of V4..V11 (diagonal plus a 2x2 block on a box).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
 
 #include "dg_internal.h"
 #include "dg_math.h"
@@ -53,7 +60,7 @@ struct P3 {
   int* status;
   double* dtpart;
   int nx, ny, nz, nc;
-  int width, tiles_x, planes, tiles_z, ntiles;
+  int width, tiles_x, tiles_y, planes, tiles_z, ntiles;  // tiles_y: groups of kGW rows
   T gamma, eps;
   T h[3];
   T c4h[3];    // 1/(4 h_d)
@@ -74,41 +81,55 @@ struct Poly {
   T m[5], g[5][3], b[3], a[8];
 };
 
+// Element e of coefficient row k: the row's base is uniform across the wave
+// and e enters as a 32-bit byte offset (ncells * 31 < 2^31 is checked at mesh
+// creation, so 8 e < 2^32).
+template <typename T>
+__device__ __forceinline__ T ld_row(const T* __restrict__ U, int nc, int k, int e) {
+  const char* row = reinterpret_cast<const char*>(U + (size_t)k * (size_t)nc);
+  return *reinterpret_cast<const T*>(row + (uint32_t)e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_row(T* __restrict__ U, int nc, int k, int e, T v) {
+  char* row = reinterpret_cast<char*>(U + (size_t)k * (size_t)nc);
+  *reinterpret_cast<T*>(row + (uint32_t)e * (uint32_t)sizeof(T)) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_poly(const T* __restrict__ U, int nc, int e, Poly<T>& q) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    q.m[v] = U[(4 * v) * nc + e];
+    q.m[v] = ld_row(U, nc, 4 * v, e);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) q.g[v][d] = U[(4 * v + 1 + d) * nc + e];
+    for (int d = 0; d < 3; ++d) q.g[v][d] = ld_row(U, nc, 4 * v + 1 + d, e);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) q.b[c] = U[(20 + c) * nc + e];
+  for (int c = 0; c < 3; ++c) q.b[c] = ld_row(U, nc, 20 + c, e);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) q.a[j] = U[(23 + j) * nc + e];
+  for (int j = 0; j < 8; ++j) q.a[j] = ld_row(U, nc, 23 + j, e);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_poly(T* __restrict__ U, int nc, int e, const Poly<T>& q) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    U[(4 * v) * nc + e] = q.m[v];
+    st_row(U, nc, 4 * v, e, q.m[v]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) U[(4 * v + 1 + d) * nc + e] = q.g[v][d];
+    for (int d = 0; d < 3; ++d) st_row(U, nc, 4 * v + 1 + d, e, q.g[v][d]);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) U[(20 + c) * nc + e] = q.b[c];
+  for (int c = 0; c < 3; ++c) st_row(U, nc, 20 + c, e, q.b[c]);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) U[(23 + j) * nc + e] = q.a[j];
+  for (int j = 0; j < 8; ++j) st_row(U, nc, 23 + j, e, q.a[j]);
 }
 
 // Conserved means in the order rho, mx, my, mz, E, Bx, By, Bz.
 template <typename T>
 __device__ __forceinline__ void load_means(const T* __restrict__ U, int nc, int e, T* m) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) m[v] = U[(4 * v) * nc + e];
+  for (int v = 0; v < 5; ++v) m[v] = ld_row(U, nc, 4 * v, e);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) m[5 + c] = U[(20 + c) * nc + e];
+  for (int c = 0; c < 3; ++c) m[5 + c] = ld_row(U, nc, 20 + c, e);
 }
 
 // Gradient of B_c from the divergence-free coefficients:
@@ -128,34 +149,15 @@ __device__ __forceinline__ T alpha_of(T phi, T hi, T lo, const T* g, const P3<T>
 }
 
 // ------------------------------------------------------------- limiter --
+// Row-waves per workgroup of the stage kernel and of the limiter: kGW
+// consecutive y-rows of one x-strip march through the same z-planes together.
+constexpr int kGW = 4;
+
+// Limits one cell (Sec. 2.5) from its bounds hi/lo over itself and its six
+// face neighbours, in the order self, -x, +x, -y, +y, -z, +z.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lim3d(P3<T> p) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= p.nc) return;
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int i = e % nx, j = (e / nx) % ny, k = e / (nx * ny);
-  const int nb[6] = {
-      e - i + (i == 0 ? nx - 1 : i - 1), e - i + (i == nx - 1 ? 0 : i + 1),
-      e + ((j == 0 ? ny - 1 : j - 1) - j) * nx, e + ((j == ny - 1 ? 0 : j + 1) - j) * nx,
-      e + ((k == 0 ? nz - 1 : k - 1) - k) * nx * ny, e + ((k == nz - 1 ? 0 : k + 1) - k) * nx * ny};
-  Poly<T> q;
-  load_poly(p.in, p.nc, e, q);
-  T hi[8], lo[8];
-  hi[0] = lo[0] = q.m[0];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) hi[v] = lo[v] = q.m[v];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) hi[5 + c] = lo[5 + c] = q.b[c];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    T mn[8];
-    load_means(p.in, p.nc, nb[f], mn);
-#pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-      hi[k2] = fmax(hi[k2], mn[k2]);
-      lo[k2] = fmin(lo[k2], mn[k2]);
-    }
-  }
+__device__ __forceinline__ void limit_cell3(Poly<T>& q, const T* hi, const T* lo,
+                                            const P3<T>& p) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     T a = alpha_of(q.m[v], hi[v], lo[v], q.g[v], p);
@@ -170,7 +172,128 @@ __global__ __launch_bounds__(256) void k_lim3d(P3<T> p) {
   }
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj) q.a[jj] *= aB;
-  store_poly(p.out, p.nc, e, q);
+}
+
+template <typename T>
+__device__ __forceinline__ void bound8(T* hi, T* lo, const T* mn) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    hi[k] = fmax(hi[k], mn[k]);
+    lo[k] = fmin(lo[k], mn[k]);
+  }
+}
+
+// Pi(U) -> out.  A workgroup of kGW row-waves owns a 64-column x-strip of kGW
+// consecutive y-rows and marches through p.planes z-planes, so each cell's
+// polynomial is read once: the x-neighbours' means come from the adjacent
+// lane, the y-neighbours' from the adjacent row-wave through LDS, the
+// z-neighbours' from the previous and the prefetched next plane in registers.
+// Only strip and group edges (and periodic wraps) read neighbour means from
+// memory.  Row-waves past the last row keep to the barriers only.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lim3d(P3<T> p) {
+  __shared__ T ml[kGW][8][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  if (grp >= p.ntiles) return;  // whole workgroup
+  const int tx = grp % p.tiles_x;
+  const int rest = grp / p.tiles_x;
+  const int gy = rest % p.tiles_y;
+  const int tz = rest / p.tiles_y;
+  const int nx = p.nx, ny = p.ny, nz = p.nz, nc = p.nc;
+  const int y0 = gy * kGW;
+  const int top = min(kGW - 1, ny - 1 - y0);
+  const bool real = w <= top;
+  const int y = y0 + (real ? w : top);
+  const int colu = tx * 64 + lane;
+  const bool own = colu < nx;
+  const int col = own ? colu : nx - 1;
+  const int xm = col == 0 ? nx - 1 : col - 1;
+  const int xp = col == nx - 1 ? 0 : col + 1;
+  // neighbour in the adjacent lane of this wave (not across a periodic wrap)
+  const bool xm_lane = lane > 0 && col > 0;
+  const bool xp_lane = lane < 63 && col + 1 < nx;
+  const int ym = y == 0 ? ny - 1 : y - 1;
+  const int yp = y == ny - 1 ? 0 : y + 1;
+  // neighbour row held by a row-wave of this group (its LDS slot)
+  const int sm_ = ym >= y0 && ym <= y0 + top ? ym - y0 : -1;
+  const int sp_ = yp >= y0 && yp <= y0 + top ? yp - y0 : -1;
+  const int z0 = tz * p.planes;
+  const int z1 = min(z0 + p.planes, nz);
+  auto idx = [&](int xx, int yy, int zz) { return (zz * ny + yy) * nx + xx; };
+  auto zw = [nz](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  auto load_rest = [&](int e, Poly<T>& q) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) q.g[v][d] = ld_row(p.in, nc, 4 * v + 1 + d, e);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q.a[j] = ld_row(p.in, nc, 23 + j, e);
+  };
+
+  // means of the planes below, at and above the current one (rho, m, E, B)
+  T mprev[8], mc[8];
+  if (real) {
+    load_means(p.in, nc, idx(col, y, zw(z0 - 1)), mprev);
+    load_means(p.in, nc, idx(col, y, z0), mc);
+  }
+  for (int z = z0; z < z1; ++z) {
+    T mnx[8];
+    Poly<T> q;
+    if (real) {
+      // the next plane's means and this cell's slopes, in flight across the
+      // barriers
+      load_means(p.in, nc, idx(col, y, zw(z + 1)), mnx);
+      load_rest(idx(col, y, z), q);
+    }
+    __syncthreads();  // the previous plane's reads of ml are done
+    if (real) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ml[w][k][lane] = mc[k];
+    }
+    __syncthreads();
+    if (real) {
+      T hi[8], lo[8], mn[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) hi[k] = lo[k] = mc[k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) mn[k] = lane_up(mc[k]);
+      if (!xm_lane) load_means(p.in, nc, idx(xm, y, z), mn);
+      bound8(hi, lo, mn);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) mn[k] = lane_down(mc[k]);
+      if (!xp_lane) load_means(p.in, nc, idx(xp, y, z), mn);
+      bound8(hi, lo, mn);
+      if (sm_ >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mn[k] = ml[sm_][k][lane];
+      } else {
+        load_means(p.in, nc, idx(col, ym, z), mn);
+      }
+      bound8(hi, lo, mn);
+      if (sp_ >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mn[k] = ml[sp_][k][lane];
+      } else {
+        load_means(p.in, nc, idx(col, yp, z), mn);
+      }
+      bound8(hi, lo, mn);
+      bound8(hi, lo, mprev);
+      bound8(hi, lo, mnx);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q.m[v] = mc[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q.b[c] = mc[5 + c];
+      limit_cell3(q, hi, lo, p);
+      if (own) store_poly(p.out, nc, idx(col, y, z), q);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        mprev[k] = mc[k];
+        mc[k] = mnx[k];
+      }
+    }
+  }
 }
 
 template <typename T, int D>
@@ -393,14 +516,6 @@ __device__ __forceinline__ double cell_dt3(const T* m, const P3<T>& p) {
   return 1.0 / s;
 }
 
-// Per-wave LDS: the current plane's polynomial of every lane and the -z face
-// sums carried from the previous plane.
-template <typename T>
-struct Lds3 {
-  T cur[kNC][64];
-  T carry[24][64];
-};
-
 template <typename T>
 __device__ __forceinline__ void lds_put_poly(T (*dst)[64], int lane, const Poly<T>& q) {
 #pragma unroll
@@ -474,23 +589,94 @@ __device__ __forceinline__ void face_into(const Poly<T>& L, const Poly<T>& R, T 
   }
 }
 
+// Face sums of axis D in 23 LDS rows: S without its normal-field entry (the
+// normal flux of B_D, which no residual uses), then T1 and T2.
+template <typename T, int D>
+__device__ __forceinline__ void put_sums(T (*dst)[64], int lane, const FaceSums<T>& f) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k != 5 + D) dst[k < 5 + D ? k : k - 1][lane] = f.S[k];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    dst[7 + k][lane] = f.T1[k];
+    dst[15 + k][lane] = f.T2[k];
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void get_sums(const T (*src)[64], int lane, FaceSums<T>& f) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) f.S[k] = k == 5 + D ? T(0) : src[k < 5 + D ? k : k - 1][lane];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f.T1[k] = src[7 + k][lane];
+    f.T2[k] = src[15 + k][lane];
+  }
+}
+
+// HLLD flux at one Gauss point (tangential signs s1, s2) of a face of axis D,
+// with the arithmetic of face() at that point.
+template <typename T, int D>
+__device__ __forceinline__ void face_point(const Poly<T>& L, const Poly<T>& R, T s1, T s2,
+                                           const P3<T>& p, T* F, bool& bad) {
+  T bL[8], iL1[8], iL2[8], bR[8], iR1[8], iR2[8];
+  face_trace<T, D>(L, T(1), p, bL, iL1, iL2);
+  face_trace<T, D>(R, T(-1), p, bR, iR1, iR2);
+  T uL[8], uR[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uL[k] = fma(s2, iL2[k], fma(s1, iL1[k], bL[k]));
+    uR[k] = fma(s2, iR2[k], fma(s1, iR1[k], bR[k]));
+  }
+  const T bn = T(0.5) * (uL[5 + D] + uR[5 + D]);
+  uL[5 + D] = bn;
+  uR[5 + D] = bn;
+  hlld<T, D>(uL, uR, p, F, bad);
+}
+
+// LDS of one workgroup (FP64 162,304 B, FP32 81,152 B).
+template <typename T>
+struct Lds3 {
+  T cur[kGW][kNC][64];      // each row-wave's current plane
+  T carry[kGW][23][64];     // each row-wave's -z face sums, carried to the next plane
+  T ysum[kGW - 1][23][64];  // -y face sums of row-waves 1.. for the row-wave below
+  T xtra[kGW][8][64];       // row-wave w: flux at Gauss point w of the group's top +y face
+};
+
+// Stage kernel: a workgroup of kGW row-waves, row-wave w owning row y0 + w of
+// an x-strip (62 interior lanes), all marching through the same z-planes.
+// Per plane: x-faces by shuffle, the -z face carried from the previous plane,
+// the -y face solved by the row-wave itself (the row below read from the
+// neighbouring row-wave's LDS slot, from memory for w = 0) and handed to the
+// row-wave below as its +y face; the group's top +y face is split by Gauss
+// point over the kGW row-waves, so that each solves 13 HLLD problems per cell.
+// Two barriers per plane; row-waves past the last row (ny not a multiple of
+// kGW) keep to the barriers and their share of the top face only.  With one
+// wave per SIMD nothing hides a load's latency but the wave's own work, so each
+// load is issued well ahead of its use (stage 2 issues its Pi(U^n) row before
+// the second barrier, which took the stage from 12.6 to 10.4 ms at 256^3).
 template <typename T, int MODE>
-__global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
+__global__ __launch_bounds__(256) void k_rhs3d(P3<T> p) {
   __shared__ Lds3<T> sm;
-  const int lane = threadIdx.x;
-  const int wave = xcd_remap(blockIdx.x, gridDim.x);
-  if (wave >= p.ntiles) return;
-  const int tx = wave % p.tiles_x;
-  const int rest = wave / p.tiles_x;
-  const int y = rest % p.ny;
-  const int tz = rest / p.ny;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  if (grp >= p.ntiles) return;  // whole workgroup
+  const int tx = grp % p.tiles_x;
+  const int rest = grp / p.tiles_x;
+  const int gy = rest % p.tiles_y;
+  const int tz = rest / p.tiles_y;
   const int nx = p.nx, ny = p.ny, nz = p.nz, nc = p.nc;
+  const int y0 = gy * kGW;
+  const int top = min(kGW - 1, ny - 1 - y0);
+  const bool real = w <= top;
+  const int y = y0 + (real ? w : top);
+  const int yS = y == 0 ? ny - 1 : y - 1;
+  const int yT1 = y0 + top == ny - 1 ? 0 : y0 + top + 1;
   const int colu = tx * p.width + lane - 1;
   const bool own = lane >= 1 && lane <= p.width && colu < nx;
   int col = colu % nx;
   if (col < 0) col += nx;
-  const int yS = y == 0 ? ny - 1 : y - 1;
-  const int yN = y == ny - 1 ? 0 : y + 1;
   const int z0 = tz * p.planes;
   const int z1 = min(z0 + p.planes, nz);
   auto idx = [&](int yy, int zz) { return (zz * ny + yy) * nx + col; };
@@ -498,86 +684,110 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
   bool bad = false;
   double dtmin = 1e300;
   const int left = lane == 0 ? 0 : lane - 1;
+  // this row-wave's Gauss point of the top face (the order of face())
+  const T gs1 = (w & 2) ? T(1) : T(-1);
+  const T gs2 = (w & 1) ? T(1) : T(-1);
 
-  {
+  if (real) {
     Poly<T> prv, cur;
     load_poly(p.in, nc, idx(y, zw(z0 - 1)), prv);
     load_poly(p.in, nc, idx(y, z0), cur);
     FaceSums<T> fz;
     face<T, 2>(prv, cur, p, fz, bad);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      sm.carry[k][lane] = fz.S[k];
-      sm.carry[8 + k][lane] = fz.T1[k];
-      sm.carry[16 + k][lane] = fz.T2[k];
-    }
-    lds_put_poly(sm.cur, lane, cur);
+    put_sums<T, 2>(sm.carry[w], lane, fz);
+    lds_put_poly(sm.cur[w], lane, cur);
   }
   T dt = T(0);
   if (MODE != kRhs) dt = (T)(p.dt_dev ? *p.dt_dev : p.dt_host);
 
   for (int z = z0; z < z1; ++z) {
-    Poly<T> nb;  // neighbour polynomial in flight: y-1, then y+1, then z+1
+    // every row-wave's plane z is in LDS; last plane's exchanges are consumed
+    __syncthreads();
+    Poly<T> nb;  // in flight: the row above the group, the row below (w = 0), plane z+1
+    load_poly(p.in, nc, idx(yT1, z), nb);
     Acc<T> acc;
     zero(acc);
-    {
+    Poly<T> ua;  // stage 2: Pi(U^n) of this row, loaded before the second barrier
+    if (real) {
       FaceSums<T> fz;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        fz.S[k] = sm.carry[k][lane];
-        fz.T1[k] = sm.carry[8 + k][lane];
-        fz.T2[k] = sm.carry[16 + k][lane];
-      }
+      get_sums<T, 2>(sm.carry[w], lane, fz);
       add_face<T, 2>(acc, fz, T(1), p);
-    }
-    {
       // x-faces: this lane solves its -x face (left neighbour from LDS), the
       // +x face comes from lane+1 by shuffle
       Poly<T> l, c;
-      lds_get_poly(sm.cur, left, l);
-      lds_get_poly(sm.cur, lane, c);
+      lds_get_poly(sm.cur[w], left, l);
+      lds_get_poly(sm.cur[w], lane, c);
       FaceSums<T> fx;
       face<T, 0>(l, c, p, fx, bad);
       add_face<T, 0>(acc, fx, T(1), p);
       shfl_down_sums(fx);
       add_face<T, 0>(acc, fx, T(-1), p);
     }
-    load_poly(p.in, nc, idx(yS, z), nb);
     {
+      Poly<T> l;
+      lds_get_poly(sm.cur[top], lane, l);
+      T F[8];
+      face_point<T, 1>(l, nb, gs1, gs2, p, F, bad);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sm.xtra[w][k][lane] = F[k];
+    }
+    if (real) {
+      if (w == 0) load_poly(p.in, nc, idx(yS, z), nb);
+      {
+        Poly<T> c;
+        lds_get_poly(sm.cur[w], lane, c);
+        add_volume(acc, c, p, bad);
+      }
+      if (w > 0) lds_get_poly(sm.cur[w - 1], lane, nb);
       Poly<T> c;
-      lds_get_poly(sm.cur, lane, c);
-      add_volume(acc, c, p, bad);
+      lds_get_poly(sm.cur[w], lane, c);
+      FaceSums<T> fy;
+      face<T, 1>(nb, c, p, fy, bad);
+      add_face<T, 1>(acc, fy, T(1), p);
+      if (w > 0) put_sums<T, 1>(sm.ysum[w - 1], lane, fy);
+      load_poly(p.in, nc, idx(y, zw(z + 1)), nb);
+      if (MODE == kStage2) load_poly(p.ua, nc, idx(y, z), ua);
+    }
+    // the -y sums and the top face's Gauss-point fluxes are in LDS
+    __syncthreads();
+    if (!real) continue;
+    {
+      FaceSums<T> fy;
+      if (w < top) {
+        get_sums<T, 1>(sm.ysum[w], lane, fy);
+      } else {
+        // sum the four Gauss points in the order of face(), so that this face
+        // matches bitwise the -y face the group above solves
+#pragma unroll
+        for (int k = 0; k < 8; ++k) fy.S[k] = fy.T1[k] = fy.T2[k] = T(0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const T s1 = (g & 2) ? T(1) : T(-1);
+          const T s2 = (g & 1) ? T(1) : T(-1);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const T F = sm.xtra[g][k][lane];
+            fy.S[k] += F;
+            fy.T1[k] = fma(s1, F, fy.T1[k]);
+            fy.T2[k] = fma(s2, F, fy.T2[k]);
+          }
+        }
+      }
+      add_face<T, 1>(acc, fy, T(-1), p);
     }
     {
       Poly<T> c;
-      lds_get_poly(sm.cur, lane, c);
-      face_into<T, 1>(nb, c, T(1), p, acc, bad);
-    }
-    load_poly(p.in, nc, idx(yN, z), nb);
-    {
-      Poly<T> c;
-      lds_get_poly(sm.cur, lane, c);
-      face_into<T, 1>(c, nb, T(-1), p, acc, bad);
-    }
-    load_poly(p.in, nc, idx(y, zw(z + 1)), nb);
-    {
-      Poly<T> c;
-      lds_get_poly(sm.cur, lane, c);
+      lds_get_poly(sm.cur[w], lane, c);
       FaceSums<T> fz;
       face<T, 2>(c, nb, p, fz, bad);
       add_face<T, 2>(acc, fz, T(-1), p);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        sm.carry[k][lane] = fz.S[k];
-        sm.carry[8 + k][lane] = fz.T1[k];
-        sm.carry[16 + k][lane] = fz.T2[k];
-      }
+      put_sums<T, 2>(sm.carry[w], lane, fz);
     }
     Poly<T> d;
     finish(acc, p, d);
     {
       Poly<T> c;
-      lds_get_poly(sm.cur, lane, c);
+      lds_get_poly(sm.cur[w], lane, c);
       if (MODE != kRhs) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -592,8 +802,6 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
       }
     }
     if (MODE == kStage2) {
-      Poly<T> ua;
-      load_poly(p.ua, nc, idx(y, z), ua);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         d.m[v] = T(0.5) * (ua.m[v] + d.m[v]);
@@ -612,14 +820,14 @@ __global__ __launch_bounds__(64) void k_rhs3d(P3<T> p) {
         dtmin = fmin(dtmin, cell_dt3(mm, p));
       }
     }
-    // the next plane becomes current (all lanes of the wave finished reading
-    // their neighbours' slots above: LDS operations of one wave run in order)
-    lds_put_poly(sm.cur, lane, nb);
+    // the next plane becomes current (the other row-waves read this slot only
+    // before the barrier above)
+    lds_put_poly(sm.cur[w], lane, nb);
   }
   if (bad && own) atomicOr(p.status, 1);
   if (MODE == kStage2 && p.dtpart) {
     dtmin = wave_min(dtmin);
-    if (lane == 0) p.dtpart[wave] = dtmin;
+    if (lane == 0) p.dtpart[grp * kGW + w] = dtmin;
   }
 }
 
@@ -655,7 +863,8 @@ P3<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
   p.width = (p.nx + p.tiles_x - 1) / p.tiles_x;
   p.planes = m->c3.planes_per_tile;
   p.tiles_z = m->c3.tiles_z;
-  p.ntiles = p.tiles_x * p.ny * p.tiles_z;
+  p.tiles_y = (p.ny + kGW - 1) / kGW;
+  p.ntiles = p.tiles_x * p.tiles_y * p.tiles_z;
   p.gamma = (T)m->cfg.gamma;
   p.eps = (T)(m->cfg.precision == DG_FP64 ? 1e-12 : 1e-6);
   const double h[3] = {m->c3.hx, m->c3.hy, m->c3.hz};
@@ -685,8 +894,15 @@ P3<T> make_params(const dg_mesh* m, const void* in, const void* ua, void* out,
 template <typename T>
 hipError_t lim_t(const dg_mesh* m, const void* in, void* out, hipStream_t s) {
   P3<T> p = make_params<T>(m, in, nullptr, out, nullptr, 0.0);
-  const unsigned nb = (unsigned)((m->ncells + 255) / 256);
-  hipLaunchKernelGGL((k_lim3d<T>), dim3(nb), dim3(256), 0, s, p);
+  // 64-column strips, groups of kGW rows, and a quarter of the stage kernel's
+  // planes per workgroup (16 at 256^3: 16k row-waves, several rounds of
+  // resident waves per SIMD for this memory-bound pass)
+  p.width = 64;
+  p.tiles_x = (p.nx + 63) / 64;
+  p.planes = std::max(1, (m->c3.planes_per_tile + 3) / 4);
+  p.tiles_z = (p.nz + p.planes - 1) / p.planes;
+  p.ntiles = p.tiles_x * p.tiles_y * p.tiles_z;
+  hipLaunchKernelGGL((k_lim3d<T>), dim3(p.ntiles), dim3(64 * kGW), 0, s, p);
   return hipGetLastError();
 }
 
@@ -698,13 +914,13 @@ hipError_t rhs_t(const dg_mesh* m, int mode, const void* in, const void* ua, voi
   const unsigned nb = (unsigned)p.ntiles;
   switch (mode) {
     case kRhs:
-      hipLaunchKernelGGL((k_rhs3d<T, kRhs>), dim3(nb), dim3(64), 0, s, p);
+      hipLaunchKernelGGL((k_rhs3d<T, kRhs>), dim3(nb), dim3(64 * kGW), 0, s, p);
       break;
     case kStage1:
-      hipLaunchKernelGGL((k_rhs3d<T, kStage1>), dim3(nb), dim3(64), 0, s, p);
+      hipLaunchKernelGGL((k_rhs3d<T, kStage1>), dim3(nb), dim3(64 * kGW), 0, s, p);
       break;
     case kStage2:
-      hipLaunchKernelGGL((k_rhs3d<T, kStage2>), dim3(nb), dim3(64), 0, s, p);
+      hipLaunchKernelGGL((k_rhs3d<T, kStage2>), dim3(nb), dim3(64 * kGW), 0, s, p);
       break;
     default:
       return hipErrorInvalidValue;
@@ -724,6 +940,15 @@ hipError_t cfl_t(const dg_mesh* m, const void* U, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt, hipStream_t s);
+
+// Row-waves of one stage launch (one partial CFL minimum each), for the
+// mesh's tiling and for the finest one (one plane per row-wave).
+int stage_waves3(const dg_mesh* m) {
+  return m->c3.tiles_x * ((m->c3.ny + kGW - 1) / kGW) * kGW * m->c3.tiles_z;
+}
+int64_t max_stage_waves3(const dg_mesh* m) {
+  return (int64_t)m->c3.tiles_x * ((m->c3.ny + kGW - 1) / kGW) * kGW * m->c3.nz;
+}
 
 // Stage dispatch for 3D MHD.  The limiter runs as its own pass into the
 // workspace (ws_a holds Pi(U) of stage 1 for the stage-2 combination, ws_b
@@ -767,7 +992,7 @@ hipError_t launch_cart3d(const dg_mesh* m, int mode, const void* in, const void*
       }
       if (e == hipSuccess) e = rhs(kStage2, b, ua, out, dt_next != nullptr);
       if (e == hipSuccess && dt_next) {
-        const int nt = m->c3.tiles_x * m->c3.ny * m->c3.tiles_z;
+        const int nt = stage_waves3(m);
         e = launch_min_finalize(m->dtpart, nt, cfl, dt_next, s);
       }
       return e;

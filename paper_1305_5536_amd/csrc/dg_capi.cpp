@@ -70,6 +70,7 @@ hipError_t launch_mhd2d_cfl(const dg_mesh* m, const void* U, double cfl, double*
                             hipStream_t s);
 hipError_t launch_cart3d_cfl(const dg_mesh* m, const void* U, double cfl, double* dt_dev,
                              hipStream_t s);
+int64_t max_stage_waves3(const dg_mesh* m);
 
 // Rows (2D) or planes (3D) marched by one wave.  Chosen so a launch has
 // several waves per SIMD on 256 CUs; an explicit override comes from the
@@ -462,11 +463,11 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
   if (e == hipSuccess) e = hipMemset(m->status, 0, sizeof(int));
   // partial minima: one per wave of the fused stage, or one per 64 cells of
   // the stand-alone CFL kernel (whole 256-thread blocks write)
-  // (the finest tiling, one row per wave, has at most ncells/60 + rows waves;
-  // ncells/56 + rows for the fused 2D step)
+  // (the finest 2D tiling, one row per wave, has at most ncells/60 + rows
+  // waves, ncells/56 + rows for the fused step; 3D: one plane per row-wave)
   if (m->kind == 0)
-    nwaves = std::max<int64_t>(nwaves, (m->ncells + 55) / 56 +
-                                           (m->dim == 2 ? m->c2.ny : m->c3.ny * m->c3.nz));
+    nwaves = std::max<int64_t>(nwaves, m->dim == 2 ? (m->ncells + 55) / 56 + m->c2.ny
+                                                   : max_stage_waves3(m));
   m->ndtpart = (int)std::max<int64_t>(nwaves, 4 * ((m->ncells + 255) / 256));
   if (e == hipSuccess) e = hipMalloc(&m->dtpart, sizeof(double) * m->ndtpart);
 

@@ -60,7 +60,7 @@ def field_errors(A, B, n, lo, hi, U=None):
     return out
 
 
-SHAPES = [(8, 6, 5), (70, 3, 4), (1, 2, 3), (5, 1, 1), (130, 2, 2)]
+SHAPES = [(8, 6, 5), (70, 3, 4), (1, 2, 3), (5, 1, 1), (130, 2, 2), (6, 5, 4), (9, 9, 3)]
 
 
 @pytest.mark.parametrize("n", SHAPES)
