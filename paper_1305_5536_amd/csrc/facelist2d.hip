@@ -26,8 +26,11 @@
 //      the slots at a time;
 //   3. each cell gathers its incidences from that table (a segmented
 //      reduction, no atomics);
-//   4. the volume term, M^-1 and the RK combination (stage 2 limits U^n of its
-//      own cell for the combination from the neighbours' means in HBM).
+//   4. the volume term, M^-1 and the RK combination (stage 2 takes Pi(U^n),
+//      which stage 1 wrote, for the combination).
+// Loads of later phases that depend on nothing the block computes (incidence
+// ranges and entries, geometry, Pi(U^n), the first pass's slots) are issued
+// before the first barrier, so that their latency overlaps phase 0.
 // A stand-alone limiter kernel (k_fl_lim) serves dg_limit.  The discrete
 // adjoint of a step (k_adjfl_L, k_adjfl_lim) gathers over the global incidence
 // lists, one thread per cell.
@@ -217,25 +220,62 @@ __device__ __forceinline__ T psi_of(T d, T phi, T hi, T lo) {
 // their loads in flight; padding entries repeat the cell itself (no change to
 // a bound, psi = 1).
 constexpr int kInc = 4;
+constexpr int kPre = 2 * kInc;  // incidences of a cell loaded ahead (two batches)
+
+// Incidence i's entries of the block-local CSR for the batch starting at b0
+// (padding repeats the batch's first entry, a batch past the end the cell's
+// first, so every index stays inside the cell's list).  Only the entries are
+// loaded ahead; the offsets of the alpha pass are loaded where they are used,
+// with nothing they wait on.
+__device__ __forceinline__ int batch_index(int b0, int u, int i0, int i1) {
+  return b0 + u < i1 ? b0 + u : (b0 < i1 ? b0 : i0);
+}
+
+struct IncPre {  // a cell's first kPre incidences, loaded before the block's first barrier
+  int inc[kPre];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_inc_pre(const PF<T>& p, int i0, int i1, IncPre& a) {
+#pragma unroll
+  for (int u = 0; u < kPre; ++u)
+    a.inc[u] = p.cell_inc[batch_index(i0 + (u / kInc) * kInc, u % kInc, i0, i1)];
+}
+
 template <typename T>
 __device__ __forceinline__ void limit_block_cell(const PF<T>& p, int i0, int i1, int self,
-                                                 const T (*m)[kLocal], T* q) {
+                                                 const T (*m)[kLocal], T* q,
+                                                 const IncPre& pre) {
   T hi[4], lo[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
   T alpha[4] = {T(1), T(1), T(1), T(1)};
-  for (int b0 = i0; b0 < i1; b0 += kInc) {
+  auto bound = [&](int nbu) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const T mm = m[3 * v][nbu];
+      hi[v] = fmax(hi[v], mm);
+      lo[v] = fmin(lo[v], mm);
+    }
+  };
+  auto limit_by = [&](T rx, T ry) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      alpha[v] = fmin(alpha[v], psi_of(q[3 * v + 1] * rx + q[3 * v + 2] * ry, q[3 * v],
+                                       hi[v], lo[v]));
+  };
+  // batches of kInc in incidence order, the first two from registers
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int b0 = i0 + (u / kInc) * kInc;
+    if (b0 < i1) bound(b0 + u % kInc < i1 ? (pre.inc[u] >> 16) : self);
+  }
+  for (int b0 = i0 + kPre; b0 < i1; b0 += kInc) {
     int nb[kInc];
 #pragma unroll
     for (int u = 0; u < kInc; ++u) nb[u] = b0 + u < i1 ? (p.cell_inc[b0 + u] >> 16) : self;
 #pragma unroll
-    for (int u = 0; u < kInc; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T mm = m[3 * v][nb[u]];
-        hi[v] = fmax(hi[v], mm);
-        lo[v] = fmin(lo[v], mm);
-      }
+    for (int u = 0; u < kInc; ++u) bound(nb[u]);
   }
   for (int b0 = i0; b0 < i1; b0 += kInc) {
     T rx[kInc], ry[kInc];
@@ -246,11 +286,7 @@ __device__ __forceinline__ void limit_block_cell(const PF<T>& p, int i0, int i1,
       ry[u] = p.inc_rf[2 * (size_t)i + 1];
     }
 #pragma unroll
-    for (int u = 0; u < kInc; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        alpha[v] = fmin(alpha[v], psi_of(q[3 * v + 1] * rx[u] + q[3 * v + 2] * ry[u], q[3 * v],
-                                         hi[v], lo[v]));
+    for (int u = 0; u < kInc; ++u) limit_by(rx[u], ry[u]);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -261,47 +297,68 @@ __device__ __forceinline__ void limit_block_cell(const PF<T>& p, int i0, int i1,
 
 // The same limiter for a cell outside the block (a halo cell) from the global
 // face lists: neighbour means gathered from `U`, eight incidences at a time
-// with all their loads in flight (padding repeats the cell itself).
+// with all their loads in flight (padding repeats the cell itself).  The
+// cell's incidence range and first eight neighbours come preloaded.
+constexpr int kHB = 8;
+struct HaloPre {
+  int i0, i1;
+  int nb[kHB];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_halo_pre(const PF<T>& p, int e, HaloPre& a) {
+  a.i0 = p.lim_inc0[e];
+  a.i1 = p.lim_inc0[e + 1];
+#pragma unroll
+  for (int u = 0; u < kHB; ++u) a.nb[u] = a.i0 + u < a.i1 ? p.lim_nbr[a.i0 + u] : e;
+}
+
 template <typename T>
 __device__ __forceinline__ void limit_global_cell(const PF<T>& p, const T* __restrict__ U, int e,
-                                                  T* q) {
-  constexpr int kB = 8;
+                                                  T* q, const HaloPre& pre) {
   T hi[4], lo[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) hi[v] = lo[v] = q[3 * v];
-  const int i0 = p.lim_inc0[e], i1 = p.lim_inc0[e + 1];
-  for (int b0 = i0; b0 < i1; b0 += kB) {
-    int nb[kB];
+  const int i0 = pre.i0, i1 = pre.i1;
+  auto bounds = [&](const int* nb) {
+    T m[kHB][4];
 #pragma unroll
-    for (int u = 0; u < kB; ++u) nb[u] = b0 + u < i1 ? p.lim_nbr[b0 + u] : e;
-    T m[kB][4];
-#pragma unroll
-    for (int u = 0; u < kB; ++u)
+    for (int u = 0; u < kHB; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) m[u][v] = U[(3 * v) * p.nc + nb[u]];
 #pragma unroll
-    for (int u = 0; u < kB; ++u)
+    for (int u = 0; u < kHB; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         hi[v] = fmax(hi[v], m[u][v]);
         lo[v] = fmin(lo[v], m[u][v]);
       }
-  }
+  };
   T alpha[4] = {T(1), T(1), T(1), T(1)};
-  for (int b0 = i0; b0 < i1; b0 += kB) {
-    T rx[kB], ry[kB];
+  auto limit_by = [&](const T* rx, const T* ry) {
 #pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      const int i = b0 + u < i1 ? b0 + u : b0;
-      rx[u] = p.lim_geo[2 * i];
-      ry[u] = p.lim_geo[2 * i + 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kB; ++u)
+    for (int u = 0; u < kHB; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         alpha[v] = fmin(alpha[v], psi_of(q[3 * v + 1] * rx[u] + q[3 * v + 2] * ry[u], q[3 * v],
                                          hi[v], lo[v]));
+  };
+  if (i0 < i1) bounds(pre.nb);
+  for (int b0 = i0 + kHB; b0 < i1; b0 += kHB) {
+    int nb[kHB];
+#pragma unroll
+    for (int u = 0; u < kHB; ++u) nb[u] = b0 + u < i1 ? p.lim_nbr[b0 + u] : e;
+    bounds(nb);
+  }
+  for (int b0 = i0; b0 < i1; b0 += kHB) {
+    T rx[kHB], ry[kHB];
+#pragma unroll
+    for (int u = 0; u < kHB; ++u) {
+      const int i = b0 + u < i1 ? b0 + u : b0;
+      rx[u] = p.lim_geo[2 * i];
+      ry[u] = p.lim_geo[2 * i + 1];
+    }
+    limit_by(rx, ry);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -323,6 +380,48 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
   const int s0 = p.blk_slot0[b], nslot = p.blk_slot0[b + 1] - s0;
   const int nc = p.nc;
   bool bad = false;
+  const int e = c0 + tid;
+  // Loads that later phases need, issued before the first barrier so that
+  // their latency overlaps phase 0 (the LDS sets the occupancy, two
+  // workgroups per CU, so these registers cost none): the cell's incidence
+  // range, first incidences, geometry and (stage 2) Pi(U^n) row; the halo
+  // cell's first neighbours; this thread's slots of the first flux pass.
+  int i0 = 0, i1 = 0;
+  T cg[8], ua[12];
+  IncPre ipre;
+  HaloPre hpre;
+  int f0 = 0, f1 = 0;  // stage 2's CFL bound: the cell's global incidence range
+  if (tid < nown) {
+    i0 = p.cell_inc0[e];
+    i1 = p.cell_inc0[e + 1];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cg[k] = p.cell_geo[8 * (size_t)e + k];
+    if (MODE == kStage2) {
+      load12(p.ua, nc, e, ua);
+      if (p.dtpart) {
+        f0 = p.lim_inc0[e];
+        f1 = p.lim_inc0[e + 1];
+      }
+    }
+  }
+  int hg = 0;
+  if (LIM && tid < nhalo) {
+    hg = p.halo_cell[h0 + tid];
+    load_halo_pre(p, hg, hpre);
+  }
+  if (LIM && tid < nown) load_inc_pre(p, i0, i1, ipre);
+  constexpr int kSP = kHalf / kBlock;  // slots per thread and flux pass
+  int slr[kSP];
+  T sgeo[kSP][7];
+#pragma unroll
+  for (int j = 0; j < kSP; ++j) {
+    const int sl = tid + j * kBlock;
+    if (sl < min(nslot, kHalf)) {
+      slr[j] = p.slot_lr[s0 + sl];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) sgeo[j][k] = p.slot_geo[8 * (size_t)(s0 + sl) + k];
+    }
+  }
   // 0. raw coefficients of the block's cells and its halo
   for (int i = tid; i < nown + nhalo; i += kBlock) {
     const int g = i < nown ? c0 + i : p.halo_cell[h0 + i - nown];
@@ -331,25 +430,20 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
   }
   __syncthreads();
   // 1. limit on read (the limiter reads only means; only gradients change)
-  const int e = c0 + tid;
   T q[12];
-  int i0 = 0, i1 = 0;
   if (tid < nown) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) q[k] = cU[k][tid];
-    i0 = p.cell_inc0[e];
-    i1 = p.cell_inc0[e + 1];
   }
   if (LIM) {
     T qh[12];
     if (tid < nhalo) {
-      const int g = p.halo_cell[h0 + tid];
 #pragma unroll
       for (int k = 0; k < 12; ++k) qh[k] = cU[k][nown + tid];
-      limit_global_cell(p, p.in, g, qh);
+      limit_global_cell(p, p.in, hg, qh, hpre);
     }
     if (tid < nown) {
-      limit_block_cell(p, i0, i1, tid, cU, q);
+      limit_block_cell(p, i0, i1, tid, cU, q, ipre);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         cU[3 * v + 1][tid] = q[3 * v + 1];
@@ -379,10 +473,22 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
   int ii = i0;
   for (int sa = 0; sa < nslot; sa += kHalf) {
     const int sb = min(nslot, sa + kHalf);
-    for (int sl = sa + tid; sl < sb; sl += kBlock) {
-      const int lr = p.slot_lr[s0 + sl];
+#pragma unroll
+    for (int j = 0; j < kSP; ++j) {
+      const int sl = sa + tid + j * kBlock;
+      if (sl >= sb) break;
+      int lr;
+      T g[7];
+      if (sa == 0) {
+        lr = slr[j];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) g[k] = sgeo[j][k];
+      } else {
+        lr = p.slot_lr[s0 + sl];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) g[k] = p.slot_geo[8 * (size_t)(s0 + sl) + k];
+      }
       const int L = lr & 0xffff, R = lr >> 16;
-      const T* g = p.slot_geo + 8 * (size_t)(s0 + sl);
       const T nx = g[0], ny = g[1], A = g[2], fx = g[3], fy = g[4], dx = g[5], dy = g[6];
       // Gauss points x_f -+ A/(2 sqrt 3) t, t = (-n_y, n_x), from L's centroid
       const T o = T(0.5) * A * is3;
@@ -459,7 +565,6 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
   // 4. volume term, M^-1, RK combination
   double dtmin = 1e300;
   if (tid < nown) {
-    const T* cg = p.cell_geo + 8 * (size_t)e;
     const T iV = cg[0];
     const T m00 = cg[1], m01 = cg[2], m11 = cg[3];
     // volume term: 4 principal-axis points, weights V/4 (the 1/V of the
@@ -506,10 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
       if (MODE == kStage2) {
         // ua: Pi(U^n) (written by stage 1 of the same U^n, or by the
         // stand-alone limiter), U^n itself without a limiter
-        T a[12];
-        load12(p.ua, nc, e, a);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = T(0.5) * (a[k] + o[k]);
+        for (int k = 0; k < 12; ++k) o[k] = T(0.5) * (ua[k] + o[k]);
       }
     }
 #pragma unroll
@@ -520,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_fl_step(PF<T> p) {
       const double pr = ((double)p.gamma - 1.0) * (o[9] - 0.5 * r * (ux * ux + uy * uy));
       const double cs = sqrt((double)p.gamma * pr * ir);
       double s = cs * (double)p.perim[e];
-      for (int i = p.lim_inc0[e]; i < p.lim_inc0[e + 1]; ++i)
+      for (int i = f0; i < f1; ++i)
         s += fabs(ux * (double)p.lim_an[2 * i] + uy * (double)p.lim_an[2 * i + 1]);
       dtmin = 2.0 / ((double)iV * s);
     }
