@@ -103,7 +103,7 @@ def parse():
     # CPU baseline sized to about 10-30 s of host work)
     dflt = {"c1": (64, 100, 10, 8000), "c2": (2048, 200, 10, 16), "c3": (256, 50, 3, 12),
             "c4": (1000000, 100, 5, 50), "c5": (256, 200, 20, 800),
-            "ot": (512, 1000, 20, 16), "moving": (262144, 200, 10, 3)}[a.config]
+            "ot": (512, 200, 20, 16), "moving": (262144, 200, 10, 3)}[a.config]
     a.n = a.n or dflt[0]
     a.steps = a.steps if a.steps is not None else dflt[1]
     a.warmup = a.warmup if a.warmup is not None else dflt[2]

@@ -578,11 +578,18 @@ void k_mhd2d(P2M<T> p) {
       add_point<T, 0>(acc, F, s, T(-1), p);
     }
     // the row above (limited on read: its y-neighbours are this row and the
-    // row above it); the loads are in flight during the volume term
+    // row above it); the loads are in flight during the volume term.  In FP64
+    // stage 2 issues its Pi(U^n) row here too: loaded right before the
+    // combination, nothing would hide its latency at one wave per SIMD (FP32
+    // runs three waves per SIMD within 168 registers, so it loads it late)
+    constexpr bool kEarlyUa = sizeof(T) == 8;
+    const int e = y * nx + col;
     Q2<T> nb;
     load_q(p.in, nc, yw(y + 1) * nx + col, nb);
     T mN2[8];
     if (LIM) load_means(p.in, nc, yw(y + 2) * nx + col, mN2);
+    Q2<T> ua;
+    if (MODE == kStage2 && kEarlyUa) load_q(p.ua, nc, e, ua);
     {
       Q2<T> c;
       lds_get(row, lane, c);
@@ -613,7 +620,6 @@ void k_mhd2d(P2M<T> p) {
     }
     Q2<T> d;
     finish(acc, p, d);
-    const int e = y * nx + col;
     if (MODE != kRhs) {
       Q2<T> c;
       lds_get(row, lane, c);
@@ -630,8 +636,7 @@ void k_mhd2d(P2M<T> p) {
       for (int j = 0; j < 5; ++j) d.a[j] = fma(dt, d.a[j], c.a[j]);
     }
     if (MODE == kStage2) {
-      Q2<T> ua;
-      load_q(p.ua, nc, e, ua);
+      if (!kEarlyUa) load_q(p.ua, nc, e, ua);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         d.m[v] = T(0.5) * (ua.m[v] + d.m[v]);
