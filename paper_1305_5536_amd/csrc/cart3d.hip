@@ -403,13 +403,13 @@ __device__ __forceinline__ void add_face(Acc<T>& a, const FaceSums<T>& f, T sigm
   }
 }
 
-// Volume term over the 2x2x2 Gauss points.
+// Volume term over the 2x2x2 Gauss points g0 .. g1-1 (of 8).
 template <typename T>
 __device__ __forceinline__ void add_volume(Acc<T>& a, const Poly<T>& q, const P3<T>& p,
-                                           bool& bad) {
+                                           bool& bad, int g0 = 0, int g1 = 8) {
   const T gm1 = p.gamma - T(1);
 #pragma unroll 1
-  for (int g = 0; g < 8; ++g) {
+  for (int g = g0; g < g1; ++g) {
     const T o[3] = {(g & 4) ? p.q[0] : -p.q[0], (g & 2) ? p.q[1] : -p.q[1],
                     (g & 1) ? p.q[2] : -p.q[2]};
     T u[5], B[3];
@@ -734,9 +734,11 @@ __global__ __launch_bounds__(256) void k_rhs3d(P3<T> p) {
     if (real) {
       if (w == 0) load_poly(p.in, nc, idx(yS, z), nb);
       {
+        // half the volume points cover the load of the row below (w = 0),
+        // the other half, after the barrier, the load of plane z+1
         Poly<T> c;
         lds_get_poly(sm.cur[w], lane, c);
-        add_volume(acc, c, p, bad);
+        add_volume(acc, c, p, bad, 0, 4);
       }
       if (w > 0) lds_get_poly(sm.cur[w - 1], lane, nb);
       Poly<T> c;
@@ -774,6 +776,11 @@ __global__ __launch_bounds__(256) void k_rhs3d(P3<T> p) {
         }
       }
       add_face<T, 1>(acc, fy, T(-1), p);
+    }
+    {
+      Poly<T> c;
+      lds_get_poly(sm.cur[w], lane, c);
+      add_volume(acc, c, p, bad, 4, 8);
     }
     {
       Poly<T> c;
