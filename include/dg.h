@@ -283,12 +283,18 @@ dg_status dg_adjoint_step(dg_mesh_t mesh, const void* U, const void* V1, double 
                           const double* dt_dev, const void* lam_np1, void* lam_n, void* stream);
 
 /* Flags of dg_run: capture the launch sequence into a hipGraph; step with
- * dg_step_mh (MUSCL-Hancock, one kernel per step) instead of SSP-RK2. */
+ * dg_step_mh (MUSCL-Hancock, one kernel per step) instead of SSP-RK2; step
+ * SSP-RK2 with the dg_stage1/dg_stage2 pair even where dg_step has a fused
+ * one-kernel step (the results then equal those of the stage calls and of a
+ * batch holding the mesh, bit for bit; on small meshes the pair is also the
+ * faster path). */
 #define DG_RUN_GRAPH 1
 #define DG_RUN_MUSCL_HANCOCK 2
+#define DG_RUN_TWO_STAGE 4
 
 /* nsteps SSP-RK2 steps (dg_step's kernels: the fused step, or the
- * dg_stage1/dg_stage2 pair when v1_keep asks for the stage-1 outputs) from U_in
+ * dg_stage1/dg_stage2 pair when v1_keep asks for the stage-1 outputs or
+ * flags has DG_RUN_TWO_STAGE) from U_in
  * to U_out, with per-step (per-instance) step sizes in the device array
  * dt_hist, nd = dg_ninst doubles per step:
  *   cfl > 0: adaptive.  dt_hist[0..nd) = the CFL step of U_in (dg_cfl_dt) and

@@ -18,6 +18,7 @@ DG_FLUX_HLL, DG_FLUX_HLLD, DG_FLUX_EXACT = 0, 1, 2
 DG_LIMITER_NONE, DG_LIMITER_MINMOD, DG_LIMITER_WENO = 0, 1, 2
 DG_RUN_GRAPH = 1
 DG_RUN_MUSCL_HANCOCK = 2
+DG_RUN_TWO_STAGE = 4
 
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ENOMEM", 3: "DG_EHIP", 4: "DG_EUNSUPPORTED",
                 5: "DG_ENONPHYSICAL", 6: "DG_EMESH"}

@@ -749,8 +749,11 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
   if (ckpt_every < 0 || (ckpt_every > 0 && nsteps > ckpt_every && !ckpt))
     return einval("dg_run: checkpoints need ckpt_every >= 0 and a ckpt array");
   if (nsteps == 1 && U_out == U_in) return einval("dg_run: U_out may equal U_in only for >= 2 steps");
-  if (flags & ~(DG_RUN_GRAPH | DG_RUN_MUSCL_HANCOCK)) return einval("dg_run: unknown flag");
+  if (flags & ~(DG_RUN_GRAPH | DG_RUN_MUSCL_HANCOCK | DG_RUN_TWO_STAGE))
+    return einval("dg_run: unknown flag");
   const bool mh = (flags & DG_RUN_MUSCL_HANCOCK) != 0;
+  const bool two_stage = (flags & DG_RUN_TWO_STAGE) != 0;
+  if (mh && two_stage) return einval("dg_run: DG_RUN_TWO_STAGE is a flag of the SSP-RK2 step");
   if (m->kind == 3) {
     set_error("dg_run: not built for moving meshes (step them with dg_step_mh)");
     return DG_EUNSUPPORTED;
@@ -793,7 +796,7 @@ dg_status dg_run(dg_mesh_t m, const void* U_in, void* U_out, int nsteps, double 
         cur = out;
         continue;
       }
-      if (!v1_keep && fused_step(m)) {
+      if (!v1_keep && !two_stage && fused_step(m)) {
         dg_status st = dispatch(m, kStep, cur, nullptr, out, dtn, 0.0, q, cfl,
                                 cfl > 0 ? dt_hist + (int64_t)(n + 1) * nd : nullptr);
         if (st != DG_OK) return st;

@@ -261,11 +261,12 @@ class Solver:
     def run(self, U: torch.Tensor, nsteps: int, cfl: float = 0.0,
             dt_hist: torch.Tensor | None = None, out: torch.Tensor | None = None,
             ckpt_every: int = 0, ckpts=None, v1_keep=None, graph: bool = True,
-            integrator: str = "rk2"):
+            integrator: str = "rk2", two_stage: bool = False):
         """nsteps steps from U (dg_run).  cfl > 0: adaptive step sizes, written
         to dt_hist ((nsteps + 1) x ninst); cfl = 0: dt_hist (nsteps x ninst) is
-        read.  integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock).  Returns
-        (U_out, dt_hist)."""
+        read.  integrator: "rk2" (SSP-RK2) or "mh" (MUSCL-Hancock).  two_stage:
+        step with the stage-1/stage-2 kernel pair where a fused step kernel
+        exists.  Returns (U_out, dt_hist)."""
         if integrator not in ("rk2", "mh"):
             raise ValueError("integrator must be 'rk2' or 'mh'")
         self._check_state(U)
@@ -296,7 +297,8 @@ class Solver:
         C.check(C.lib().dg_run(self._h, _ptr(U), _ptr(out), int(nsteps), float(cfl),
                                _ptr(dt_hist), int(ckpt_every), ck, v1,
                                (C.DG_RUN_GRAPH if graph else 0) |
-                               (C.DG_RUN_MUSCL_HANCOCK if integrator == "mh" else 0),
+                               (C.DG_RUN_MUSCL_HANCOCK if integrator == "mh" else 0) |
+                               (C.DG_RUN_TWO_STAGE if two_stage else 0),
                                _stream()), "dg_run")
         return out, dt_hist
 

@@ -376,6 +376,36 @@ def test_fused_step_reports_nonphysical_state(torch_cuda):
         s.check()
 
 
+def test_run_two_stage_flag_steps_with_the_stage_pair(torch_cuda):
+    """dg_run with DG_RUN_TWO_STAGE steps with the stage-1/stage-2 kernels: its
+    states and step sizes equal those of stage1 + stage2 called one at a time
+    and of the run that keeps the stage-1 outputs, bit for bit, graph-captured
+    or not; the flag is refused together with MUSCL-Hancock."""
+    from paper_1305_5536_amd import capi as C
+    n, lo, hi = (70, 33), (0.0, 0.0), (1.0, 1.0)
+    U0 = W.random_p1_state(n, lo, hi, G53, seed=35, amp=0.3)
+    s = _solver(n, lo, hi, G53)
+    U = s.to_device(U0)
+    dt = s.cfl_dt(U, 0.3)
+    A, V1, B = U.clone(), s.empty(), s.empty()
+    for _ in range(5):
+        s.stage1(A, dt, V1)
+        s.stage2(A, V1, dt, B, cfl=0.3, dt_next=dt)
+        A, B = B, A
+    v1 = [s.empty() for _ in range(5)]
+    kept, hist_kept = s.run(U, 5, cfl=0.3, v1_keep=v1, graph=False)
+    for graph in (False, True, True):
+        out, hist = s.run(U, 5, cfl=0.3, graph=graph, two_stage=True)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(out, A), graph
+        assert torch_cuda.equal(out, kept), graph
+        assert torch_cuda.equal(hist, hist_kept), graph
+        assert hist[5].item() == dt.item(), graph
+    with pytest.raises(C.DGError):
+        s.run(U, 2, cfl=0.3, graph=False, two_stage=True, integrator="mh")
+    s.check()
+
+
 def test_run_uses_the_fused_step(torch_cuda):
     """dg_run on a 2D Euler mesh steps with the fused kernel (graph-captured,
     replayed twice) and equals dg_step_cfl one call at a time bit for bit, and
