@@ -94,7 +94,8 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
 // of R rows costs about R + 1.85 stage-2 row times (its four extra stage-1
 // rows are a little cheaper than stage-2 rows), and the waves run in rounds of
 // one per SIMD (FP64: one wave per SIMD by registers; FP32: two), so R in
-// [8, 64] minimises rounds x (R + 1.85): the last round should be nearly full.
+// [8, 128] minimises rounds x (R + 1.85): the last round should be nearly full
+// (2048^2: FP64 76 rows, one round of 999 waves; FP32 38 rows).
 static int default_step_rows(int64_t ntiles_x, int64_t nrows, bool f64) {
   const char* env = std::getenv("DG_STEP_ROWS");
   int64_t rows = env ? std::atoi(env) : 0;
@@ -108,7 +109,7 @@ static int default_step_rows(int64_t ntiles_x, int64_t nrows, bool f64) {
     }
     const int64_t slots = (int64_t)cus * 4 * (f64 ? 1 : 2);
     double best = 1e300;
-    for (int64_t r = 8; r <= 64; ++r) {
+    for (int64_t r = 8; r <= 128; ++r) {
       const int64_t rr = std::min(r, nrows);
       const int64_t waves = ntiles_x * ((nrows + rr - 1) / rr);
       const double cost = (double)((waves + slots - 1) / slots) * ((double)rr + 1.85);
