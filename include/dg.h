@@ -108,7 +108,8 @@ typedef struct {
  *   face_centroid[nfaces][2] (edge midpoint, in L's periodic frame),
  *   face_shift[nfaces][2] in {-1, 0, 1}: R's image next to L sits at
  *     centroid[R] + shift * box.
- *   Every cell must be closed: sum over its faces of A n = 0 (checked).
+ *   Every cell must have at least one face and be closed: sum over its faces of
+ *   A n = 0 (both checked).
  * kind 2: a batch of ninst periodic 2D Cartesian Euler instances (dim = 2):
  *   inst_n[ninst][2] = (nx, ny), inst_box[ninst][4] = (lo_x, lo_y, hi_x, hi_y),
  *   host arrays copied at create.

@@ -1113,6 +1113,10 @@ dg_status facelist_create(dg_mesh* m, const dg_mesh_desc* d) {
                 " needs V > 0 and positive-definite moments");
       return DG_EINVAL;
     }
+    if (!(perim[e] > 0)) {
+      set_error("dg_mesh_create: cell " + std::to_string(e) + " has no faces");
+      return DG_EINVAL;
+    }
     if (std::hypot(closure[2 * e], closure[2 * e + 1]) > 1e-9 * perim[e]) {
       set_error("dg_mesh_create: cell " + std::to_string(e) + " is not closed (sum A n != 0)");
       return DG_EINVAL;

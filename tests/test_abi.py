@@ -100,3 +100,42 @@ def test_oversized_meshes_rejected_before_any_device_call():
     d.ncells, d.nfaces = 200_000_000, 3
     assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
         capi.DG_EINVAL
+
+
+def test_facelist_cell_without_faces_rejected():
+    """A face list in which a cell has no faces (no tessellation has one) is
+    refused with DG_EINVAL during validation, before any device call: the
+    kernels take every cell's incidence list as non-empty."""
+    import numpy as np
+
+    from paper_1305_5536_amd import capi
+    from workloads.voronoi import periodic_voronoi
+    lib = capi.lib()
+    m = periodic_voronoi(30, seed=11, lloyd=1)
+    nc = len(m["cell_volume"])
+    arrs = {
+        "cell_volume": np.append(np.asarray(m["cell_volume"], np.float64), 1e-3),
+        "cell_centroid": np.append(np.asarray(m["cell_centroid"], np.float64).reshape(-1),
+                                   [0.5, 0.5]),
+        "cell_moments": np.append(np.asarray(m["cell_moments"], np.float64).reshape(-1),
+                                  [1e-7, 0.0, 1e-7]),
+        "face_area": np.ascontiguousarray(m["face_area"], np.float64),
+        "face_normal": np.ascontiguousarray(m["face_normal"], np.float64),
+        "face_centroid": np.ascontiguousarray(m["face_centroid"], np.float64),
+    }
+    fc = np.ascontiguousarray(m["face_cells"], np.int32)
+    fs = np.ascontiguousarray(m["face_shift"], np.int8)
+    d = capi.dg_mesh_desc()
+    d.dim, d.kind = 2, 1
+    for k, a in arrs.items():
+        setattr(d, k, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    d.face_cells = fc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.face_shift = fs.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+    d.ncells, d.nfaces = nc + 1, len(arrs["face_area"])
+    d.box[0], d.box[1] = float(m["box"][0]), float(m["box"][1])
+    cfg = capi.dg_config(capi.DG_EULER, capi.DG_FP64, capi.DG_FLUX_HLL, 1, 1.4)
+    out = ctypes.c_void_p()
+    assert lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out)) == \
+        capi.DG_EINVAL
+    assert f"cell {nc} has no faces".encode() in lib.dg_last_error()
+    assert not out.value
