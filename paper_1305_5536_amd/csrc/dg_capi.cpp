@@ -90,6 +90,38 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
+// Rows per wave of the 2D Euler stage kernels and the MUSCL-Hancock step.
+// FP64: stage 1 runs two waves per SIMD, stage 2 and the MUSCL-Hancock kernel
+// one (registers); a wave of R rows costs about R + 2 row times, so R in
+// [4, 128] minimises (rounds at two waves per SIMD + rounds at one) x (R + 2)
+// (2048^2: 36 rows, 1995 waves, one round of stage 1 and two of stage 2).
+// FP32 runs several waves per SIMD, which hide each other's latency: the
+// generic rule (about 4096 waves).  DG_TILE_ROWS overrides both.
+static int default_rows_euler2d(int64_t ntiles_x, int64_t nrows, bool f64) {
+  if (!f64 || std::getenv("DG_TILE_ROWS")) return default_rows(ntiles_x, nrows);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  const int64_t one = (int64_t)cus * 4;
+  double best = 1e300;
+  int64_t rows = 4;
+  for (int64_t r = 4; r <= 128; ++r) {
+    const int64_t rr = std::min(r, nrows);
+    const int64_t waves = ntiles_x * ((nrows + rr - 1) / rr);
+    const int64_t rounds = (waves + 2 * one - 1) / (2 * one) + (waves + one - 1) / one;
+    const double cost = (double)rounds * ((double)rr + 2.0);
+    if (cost < best - 1e-9) {
+      best = cost;
+      rows = rr;
+    }
+  }
+  return (int)std::min<int64_t>(rows, nrows);
+}
+
 // Rows per wave of the fused 2D Euler step (DG_STEP_ROWS overrides).  A wave
 // of R rows costs about R + 1.85 stage-2 row times (its four extra stage-1
 // rows are a little cheaper than stage-2 rows), and the waves run in rounds of
@@ -387,7 +419,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
     m->c2.tiles_x = (int)((d->n[0] + 59) / 60);  // 60 interior columns per wave
     m->c2.rows_per_tile =
         mhd ? default_rows_mhd2d(m->c2.tiles_x, d->n[1], cfg->precision == DG_FP64)
-            : default_rows(m->c2.tiles_x, d->n[1]);
+            : default_rows_euler2d(m->c2.tiles_x, d->n[1], cfg->precision == DG_FP64);
     m->c2.tiles_y = (int)((d->n[1] + m->c2.rows_per_tile - 1) / m->c2.rows_per_tile);
     nwaves = (int64_t)m->c2.tiles_x * m->c2.tiles_y;
     m->c2.step_tiles_x = (int)((d->n[0] + 55) / 56);  // 56 output columns per wave
@@ -946,7 +978,8 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
     int r = rows ? std::min(rows, m->c2.ny)
                  : (m->cfg.physics == DG_MHD ? default_rows_mhd2d(m->c2.tiles_x, m->c2.ny,
                                                                   m->cfg.precision == DG_FP64)
-                                             : default_rows(m->c2.tiles_x, m->c2.ny));
+                                             : default_rows_euler2d(m->c2.tiles_x, m->c2.ny,
+                                                                    m->cfg.precision == DG_FP64));
     m->c2.rows_per_tile = r;
     m->c2.tiles_y = (m->c2.ny + r - 1) / r;
     const int rs = rows ? std::min(rows, m->c2.ny)
