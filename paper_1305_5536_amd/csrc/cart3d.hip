@@ -953,6 +953,9 @@ hipError_t launch_min_finalize(const double* part, int n, double cfl, double* dt
 int stage_waves3(const dg_mesh* m) {
   return m->c3.tiles_x * ((m->c3.ny + kGW - 1) / kGW) * kGW * m->c3.tiles_z;
 }
+// Workgroups of one z-range of the stage kernel (x-strips times groups of kGW
+// rows), for a mesh of tiles_x strips and ny rows.
+int64_t stage_groups3(int tiles_x, int ny) { return (int64_t)tiles_x * ((ny + kGW - 1) / kGW); }
 int64_t max_stage_waves3(const dg_mesh* m) {
   return (int64_t)m->c3.tiles_x * ((m->c3.ny + kGW - 1) / kGW) * kGW * m->c3.nz;
 }
