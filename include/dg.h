@@ -352,8 +352,11 @@ dg_status dg_cfl_dt_static(dg_mesh_t mesh, const void* U, double cfl, double* dt
                            void* stream);
 
 /* Launch shape of the Cartesian stage kernels: the number of rows (2D, and
- * every instance of a batch) or z-planes (3D) one wave marches through.  0
- * restores the library default.
+ * every instance of a batch) one wave marches through, or of z-planes (3D)
+ * one workgroup of four row-waves marches through.  0 restores the library
+ * default, which a positive DG_TILE_ROWS (stage kernels, batches) or
+ * DG_STEP_ROWS (fused 2D Euler step) environment variable replaces for the
+ * whole process.
  * Results do not depend on it (every face and cell is computed with the same
  * arithmetic whatever the tiling); only speed does.  Face-list meshes ignore
  * it.  Returns DG_EINVAL for a negative value. */

@@ -74,8 +74,10 @@ int64_t max_stage_waves3(const dg_mesh* m);
 int64_t stage_groups3(int tiles_x, int ny);
 
 // Rows (2D) or planes (3D) marched by one wave.  Chosen so a launch has
-// several waves per SIMD on 256 CUs; an explicit override comes from the
-// DG_TILE_ROWS environment variable (used by the autotuner).
+// several waves per SIMD on 256 CUs.  The DG_TILE_ROWS environment variable
+// overrides this and every model-based default below for the whole process
+// (launch-shape experiments; dg_set_tiling, which the autotuner uses, takes
+// precedence over both).
 static int default_rows(int64_t ntiles_x, int64_t nrows) {
   const char* env = std::getenv("DG_TILE_ROWS");
   if (env) {
@@ -197,6 +199,7 @@ static int default_step_rows(int64_t ntiles_x, int64_t nrows, bool f64) {
 // mesh, 2 to 16 rows, measured best (2048^2: 9 rows, 0.760 ms against 0.773
 // with the FP64 model's 24).
 static int default_rows_mhd2d(int64_t ntiles_x, int64_t nrows, bool f64) {
+  if (std::getenv("DG_TILE_ROWS")) return default_rows(ntiles_x, nrows);
   if (!f64) {
     int64_t rows = (ntiles_x * nrows + 8191) / 8192;
     rows = std::max<int64_t>(2, std::min<int64_t>(16, rows));

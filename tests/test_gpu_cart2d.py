@@ -290,6 +290,37 @@ def test_results_do_not_depend_on_tiling(torch_cuda):
         assert torch_cuda.equal(b, outs[0][1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tile_rows_environment_replaces_every_default(monkeypatch, torch_cuda, precision):
+    """DG_TILE_ROWS replaces the library default of every Cartesian stage
+    kernel (2D Euler, 2D MHD, 3D planes) at creation and after tiling = 0; an
+    explicit tiling still wins.  Results stay those of any other tiling."""
+    from paper_1305_5536_amd.solver import Solver, cartesian
+    monkeypatch.setenv("DG_TILE_ROWS", "7")
+    n2, n3 = (96, 40), (20, 9, 30)
+    meshes = [
+        (cartesian(n2, (0.0, 0.0), (1.0, 1.0)), "euler"),
+        (cartesian(n2, (0.0, 0.0), (1.0, 1.0)), "mhd"),
+        (cartesian(n3, (0.0,) * 3, (1.0,) * 3), "mhd"),
+    ]
+    for mesh, physics in meshes:
+        s = Solver(mesh, physics=physics, precision=precision, gamma=G53)
+        assert s.tiling == 7, (physics, mesh)
+        s.tiling = 5
+        assert s.tiling == 5
+        s.tiling = 0
+        assert s.tiling == 7
+    monkeypatch.delenv("DG_TILE_ROWS")
+    s = _solver(n2, (0.0, 0.0), (1.0, 1.0), G53, precision=precision)
+    default = s.tiling
+    s.tiling = 7
+    U = s.to_device(W.random_p1_state(n2, (0.0, 0.0), (1.0, 1.0), G53, seed=16, amp=0.2))
+    a = s.step(U, 1e-3)
+    s.tiling = 0
+    assert s.tiling == default
+    assert torch_cuda.equal(a, s.step(U, 1e-3))
+
+
 def test_autotuner_picks_a_candidate(tmp_path, monkeypatch, torch_cuda):
     from paper_1305_5536_amd.autotune import autotune
     monkeypatch.setenv("DG_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
