@@ -161,3 +161,42 @@ def test_stage2_cfl_and_determinism(oracle, torch_cuda):
     for rows in (1, 3, 7):
         s.tiling = rows
         assert torch_cuda.equal(s.step(U, dt), b)
+
+
+def uniform_mhd_state(n, lo, hi, axis, bt, rho=1.3, p=0.4):
+    """A uniform state (means only) whose field lies along ``axis`` with B_n^2 = 4 gamma p
+    (fast speed = Alfven speed on those faces) plus a transverse field bt; the
+    normal velocity is inside the fan, the transverse one arbitrary."""
+    bn = np.sqrt(4.0 * G53 * p)
+    B = np.full(3, bt)
+    B[axis] = bn
+    v = np.array([0.5, -0.4, 0.3])
+    v[axis] = 0.3 * bn / np.sqrt(rho)
+    cons = [rho, *(rho * v), p / (G53 - 1.0) + 0.5 * rho * v @ v + 0.5 * B @ B, *B]
+    U = np.zeros((31, int(np.prod(n))))
+    for k, c in zip([0, 4, 8, 12, 16, 20, 21, 22], cons):
+        U[k] = c
+    return U.reshape(-1), np.abs(v).max() + bn / np.sqrt(rho)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_degenerate_hlld_faces_keep_a_uniform_state(torch_cuda, axis, precision):
+    """On the faces normal to the field the fast and Alfven speeds coincide and
+    HLLD's star-state denominator is rounding noise (the outer transverse v and B
+    are taken there, Sec. 2.3).  A uniform state is steady: L(U) = 0 and the
+    limited step returns U, up to rounding (a missing switch gives NaN at bt = 0
+    and noise of order bt / eps at bt = 1e-9)."""
+    n, lo, hi = (9, 7, 6), (0.0,) * 3, (1.0,) * 3
+    h = 1.0 / 9
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    for bt in (0.0, 1e-9):
+        U0, c = uniform_mhd_state(n, lo, hi, axis, bt)
+        s = _solver(n, lo, hi, precision=precision)
+        U = s.to_device(U0)
+        L = s.rhs(U).double().cpu().numpy()
+        assert np.all(np.isfinite(L)), (axis, bt)
+        assert np.abs(L).max() <= tol * np.abs(U0).max() * c / h, (axis, bt, np.abs(L).max())
+        U1 = s.step(U, 1e-3).double().cpu().numpy()
+        s.check()
+        assert np.abs(U1 - U0).max() <= tol * np.abs(U0).max(), (axis, bt)

@@ -247,3 +247,36 @@ def test_unsupported_entry_points(torch_cuda):
     U = s.to_device(_state((8, 8), seed=1))
     with pytest.raises(DGError):
         s.step_mh(U, 1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_degenerate_hlld_faces_keep_a_uniform_state(torch_cuda, axis, precision):
+    """B along one axis with B_n^2 = 4 gamma p, transverse field 0 or 1e-9: on
+    those faces HLLD's star-state denominator is rounding noise (outer transverse
+    v and B taken, Sec. 2.3).  A uniform state is steady: L(U) = 0 and the
+    limited step returns U, up to rounding."""
+    n, lo, hi = (11, 9), (0.0, 0.0), (1.0, 1.0)
+    h = 1.0 / 11
+    rho, p = 1.3, 0.4
+    bn = np.sqrt(4.0 * G53 * p)
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    for bt in (0.0, 1e-9):
+        B = np.full(3, bt)
+        B[axis] = bn
+        v = np.array([0.5, -0.4, 0.3])
+        v[axis] = 0.3 * bn / np.sqrt(rho)
+        cons = [rho, *(rho * v), p / (G53 - 1.0) + 0.5 * rho * v @ v + 0.5 * B @ B, *B]
+        U0 = np.zeros((NC, n[0] * n[1]))
+        for k, v0 in zip([0, 3, 6, 9, 12, 15, 16, 17], cons):
+            U0[k] = v0
+        U0 = U0.reshape(-1)
+        c = np.abs(v).max() + bn / np.sqrt(rho)
+        s = _solver(n, lo, hi, precision=precision)
+        U = s.to_device(U0)
+        L = s.rhs(U).double().cpu().numpy()
+        assert np.all(np.isfinite(L)), (axis, bt)
+        assert np.abs(L).max() <= tol * np.abs(U0).max() * c / h, (axis, bt, np.abs(L).max())
+        U1 = s.step(U, 1e-3).double().cpu().numpy()
+        s.check()
+        assert np.abs(U1 - U0).max() <= tol * np.abs(U0).max(), (axis, bt)

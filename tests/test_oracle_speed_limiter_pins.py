@@ -13,6 +13,12 @@ common field alpha of the MHD limiter.
   S_L = min(v_nL, v_nR) - max(c_fL, c_fR) is >= 0 (reading Z4); boosting both
   states along n moves S_L through zero, and the switch must happen where the
   NumPy fast speeds put it.
+* HLLD's star states divide by rho (S - v_n)(S - S_M) - B_n^2, which vanishes
+  where the fast speed meets the Alfven speed: tangential field (near) zero and
+  B_n^2 >= gamma p (reading Z4 takes the outer transverse v and B there).  Two
+  equal states must still give the physical flux (consistency, exact in the
+  limit); a missing switch divides rounding noise by rounding noise, a switch
+  to zero transverse field loses S_L B_t.
 * The limiter (Sec. 2.5, reading Z5) gives the three field components one alpha:
   on fields that vary along one axis that alpha has the 1D closed form
   min over components of min(1, 2 min(|D+|, |D-|) / (|g| h)) (0 at a strict
@@ -219,6 +225,34 @@ def test_hlld_outer_speeds_switch_where_fast_speeds_put_them(oracle, side):
 
 
 # --------------------------------------------------- common field alpha (MHD)
+@pytest.mark.parametrize("bt", [0.0, 1e-9, 1e-7])
+def test_hlld_degenerate_star_states_keep_consistency(oracle, bt):
+    """Equal left and right states with B_n^2 > gamma p and a tangential field of
+    magnitude bt: the fast speed equals the Alfven speed up to O(bt^2), so the
+    star-state denominator is rounding noise, and the flux must still be the
+    physical one (NumPy flux, not the oracle's), finite, in every HLLD region."""
+    rng = np.random.default_rng(91)
+    for _ in range(200):
+        rho, p = rng.uniform(0.5, 2.0), rng.uniform(0.1, 1.0)
+        n = _unit(rng, 3)
+        bn = math.sqrt(G53 * p * rng.uniform(1.5, 6.0)) * rng.choice([-1.0, 1.0])
+        t = _unit(rng, 3)
+        t -= (t @ n) * n
+        t /= np.linalg.norm(t)
+        B = bn * n + bt * t
+        ca = abs(bn) / math.sqrt(rho)
+        # normal velocity inside the fan (every region of HLLD in turn), any
+        # tangential velocity
+        vn = rng.uniform(-0.95, 0.95) * ca
+        vt = rng.normal(0.0, 0.5, 3)
+        vt -= (vt @ n) * n
+        u = P.mhd_state(rho, vn * n + vt, p, B, G53)
+        F = oracle.hlld(u, u, n, G53)
+        ref = P.flux(u, n, G53, True)
+        assert np.all(np.isfinite(F))
+        assert np.allclose(F, ref, rtol=1e-12, atol=1e-13), (F - ref, bt)
+
+
 def _closed_form_alpha(phim, phi, phip, g, h):
     """1D limiter factor of one variable: the largest alpha in [0, 1] with both
     face extrapolations phi -+ alpha g h/2 inside [min, max] of the three
