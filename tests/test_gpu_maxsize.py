@@ -179,3 +179,80 @@ def test_largest_3d_mhd_mesh(oracle, torch_cuda, precision):
     # (64-cell strips), y (groups of four rows) and z (planes per workgroup)
     _run_max_case(torch_cuda, (411, 409, 412), "mhd", precision, oracle,
                   [0, 4, 8, 12, 16, 20, 21, 22])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_largest_batch(oracle, torch_cuda, precision):
+    """A batch of three uneven 2D Euler instances whose cells total just below
+    2^31 / 12 (the batch's indexing limit): per instance, every row of the CFL
+    step, of one step and of the two stages equals bit for bit the single-mesh
+    stage kernels on two rows of the same spacings."""
+    torch = torch_cuda
+    from paper_1305_5536_amd.solver import Solver, batch, cartesian
+    sizes = [(8191, 9000), (5003, 12000), (6700, 6746)]
+    total = sum(nx * ny for nx, ny in sizes)
+    assert total * 12 < LIMIT and (total + 6746) * 12 >= LIMIT
+    elem = 8 if precision == "fp64" else 4
+    need = 6.5 * 12 * total * elem
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
+    b = Solver(batch(sizes), precision=precision, gamma=G53)
+    off = [int(v) for v in b.offsets]
+    U = b.empty()
+    smalls = []
+    for i, (nx, ny) in enumerate(sizes):
+        lo, hi = (0.0, 0.0), (1.0, 2.0 / ny)
+        Us_host = W.project_cartesian(_fields(False), (nx, 2), lo, hi)
+        ss = Solver(cartesian((nx, 2), lo, hi), precision=precision, gamma=G53)
+        Us = ss.to_device(Us_host)
+        U.view(12, -1)[:, off[i]:off[i + 1]].view(12, ny, nx).copy_(
+            Us.view(12, 2, nx)[:, :1, :].expand(12, ny, nx))
+        smalls.append((ss, Us, Us_host, lo, hi))
+    print(f"max-size batch {sizes} {precision}: {total} cells x 12", flush=True)
+
+    def inst_rows_equal(big, i, ref):
+        nx, ny = sizes[i]
+        v = big.view(12, -1)[:, off[i]:off[i + 1]].view(12, ny, nx)
+        return torch.equal(v, ref.view(12, 2, nx)[:, :1, :].expand(12, ny, nx))
+
+    dtb = b.cfl_dt(U, 0.3)
+    out = b.step(U, dtb)
+    V1 = b.empty()
+    b.stage1(U, dtb, V1)
+    b.check()
+    for i, (ss, Us, Us_host, lo, hi) in enumerate(smalls):
+        dt = ss.cfl_dt(Us, 0.3)
+        assert dt.item() == dtb[i].item(), i
+        v1, ref = ss.empty(), ss.empty()
+        ss.stage1(Us, dt, v1)
+        ss.stage2(Us, v1, dt, ref)
+        ss.check()
+        assert inst_rows_equal(U, i, Us), i
+        assert inst_rows_equal(V1, i, v1), i
+        assert inst_rows_equal(out, i, ref), i
+    b.stage2(U, V1, dtb, out)
+    b.check()
+    for i, (ss, Us, Us_host, lo, hi) in enumerate(smalls):
+        dt = ss.cfl_dt(Us, 0.3)
+        v1, ref = ss.empty(), ss.empty()
+        ss.stage1(Us, dt, v1)
+        ss.stage2(Us, v1, dt, ref)
+        assert inst_rows_equal(out, i, ref), i
+    # the smallest instance's two-row mesh against the oracle
+    ss, Us, Us_host, lo, hi = smalls[2]
+    om = oracle.Mesh.cartesian((sizes[2][0], 2), lo, hi)
+    dt = oracle.cfl_dt(om, Us_host, G53, 0.3)
+    # (FP32: the CFL step of the rounded state)
+    assert abs(dt - dtb[2].item()) <= (1e-14 if precision == "fp64" else 1e-6) * dt
+    v1, got = ss.empty(), ss.empty()
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device=ss.device)
+    ss.stage1(Us, dt_dev, v1)
+    ss.stage2(Us, v1, dt_dev, got)
+    err = _field_error(got.double().cpu().numpy(), oracle.step(om, Us_host, dt, G53, True), 12,
+                       [0, 3, 6, 9], 1.0 / sizes[2][0])
+    print(f"  two-row mesh of instance 2 vs oracle, one step: {err:.3e}", flush=True)
+    assert err < (1e-13 if precision == "fp64" else 2e-5), err
+    del U, V1, out
+    b.close()
+    torch.cuda.empty_cache()
