@@ -256,3 +256,96 @@ def test_largest_batch(oracle, torch_cuda, precision):
     del U, V1, out
     b.close()
     torch.cuda.empty_cache()
+
+
+def _grid_facelist(nx, ny, h):
+    """A periodic nx x ny grid of square cells of side h written as a face-list
+    descriptor (cells x fastest; per cell its +x face, then its +y face).  With h
+    a power of two every coordinate and offset is exact, so every cell sees the
+    same geometry bit for bit."""
+    nc = nx * ny
+    i = np.tile(np.arange(nx), ny)
+    j = np.repeat(np.arange(ny), nx)
+    cen = np.stack([(i + 0.5) * h, (j + 0.5) * h], axis=1)
+    fc = np.empty((2 * nc, 2), np.int32)
+    fc[0::2, 0] = fc[1::2, 0] = np.arange(nc)
+    fc[0::2, 1] = j * nx + (i + 1) % nx
+    fc[1::2, 1] = ((j + 1) % ny) * nx + i
+    nrm = np.zeros((2 * nc, 2))
+    nrm[0::2, 0] = 1.0
+    nrm[1::2, 1] = 1.0
+    xf = np.repeat(cen, 2, axis=0)
+    xf[0::2, 0] += 0.5 * h
+    xf[1::2, 1] += 0.5 * h
+    sh = np.zeros((2 * nc, 2), np.int8)
+    sh[0::2, 0] = i + 1 == nx
+    sh[1::2, 1] = j + 1 == ny
+    m2 = h ** 4 / 12.0
+    return {"kind": "facelist", "box": np.array([nx * h, ny * h]),
+            "cell_volume": np.full(nc, h * h), "cell_centroid": cen,
+            "cell_moments": np.tile([m2, 0.0, m2], (nc, 1)),
+            "face_cells": fc, "face_area": np.full(2 * nc, h), "face_normal": nrm,
+            "face_centroid": xf, "face_shift": sh}
+
+
+@pytest.mark.timeout(300)
+def test_largest_facelist_mesh(oracle, torch_cuda):
+    """The face-list path (static Voronoi meshes) at its limit, 20 nfaces just below
+    2^31: a 7327^2 periodic grid written as a face list (53.7M cells, 107M faces),
+    FP64, with a state that varies along x only.  Cells in different positions of
+    their blocks may sum their faces in a different order, so rows are compared to
+    the two-row mesh's result to 1e-13 rather than bit for bit."""
+    torch = torch_cuda
+    from paper_1305_5536_amd.solver import Solver
+    nx = ny = 7327
+    h = 2.0 ** -13
+    nc = nx * ny
+    assert 20 * 2 * nc < LIMIT and 20 * 2 * (nc + ny) >= LIMIT
+    free, _ = torch.cuda.mem_get_info()
+    if free < 120e9:
+        pytest.skip(f"needs 120 GB of free device memory, {free / 1e9:.0f} GB free")
+    d_small = _grid_facelist(nx, 2, h)
+    U_small = W.project_cartesian(_fields(False), (nx, 2), (0.0, 0.0), (nx * h, 2 * h))
+    ss = Solver(d_small, gamma=G53)
+    Us = ss.to_device(U_small)
+    print(f"max-size face list {nx}x{ny}: {nc} cells, {2 * nc} faces; building", flush=True)
+    sb = Solver(_grid_facelist(nx, ny, h), gamma=G53)
+    print("  mesh built", flush=True)
+    Ub = Us.view(12, 2, nx)[:, :1, :].expand(12, ny, nx).contiguous().view(-1)
+    w = torch.full((12, 1, 1), h, dtype=torch.float64, device=Us.device)
+    w[0::3] = 1.0
+    scale = Us.view(12, -1)[0::3].abs().max().item()
+
+    def rows_err(big, small):
+        big = big.view(12, ny, nx)
+        ref = small.view(12, 2, nx)[:, :1, :]
+        return ((big - ref).abs() * w).max().item() / scale
+
+    dt_b, dt_s = sb.cfl_dt(Ub, 0.3).item(), ss.cfl_dt(Us, 0.3).item()
+    assert abs(dt_b - dt_s) <= 1e-14 * dt_s, (dt_b, dt_s)
+    dt = 0.5 * dt_s
+    a = ss.step(Us, dt)
+    out = sb.step(Ub, dt)
+    sb.check()
+    ss.check()
+    e_step = rows_err(out, a)
+    V1, v1 = sb.empty(), ss.empty()
+    sb.stage1(Ub, dt, V1)
+    ss.stage1(Us, dt, v1)
+    e_st1 = rows_err(V1, v1)
+    sb.stage2(Ub, V1, dt, out)
+    b = ss.empty()
+    ss.stage2(Us, v1, dt, b)
+    sb.check()
+    e_st2 = rows_err(out, b)
+    print(f"  rows vs two-row mesh: step {e_step:.2e}, stage 1 {e_st1:.2e}, stage 2 {e_st2:.2e}",
+          flush=True)
+    assert max(e_step, e_st1, e_st2) < 1e-13, (e_step, e_st1, e_st2)
+    del Ub, V1, out
+    sb.close()
+    torch.cuda.empty_cache()
+    om = oracle.Mesh.facelist(d_small)
+    err = _field_error(a.double().cpu().numpy(), oracle.step(om, U_small, dt, G53, True), 12,
+                       [0, 3, 6, 9], h)
+    print(f"  two-row face list vs oracle, one step: {err:.3e}", flush=True)
+    assert err < 1e-13, err
