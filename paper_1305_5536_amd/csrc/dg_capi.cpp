@@ -93,6 +93,12 @@ static int default_rows(int64_t ntiles_x, int64_t nrows) {
   return (int)rows;
 }
 
+// Rows per tile of every instance of a batch: 16 (DG_TILE_ROWS overrides).
+static int default_batch_rows() {
+  const char* env = std::getenv("DG_TILE_ROWS");
+  return env && std::atoi(env) > 0 ? std::atoi(env) : 16;
+}
+
 // Planes per workgroup of the 3D stage kernel (DG_TILE_ROWS overrides): one
 // workgroup per CU in FP64 and two in FP32 (set by the LDS), so P in [4, 64]
 // minimises rounds x (P + 1), a workgroup of P planes costing about P + 1
@@ -517,8 +523,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* d, const dg_config* cfg, dg_mesh_t*
       return einval("dg_mesh_create: batch too large for 32-bit indexing");
     }
     m->bt.ninst = d->ninst;
-    const char* env = std::getenv("DG_TILE_ROWS");
-    m->bt.rows = env && std::atoi(env) > 0 ? std::atoi(env) : 16;
+    m->bt.rows = default_batch_rows();
     const bool f64 = cfg->precision == DG_FP64;
     hipError_t e2 = hipMalloc(&m->bt.inst, batch_record_size(f64) * d->ninst);
     if (e2 == hipSuccess) e2 = hipMalloc(&m->bt.tile_inst, sizeof(int) * maxtiles);
@@ -1007,7 +1012,7 @@ dg_status dg_set_tiling(dg_mesh_t m, int rows) {
   if (m->kind == 2) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "dg_set_tiling: synchronise");
-    m->bt.rows = rows ? rows : 16;
+    m->bt.rows = rows ? rows : default_batch_rows();
     return batch_upload(m);
   }
   if (m->kind != 0) return DG_OK;
