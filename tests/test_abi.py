@@ -102,6 +102,52 @@ def test_oversized_meshes_rejected_before_any_device_call():
         capi.DG_EINVAL
 
 
+def test_empty_meshes_rejected_before_any_device_call():
+    """Empty inputs of every mesh kind are refused with DG_EINVAL during
+    validation (no allocation, no launch): a Cartesian axis of zero cells, a
+    face list without cells or faces, a batch without instances or with an
+    empty instance, a moving mesh without generators."""
+    import numpy as np
+
+    from paper_1305_5536_amd import capi
+    lib = capi.lib()
+    out = ctypes.c_void_p()
+    euler = capi.dg_config(capi.DG_EULER, capi.DG_FP64, capi.DG_FLUX_HLL, 1, 1.4)
+    mhd = capi.dg_config(capi.DG_MHD, capi.DG_FP64, capi.DG_FLUX_HLLD, 1, 5.0 / 3.0)
+
+    def refused(d, cfg):
+        out.value = None
+        st = lib.dg_mesh_create(ctypes.byref(d), ctypes.byref(cfg), ctypes.byref(out))
+        return st == capi.DG_EINVAL and not out.value
+
+    for dim, cfg in ((2, euler), (2, mhd), (3, mhd)):
+        for empty_axis in range(dim):
+            d = capi.dg_mesh_desc()
+            d.dim, d.kind = dim, 0
+            for k in range(dim):
+                d.n[k], d.lo[k], d.hi[k] = (0 if k == empty_axis else 8), 0.0, 1.0
+            assert refused(d, cfg), (dim, empty_axis)
+            assert b"cell count" in lib.dg_last_error()
+    for ncells, nfaces in ((0, 0), (0, 4), (4, 0)):
+        d = capi.dg_mesh_desc()
+        d.dim, d.kind = 2, 1
+        d.ncells, d.nfaces = ncells, nfaces
+        d.box[0] = d.box[1] = 1.0
+        assert refused(d, euler), (ncells, nfaces)
+    n = np.array([16, 8, 0, 4], np.int32)
+    box = np.tile([0.0, 0.0, 1.0, 1.0], 2)
+    for ninst, sizes in ((0, n), (2, n)):
+        d = capi.dg_mesh_desc()
+        d.dim, d.kind, d.ninst = 2, 2, ninst
+        d.inst_n = sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.inst_box = box.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        assert refused(d, euler), ninst
+    d = capi.dg_mesh_desc()
+    d.dim, d.kind = 2, 3
+    d.box[0] = d.box[1] = 1.0
+    assert refused(d, euler)
+
+
 def test_facelist_cell_without_faces_rejected():
     """A face list in which a cell has no faces (no tessellation has one) is
     refused with DG_EINVAL during validation, before any device call: the
