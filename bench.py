@@ -1155,7 +1155,8 @@ def copy_calibration():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark measures one GPU (the library has no "
+                                   "multi-GPU path); --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     if a.copy_calibration:
